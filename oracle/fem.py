@@ -1,0 +1,179 @@
+"""Galerkin residual, linearised operator and energy, from dense element tables (no sum factorisation).
+
+Definitions (Section 2, material configuration, no body force or traction in the operator
+configurations):
+
+* residual     r_(c,a) = sum_q w_q detJ0 sum_J P_cJ(F_q) (Grad phi_a)_J                (Eq. of r_Omega0)
+* linearised   (K du)_(c,a) = sum_q w_q detJ0 sum_J,k,L (Grad phi_a)_J A_cJkL (Grad du)_kL
+               with A = dP/dF, i.e. the directional derivative of the residual (Problem 2.2)
+* energy       Pi(u) = sum_q w_q detJ0 Psi(C_q)  (whose gradient is the residual)
+
+Geometry: trilinear map of each hexahedron from its 8 vertices, J0 = dX/dxi at every Gauss point,
+Grad phi = J0^-T grad_xi phi, weights w_q det J0 (Gauss weights are tensor products on [0,1]^3).
+
+Constraints (the test space H^1_0 with homogeneous data, Problems 2.1-2.2; the operator reading
+is identity rows and columns on constrained DoFs): r~ = P_f r,  K~ du = P_f K P_f du + P_c du.
+
+All functions accept complex displacement vectors so that tests can take complex-step derivatives.
+Work proceeds over chunks of cells; arrays are the plain [cells, q-points, ...] tensors.
+
+Test infrastructure only. Pinned in tests/test_oracle_fem.py (patch test, rigid rotation,
+translation invariance, residual = complex-step gradient of the energy, tangent = complex-step
+derivative of the residual, symmetry, linear elasticity at u = 0 against an independent
+Voigt-notation stiffness).
+"""
+import numpy as np
+
+from . import basis, material
+
+
+class ElementTables:
+    """Dense 3D tables of the Q_p basis at the (p+1)^3 Gauss points.
+
+    N[q, a] = l_i(x_qx) l_j(x_qy) l_k(x_qz),  dN[q, a, d] its reference derivatives,
+    W[q] = product Gauss weight;  q = qx + n (qy + n qz),  a = i + n (j + n k).
+    TN[q, v, d]: reference derivatives of the 8 trilinear vertex functions (geometry).
+    """
+
+    def __init__(self, p):
+        n = p + 1
+        self.p, self.n = p, n
+        xg = basis.gll_points(p)
+        xq, wq = basis.gauss_rule(n)
+        L = basis.lagrange_values(xg, xq)
+        dL = basis.lagrange_derivatives(xg, xq)
+        n3 = n ** 3
+
+        def t3(A, B, C):
+            return np.einsum("xi,yj,zk->zyxkji", A, B, C).reshape(n3, n3)
+
+        self.N = t3(L, L, L)
+        self.dN = np.stack([t3(dL, L, L), t3(L, dL, L), t3(L, L, dL)], axis=-1)
+        self.W = np.einsum("x,y,z->zyx", wq, wq, wq).reshape(n3)
+        self.xq = xq
+        # trilinear vertex functions phi_0(s) = 1 - s, phi_1(s) = s
+        qz, qy, qx = np.meshgrid(xq, xq, xq, indexing="ij")
+        s, t, r = qx.ravel(), qy.ravel(), qz.ravel()
+        TN = np.zeros((n3, 8, 3))
+        for c in range(2):
+            for b in range(2):
+                for a in range(2):
+                    fa, fb, fc = (s if a else 1 - s), (t if b else 1 - t), (r if c else 1 - r)
+                    da, db, dc = (1.0 if a else -1.0), (1.0 if b else -1.0), (1.0 if c else -1.0)
+                    v = a + 2 * b + 4 * c
+                    TN[:, v, 0] = da * fb * fc
+                    TN[:, v, 1] = fa * db * fc
+                    TN[:, v, 2] = fa * fb * dc
+        self.TN = TN
+
+
+class Problem:
+    """A mesh, a material and the element tables; the operator evaluations act on (3, n_nodes)."""
+
+    def __init__(self, mesh, mat, chunk=256):
+        self.mesh = mesh
+        self.mat = mat
+        self.tab = ElementTables(mesh.p)
+        self.chunk = chunk
+
+    # -- geometry -----------------------------------------------------------------------------
+    def geometry(self, cells):
+        """(invJ0 [E, Q, 3(d), 3(J)], wdet [E, Q]) for the given cells; asserts det J0 > 0."""
+        X8 = self.mesh.cell_vertex_xyz[cells]                       # [E, 8, 3]
+        J0 = np.einsum("evc,qvd->eqcd", X8, self.tab.TN)            # dX_c / dxi_d
+        det = np.linalg.det(J0)
+        if np.any(det <= 0.0):
+            raise ValueError("inverted or degenerate cell: det J0 <= 0")
+        return np.linalg.inv(J0), det * self.tab.W[None, :]
+
+    def physical_gradients(self, cells):
+        """Grad phi_a at every q-point: [E, Q, n^3, 3] = sum_d dN[q,a,d] invJ0[d,J]."""
+        invJ0, wdet = self.geometry(cells)
+        return np.einsum("qad,eqdJ->eqaJ", self.tab.dN, invJ0), wdet
+
+    def _cell_values(self, vec, cells):
+        """Element-local values [E, 3, n^3] of a (3, n_nodes) vector."""
+        return np.transpose(vec[:, self.mesh.cell_nodes[cells]], (1, 0, 2))
+
+    def _chunks(self, cells=None):
+        cells = np.arange(self.mesh.n_cells) if cells is None else np.asarray(cells)
+        for s in range(0, len(cells), self.chunk):
+            yield cells[s:s + self.chunk]
+
+    def _scatter(self, out, cells, contrib):
+        nodes = self.mesh.cell_nodes[cells]
+        for c in range(3):
+            np.add.at(out[c], nodes.ravel(), contrib[:, c, :].ravel())
+
+    def deformation_gradient(self, u, cells):
+        Gphi, wdet = self.physical_gradients(cells)
+        ue = self._cell_values(u, cells)
+        H = np.einsum("eca,eqaJ->eqcJ", ue, Gphi)
+        F = np.eye(3) + H
+        if np.any(np.real(np.linalg.det(F)) <= 0.0):
+            raise ValueError("deformation inverts a q-point: J <= 0")
+        return F, Gphi, wdet
+
+    # -- operator evaluations -----------------------------------------------------------------
+    def energy(self, u):
+        total = 0.0
+        for cells in self._chunks():
+            F, _, wdet = self.deformation_gradient(u, cells)
+            C = np.einsum("...ki,...kj->...ij", F, F)
+            total = total + np.sum(wdet * material.psi(C, self.mat))
+        return total
+
+    def residual(self, u, cells=None, constrain=True):
+        """r~(u) with constrained rows set to zero; ``cells`` restricts the sum (for sampling)."""
+        u = np.asarray(u)
+        out = np.zeros((3, self.mesh.n_nodes), dtype=np.result_type(u.dtype, np.float64))
+        for ch in self._chunks(cells):
+            F, Gphi, wdet = self.deformation_gradient(u, ch)
+            P = material.first_pk(F, self.mat)
+            contrib = np.einsum("eq,eqcJ,eqaJ->eca", wdet, P, Gphi)
+            self._scatter(out, ch, contrib)
+        if constrain:
+            out[:, self.mesh.constrained] = 0.0
+        return out
+
+    def apply_tangent(self, u, du, cells=None, constrain=True):
+        """K~(u) du = P_f K P_f du + P_c du, cell by cell (no global matrix)."""
+        u = np.asarray(u)
+        du = np.array(du, dtype=np.result_type(du, np.float64), copy=True)
+        mask = self.mesh.constrained if constrain else np.zeros(self.mesh.n_nodes, dtype=bool)
+        du_f = du.copy()
+        du_f[:, mask] = 0.0
+        out = np.zeros((3, self.mesh.n_nodes), dtype=np.result_type(u.dtype, du.dtype, np.float64))
+        for ch in self._chunks(cells):
+            F, Gphi, wdet = self.deformation_gradient(u, ch)
+            A = material.first_elasticity(F, self.mat)
+            G = np.einsum("eka,eqaL->eqkL", self._cell_values(du_f, ch), Gphi)
+            Pdot = np.einsum("eqiJkL,eqkL->eqiJ", A, G)
+            contrib = np.einsum("eq,eqcJ,eqaJ->eca", wdet, Pdot, Gphi)
+            self._scatter(out, ch, contrib)
+        out[:, mask] = du[:, mask]
+        return out
+
+    def cells_touching(self, nodes):
+        """Cells whose node lists contain any of ``nodes`` (for sampled rows)."""
+        hit = np.isin(self.mesh.cell_nodes, np.asarray(nodes)).any(axis=1)
+        return np.nonzero(hit)[0]
+
+    def tangent_matrix(self, u, constrain=True):
+        """Assembled K~ (dense, DoF order c * n_nodes + node); for small meshes only."""
+        nn = self.mesh.n_nodes
+        K = np.zeros((3 * nn, 3 * nn))
+        for ch in self._chunks():
+            F, Gphi, wdet = self.deformation_gradient(u, ch)
+            A = material.first_elasticity(F, self.mat)
+            Ke = np.einsum("eq,eqaJ,eqiJkL,eqbL->eiakb", wdet, Gphi, A, Gphi)
+            nodes = self.mesh.cell_nodes[ch]
+            for e in range(len(ch)):
+                dof = (np.arange(3)[:, None] * nn + nodes[e][None, :]).ravel()
+                K[np.ix_(dof, dof)] += Ke[e].reshape(3 * nodes.shape[1], 3 * nodes.shape[1])
+        if constrain:
+            cdofs = np.nonzero(np.tile(self.mesh.constrained, 3))[0]
+            K[cdofs, :] = 0.0
+            K[:, cdofs] = 0.0
+            K[cdofs, cdofs] = 1.0
+        return K
