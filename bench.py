@@ -1,0 +1,277 @@
+#!/usr/bin/env python3
+"""Benchmark of the matrix-free tangent apply (one JSON line on stdout).
+
+Workload: the operator-apply sweep of the perturbed cube: 32^3 hexahedra on [0,1]^3 with interior
+vertices moved by U(-0.2h, 0.2h) (seed 2), Q_p with p+1 Gauss points per direction, cNH with
+mu = 1, lambda = 100, u a smooth field with largest principal stretch 1.3, du ~ N(0,1) (seed 3),
+Dirichlet on x = 0, FP64. A step is one hx_apply_tangent on the headline configuration (default
+p = 4 in the fastest storage mode measured in this run); the linearisation update runs once
+before timing, as in the paper's protocol (Section 7.2). Inputs are resident in HBM when the
+timed region starts.
+
+Also reported: GDoF/s of every (p, storage mode) pair for p = 2, 3, 4, 6, the update and
+residual times, FP32 / BF16 / FP16 applies of the anisotropic 64x32x32 Q3 workload with their
+errors against the FP64 apply, the live roofline of the headline kernel and the FP64 oracle
+timed on a bounded sample of cells on the host (cpu_baseline).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+
+# Algorithmic work per q-point (FP64 flops, cNH) of each storage mode's q-point routine, and
+# stored words per q-point; sum factorisation adds 12 n^4 fused multiply-adds per field and cell
+# (6 sweeps forward, 6 backward), 6 n^4 for the linearisation point in recompute mode.
+QPOINT_FLOPS = {"tangent": 162, "finv_j": 400, "none": 597}
+QPOINT_WORDS = {"tangent": 45, "finv_j": 10, "none": 0}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--p", type=int, default=4)
+    ap.add_argument("--mode", default="auto", choices=["auto", "none", "finv_j", "tangent"])
+    ap.add_argument("--degrees", default="2,3,4,6")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cells", type=int, default=32)
+    return ap.parse_args()
+
+
+def algorithmic(p, mode, n_cells, n_dofs):
+    n = p + 1
+    Q = n ** 3
+    words = QPOINT_WORDS[mode]
+    vec_words = 2 + (1 if mode == "none" else 0)
+    bytes_ = 8.0 * (vec_words * n_dofs + words * Q * n_cells)
+    fields = 3 + (3 if mode == "none" else 0)
+    sumfac_fma = (12 * n ** 4) * 3 + (6 * n ** 4 * 3 if mode == "none" else 0)
+    flops = n_cells * (2.0 * sumfac_fma + QPOINT_FLOPS[mode] * Q)
+    del fields
+    return bytes_, flops
+
+
+class Timer:
+    """HIP events on the stream the kernels are launched on."""
+
+    def __init__(self, torch, stream):
+        self.torch, self.stream = torch, stream
+
+    def time(self, fn, reps):
+        t = self.torch
+        e0, e1 = t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)
+        t.cuda.synchronize()
+        e0.record(self.stream)
+        for _ in range(reps):
+            fn()
+        e1.record(self.stream)
+        t.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+
+def cube_operator(hx, workloads, p, cells):
+    V = workloads.box_vertices(cells, cells, cells, perturb=0.2, seed=2)
+    op = hx.Operator(cells, cells, cells, V, p, law="cnh", mu=1.0, lam=100.0, dirichlet_faces=(0,))
+    return op, V
+
+
+def cpu_baseline(p, cells, budget_s=15.0):
+    """The FP64 oracle's element-by-element tangent apply on a bounded block of cells."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+    import workloads
+    from oracle import fem, material, mesh
+    V = workloads.box_vertices(cells, cells, cells, perturb=0.2, seed=2)
+    m = mesh.BoxMesh(cells, cells, cells, V, p, dirichlet_faces=(0,))
+    pb = fem.Problem(m, material.Material("cnh", mu=1.0, lam=100.0), chunk=64)
+    u, du = workloads.sweep_fields(m.node_coords, m.constrained)
+    ctx = threadpool_limits(1) if threadpool_limits else None
+    done, t_total, block = 0, 0.0, 64
+    start = 0
+    while t_total < budget_s and start < m.n_cells:
+        cells_blk = np.arange(start, min(start + block, m.n_cells))
+        t0 = time.perf_counter()
+        pb.apply_tangent(u, du, cells=cells_blk)
+        t_total += time.perf_counter() - t0
+        done += len(cells_blk)
+        start += block
+    if ctx is not None:
+        ctx.__exit__(None, None, None)
+    dofs_per_cell = 3 * m.n_nodes / m.n_cells
+    return {"value": done * dofs_per_cell / t_total / 1e9, "unit": "GDoF/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} of {m.n_cells} cells of the {cells}^3 Q{p} cube (cNH), "
+                      f"{t_total:.1f} s single-threaded; DoF/s scaled by 3*n_nodes/n_cells"}
+
+
+def measured_traffic(p, mode):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they match this source."""
+    path = os.path.join(ROOT, "profiles", f"apply_{mode}_p{p}_cube32_pmc.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_2408_12479_amd", "csrc", "hx_kernels.hpp")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if rec.get("kernel_src_sha256") != sha:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding is a design note only)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2408_12479_amd as hx
+    import workloads
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    timer = Timer(torch, stream)
+    degrees = [int(x) for x in args.degrees.split(",")]
+    if args.p not in degrees:
+        degrees.append(args.p)
+    modes = ["none", "finv_j", "tangent"]
+    sweep = {}
+    extra = {}
+    head = None
+    for p in sorted(degrees):
+        if args.no_sweep and p != args.p:
+            continue
+        op, _ = cube_operator(hx, workloads, p, args.cells)
+        coords = op.node_coords()
+        mask = op.constrained_mask()
+        u, du = workloads.sweep_fields(coords, mask)
+        ud = torch.tensor(u.reshape(-1), dtype=torch.float64, device=dev)
+        dud = torch.tensor(du.reshape(-1), dtype=torch.float64, device=dev)
+        dst = torch.empty_like(dud)
+        r = torch.empty_like(ud)
+        t_res = timer.time(lambda: op.residual(ud, r), 5)
+        res = {"dofs": op.num_dofs, "cells": op.num_cells, "residual_ms": t_res}
+        for mode in modes:
+            t0 = time.perf_counter()
+            op.update_linearization(ud, mode=mode, precision="fp64")
+            t_upd = (time.perf_counter() - t0) * 1e3
+            for _ in range(args.warmup):
+                op.apply_tangent(dud, dst)
+            reps = args.steps if p == args.p else max(5, args.steps // 4)
+            ms = timer.time(lambda: op.apply_tangent(dud, dst), reps)
+            b, f = algorithmic(p, mode, op.num_cells, op.num_dofs)
+            res[mode] = {"apply_ms": ms, "gdofs": op.num_dofs / ms / 1e6, "update_ms": t_upd,
+                         "data_bytes": op.linearization_bytes("fp64"),
+                         "hbm_frac": b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "fp64_frac": f / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}
+        sweep[f"p{p}"] = res
+        print(f"[bench] p={p}: " + ", ".join(f"{m_} {res[m_]['gdofs']:.2f} GDoF/s" for m_ in modes),
+              file=sys.stderr, flush=True)
+        if p == args.p:
+            mode = args.mode if args.mode != "auto" else max(modes, key=lambda m_: res[m_]["gdofs"])
+            op.update_linearization(ud, mode=mode, precision="fp64")
+            for _ in range(args.warmup):
+                op.apply_tangent(dud, dst)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                op.apply_tangent(dud, dst)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            b, f = algorithmic(p, mode, op.num_cells, op.num_dofs)
+            head = dict(p=p, mode=mode, ms=ms, dofs=op.num_dofs, cells=op.num_cells, bytes=b, flops=f)
+        op.close()
+        del ud, dud, dst, r
+        torch.cuda.empty_cache()
+
+    if not args.no_fp32:
+        extra["fiber_box_q3"] = fp32_study(hx, workloads, torch, dev, timer, args)
+
+    # roofline of the headline kernel
+    ms = head["ms"]
+    gbs = head["bytes"] / (ms * 1e-3) / 1e9
+    tfl = head["flops"] / (ms * 1e-3) / 1e12
+    if gbs / HBM_PEAK_GBS >= tfl / FP64_PEAK_TFLOPS:
+        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+        tr = measured_traffic(head["p"], head["mode"])
+        roof["traffic"] = tr
+    else:
+        roof = {"bound": "alu", "achieved": tfl, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": tfl / FP64_PEAK_TFLOPS, "traffic": measured_traffic(head["p"], head["mode"])}
+
+    out = {
+        "metric": "GDoF/s of tangent apply (Q2-Q6), FP64",
+        "value": head["dofs"] / ms / 1e6,
+        "unit": "GDoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"perturbed cube {args.cells}^3 cells, Q{head['p']}, cNH mu=1 lambda=100, "
+                               f"stretch 1.3, storage mode {head['mode']}",
+                   "dofs": head["dofs"], "cells": head["cells"], "p": head["p"], "storage": head["mode"]},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(head["p"], args.cells)
+    out["sweep"] = sweep
+    out["extra"] = extra
+    print(json.dumps(out), flush=True)
+
+
+def fp32_study(hx, workloads, torch, dev, timer, args):
+    """FP32 applies (FP32 / BF16 / FP16 stored data) vs the FP64 apply on the 64x32x32 Q3 fibre box."""
+    import math
+    V = workloads.box_vertices(64, 32, 32, lengths=(2.0, 1.0, 1.0), perturb=0.0)
+    H4, H6, M4, M6 = hx.fiber_structure(3.62, 34.3, math.radians(45.0))
+    op = hx.Operator(64, 32, 32, V, 3, law="fiber", mu=2.0, kappa=1e3, k1=1.0, k2=10.0,
+                     H4=H4, H6=H6, M4=M4, M6=M6, dirichlet_faces=())
+    u, du = workloads.fiber_fields(op.node_coords())
+    ud = torch.tensor(u.reshape(-1), dtype=torch.float64, device=dev)
+    dud = torch.tensor(du.reshape(-1), dtype=torch.float64, device=dev)
+    du32 = dud.float()
+    ref = {}
+    out = {"dofs": op.num_dofs}
+    for mode in ["none", "finv_j", "tangent"]:
+        op.update_linearization(ud, mode=mode, precision="fp64")
+        y = op.apply_tangent(dud)
+        ms = timer.time(lambda: op.apply_tangent(dud, y), 10)
+        ref[mode] = y.clone()
+        out[f"fp64_{mode}"] = {"gdofs": op.num_dofs / ms / 1e6}
+    yref = ref["tangent"]
+    nrm = torch.linalg.norm(yref).item()
+    for mode, precs in [("none", ["fp32"]), ("finv_j", ["fp32"]), ("tangent", ["fp32", "fp32_bf16", "fp32_fp16"])]:
+        for prec in precs:
+            op.update_linearization(ud, mode=mode, precision=prec)
+            y = op.apply_tangent(du32, precision=prec)
+            ms = timer.time(lambda: op.apply_tangent(du32, y, precision=prec), 10)
+            err = torch.linalg.norm(y.double() - yref).item() / nrm
+            out[f"{prec}_{mode}"] = {"gdofs": op.num_dofs / ms / 1e6, "rel_err_vs_fp64": err}
+    op.close()
+    return out
+
+
+if __name__ == "__main__":
+    main()

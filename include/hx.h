@@ -1,0 +1,180 @@
+/*
+ * hx.h - C ABI of libhx.so: matrix-free residual and linearised operator of finite-strain
+ * hyperelasticity on hexahedral Q_p elements, evaluated by sum factorisation on AMD MI355X
+ * (gfx950).
+ *
+ * The operation is the one of the paper (Schussnig, Fehn, Munch, Kronbichler, "Matrix-free
+ * higher-order finite element methods for hyperelasticity"):
+ *   - residual   r(v, u) = (Grad v, P)_Omega0 with P = F S          (Section 2, material residual)
+ *   - linearised D_u r(v, du)|_u = (Grad v, Grad du S + F D_u S)    (Section 2, directional
+ *                derivative of the residual; Problem 2.2)
+ *   - laws       compressible / nearly incompressible neo-Hookean and the dispersed two-fibre
+ *                model (Section 3), in the stable forms of Section 4
+ *   - storage    quadrature-point data recomputed on the fly or stored once per Newton step
+ *                and reused by every operator application (Section 5, Algorithm 1)
+ *
+ * No C++ exception crosses this boundary. Every call returns hx_status; hx_last_error() gives a
+ * message for the last failing call on a context. No torch or HIP type appears in a signature:
+ * device buffers are plain pointers, streams are passed as void* (a hipStream_t, NULL = the
+ * default stream).
+ *
+ * Conventions shared by all calls
+ * -------------------------------
+ * Mesh: a structured nx x ny x nz lattice of hexahedra with given vertex positions (interior
+ * vertices may be perturbed; each lattice direction may be periodic). Cells are numbered
+ * e = ex + nx*(ey + ny*ez). The geometry of a cell is the trilinear map of its 8 vertices.
+ *
+ * Nodes: the lattice of Gauss-Lobatto points of degree p, N_d = n_d*p (+1 if direction d is not
+ * periodic) points per direction, node = I + N_x*(J + N_y*K). Quadrature: (p+1)^3 Gauss points.
+ *
+ * Vectors: device arrays in structure-of-arrays layout [3][n_nodes] (DoF index c*n_nodes+node),
+ * contiguous, owned by the caller. FP64 (double) unless a call says otherwise.
+ *
+ * Dirichlet: nodes on the faces selected by hx_mesh.dirichlet_faces carry homogeneous data
+ * (the test space H^1_0 of Problems 2.1/2.2). hx_residual writes 0 on constrained rows;
+ * hx_apply_tangent treats du as 0 on constrained DoFs for the free rows and writes dst = du on
+ * constrained rows (operator P_f K P_f + P_c, symmetric).
+ *
+ * Asynchrony: operator calls enqueue kernels on the given stream and return without waiting,
+ * except hx_update_linearization, which waits on its stream to read the device status flag.
+ * Calls on one context must not overlap in time on different streams.
+ */
+#ifndef HX_H
+#define HX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hx_ctx_s* hx_ctx;
+
+typedef enum {
+  HX_OK = 0,
+  HX_E_ARG = 1,           /* invalid argument (null pointer, size, unknown enum value) */
+  HX_E_HIP = 2,           /* a HIP runtime call failed */
+  HX_E_NOMEM = 3,         /* device allocation failed */
+  HX_E_STATE = 4,         /* call out of order (e.g. apply before any linearisation update) */
+  HX_E_INVERTED = 5,      /* det J0 <= 0 in a cell (setup) or J <= 0 at a q-point (update) */
+  HX_E_NONFINITE = 6,     /* NaN or Inf in the linearisation data */
+  HX_E_NOT_CONVERGED = 7, /* iterative solve did not reach its tolerance */
+  HX_E_UNSUPPORTED = 8    /* combination of degree / law / precision / mode not built */
+} hx_status;
+
+typedef enum { HX_LAW_CNH = 0, HX_LAW_INH = 1, HX_LAW_FIBER = 2 } hx_law;
+
+/* What hx_update_linearization keeps per quadrature point (Section 5, storage strategies).
+ *   NONE     nothing: every apply re-interpolates u_k and recomputes kinematics and the law
+ *            (the "on-the-fly" variant); the library keeps a copy of u_k.
+ *   FINV_J   F^-1 (9 words) and J - 1 (1 word); the apply recomputes the law scalars and the
+ *            trilinear geometry.
+ *   TANGENT  the symmetric 9x9 tangent in reference coordinates, 45 words:
+ *            D_(i a)(k b) = w_q detJ0 sum_{J,L} J0^-1_aJ A_iJkL J0^-1_bL, A = dP/dF,
+ *            geometry and weight folded in; the apply is a 9x9 product per q-point. */
+typedef enum { HX_STORE_NONE = 0, HX_STORE_FINV_J = 1, HX_STORE_TANGENT = 2 } hx_storage;
+
+/* Arithmetic of hx_apply_tangent and the type of its stored data.
+ *   FP64             double vectors, double compute, double data
+ *   FP32             float vectors, float compute, float data
+ *   FP32_BF16DATA    float vectors and compute, bfloat16 data (TANGENT only)
+ *   FP32_FP16DATA    float vectors and compute, binary16 data scaled per cell by a power of
+ *                    two (TANGENT only)
+ * The linearisation data itself is always computed in FP64 and rounded once when stored. */
+typedef enum {
+  HX_FP64 = 0,
+  HX_FP32 = 1,
+  HX_FP32_BF16DATA = 2,
+  HX_FP32_FP16DATA = 3
+} hx_precision;
+
+typedef struct {
+  int32_t nx, ny, nz;       /* cells per lattice direction, each >= 1 */
+  int32_t periodic;         /* bit d (d = 0,1,2 for x,y,z) set: direction d is periodic */
+  const double* vertices;   /* HOST array [V_z][V_y][V_x][3], V_d = n_d (+1 if not periodic),
+                               x fastest; copied by hx_setup */
+  uint32_t dirichlet_faces; /* bit f set: face f is constrained, f = 0..5 = -x,+x,-y,+y,-z,+z;
+                               bits of periodic directions are ignored */
+} hx_mesh;
+
+/* Material parameters (Section 3). cNH uses mu, lambda with Psi = mu/2 (I1 - 3 - 2 ln J) +
+ * lambda ln^2 J. iNH uses mu, kappa with Psi = mu/2 (J^-2/3 I1 - 3) + kappa/4 (J^2 - 1 - 2 ln J).
+ * FIBER adds k1, k2 and, for the two families i = 4, 6, the symmetric structure tensor H_i
+ * (row-major 3x3) and the mean fibre direction M_i used in the tension switch I*_i > 1
+ * (hx_fiber_structure computes both from dispersion parameters). */
+typedef struct {
+  hx_law law;
+  double mu, lambda, kappa, k1, k2;
+  double H4[9], H6[9];
+  double M4[3], M6[3];
+} hx_material;
+
+typedef struct {
+  int32_t jpow_newton_iters; /* FP32 arithmetic: J^-2/3 by this many Newton steps from x0 = 1
+                                (Algorithm 2, Section 4), accurate only near J = 1;
+                                0 = cube root (the default, also with opt == NULL). FP64
+                                always uses the cube root. */
+  int32_t reserved[7];       /* must be zero */
+} hx_options;
+
+/* Builds a context: copies the mesh to the device, sets up the 1D basis tables for degree p,
+ * checks det J0 > 0 at every Gauss point of every cell (HX_E_INVERTED otherwise).
+ * p in [1, 6]. opt may be NULL (defaults). On success *out owns device memory until
+ * hx_destroy. The current HIP device at the time of the call is the context's device. */
+hx_status hx_setup(const hx_mesh* mesh, int32_t p, const hx_material* mat,
+                   const hx_options* opt, hx_ctx* out);
+
+/* Frees every device and host resource of the context. NULL is accepted. */
+hx_status hx_destroy(hx_ctx ctx);
+
+/* 3 * n_nodes, or -1 for a NULL context. */
+int64_t hx_num_dofs(hx_ctx ctx);
+int64_t hx_num_nodes(hx_ctx ctx);
+int64_t hx_num_cells(hx_ctx ctx);
+
+/* Writes the node positions, HOST array [n_nodes][3]: the trilinear map of the cell with lattice
+ * index min(I / p, n_d - 1) per direction, at the Gauss-Lobatto point of the local index. */
+hx_status hx_node_coords(hx_ctx ctx, double* host_xyz);
+
+/* Writes the constraint mask, HOST array [n_nodes] of 0/1. */
+hx_status hx_constrained_mask(hx_ctx ctx, uint8_t* host_mask);
+
+/* r = r~(u): material residual (Section 2) of the displacement u, FP64, device arrays
+ * [3][n_nodes]; constrained rows are 0. u and r must not alias. */
+hx_status hx_residual(hx_ctx ctx, const double* u, double* r, void* stream);
+
+/* Linearisation update at u (Algorithm 1, "update quadrature point data"): stores the data of
+ * the requested mode in the requested storage precision. The FP64 class (prec == HX_FP64) and
+ * the FP32 class (the three FP32 values) are separate slots, so one context can hold an FP64
+ * operator and an FP32 operator at once. Waits for the stream; returns HX_E_INVERTED if J <= 0
+ * at some q-point and HX_E_NONFINITE on NaN/Inf. The data is kept even on those errors. */
+hx_status hx_update_linearization(hx_ctx ctx, const double* u, hx_storage mode,
+                                  hx_precision prec, void* stream);
+
+/* dst = K~(u_k) du with the linearisation of the slot selected by prec (HX_FP64: double du and
+ * dst; any FP32 value: float du and dst, data as last stored in the FP32 slot). du and dst are
+ * device arrays [3][n_nodes] and must not alias. HX_E_STATE if that slot was never updated. */
+hx_status hx_apply_tangent(hx_ctx ctx, const void* du, void* dst, hx_precision prec,
+                           void* stream);
+
+/* Bytes of per-q-point data held by a slot (0 before its first update). */
+int64_t hx_linearization_bytes(hx_ctx ctx, hx_precision prec);
+
+/* Host helper (Section 3): structure tensors and mean directions of the two fibre families from
+ * the dispersion parameters (a, b), the mean in-plane angle phi (radians) and the local frame
+ * E = rows E1 (circumferential), E2 (longitudinal), E3 (radial), row-major 3x3.
+ * H33 = 1/(4b) - exp(-2b) / (sqrt(2 pi b) erf(sqrt(2b))), H11/H22 = (1 - H33)/2 (1 +- I1(a)/I0(a));
+ * family 4: M1 = cos(phi) E1 + sin(phi) E2, M2 = -sin(phi) E1 + cos(phi) E2, M3 = E3;
+ * family 6: the same with -phi; H_i = sum_k H_kk M_k (x) M_k. Outputs are host arrays. */
+hx_status hx_fiber_structure(double a, double b, double phi, const double* E,
+                             double* H4, double* H6, double* M4, double* M6);
+
+/* Message for the last error on ctx (or of the last failed hx_setup when ctx is NULL). */
+const char* hx_last_error(hx_ctx ctx);
+const char* hx_status_string(hx_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HX_H */

@@ -1,0 +1,184 @@
+"""Python binding of libhx.so (see include/hx.h): argument marshalling only.
+
+Every operator evaluation runs in the HIP kernels of the library; torch provides device memory and
+streams. Importing the package loads the in-tree ``libhx.so`` and fails loudly if it is missing
+(build it with ``python -m paper_2408_12479_amd.build`` or ``__graft_entry__.build()``).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhx.so")
+
+# enums of hx.h
+HX_OK = 0
+STATUS = {0: "HX_OK", 1: "HX_E_ARG", 2: "HX_E_HIP", 3: "HX_E_NOMEM", 4: "HX_E_STATE", 5: "HX_E_INVERTED",
+          6: "HX_E_NONFINITE", 7: "HX_E_NOT_CONVERGED", 8: "HX_E_UNSUPPORTED"}
+LAWS = {"cnh": 0, "inh": 1, "fiber": 2}
+MODES = {"none": 0, "finv_j": 1, "tangent": 2}
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_bf16": 2, "fp32_fp16": 3}
+
+
+class HxError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class _Mesh(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("periodic", ctypes.c_int32), ("vertices", ctypes.POINTER(ctypes.c_double)),
+                ("dirichlet_faces", ctypes.c_uint32)]
+
+
+class _Material(ctypes.Structure):
+    _fields_ = [("law", ctypes.c_int), ("mu", ctypes.c_double), ("lam", ctypes.c_double),
+                ("kappa", ctypes.c_double), ("k1", ctypes.c_double), ("k2", ctypes.c_double),
+                ("H4", ctypes.c_double * 9), ("H6", ctypes.c_double * 9),
+                ("M4", ctypes.c_double * 3), ("M6", ctypes.c_double * 3)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("jpow_newton_iters", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2408_12479_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64 = ctypes.c_void_p, ctypes.c_int64
+    sig = {
+        "hx_setup": (ctypes.c_int, [ctypes.POINTER(_Mesh), ctypes.c_int32, ctypes.POINTER(_Material),
+                                    ctypes.POINTER(_Options), ctypes.POINTER(vp)]),
+        "hx_destroy": (ctypes.c_int, [vp]),
+        "hx_num_dofs": (i64, [vp]),
+        "hx_num_nodes": (i64, [vp]),
+        "hx_num_cells": (i64, [vp]),
+        "hx_node_coords": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double)]),
+        "hx_constrained_mask": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_uint8)]),
+        "hx_residual": (ctypes.c_int, [vp, vp, vp, vp]),
+        "hx_update_linearization": (ctypes.c_int, [vp, vp, ctypes.c_int, ctypes.c_int, vp]),
+        "hx_apply_tangent": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, vp]),
+        "hx_linearization_bytes": (i64, [vp, ctypes.c_int]),
+        "hx_fiber_structure": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double]
+                               + [ctypes.POINTER(ctypes.c_double)] * 5),
+        "hx_last_error": (ctypes.c_char_p, [vp]),
+        "hx_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(status, ctx=None):
+    if status != HX_OK:
+        raise HxError(status, lib.hx_last_error(ctx).decode())
+
+
+def _dptr(arr):
+    return arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def fiber_structure(a, b, phi, E=None):
+    """(H4, H6, M4, M6) of the two fibre families (library host helper, Section 3)."""
+    E = np.ascontiguousarray(np.eye(3) if E is None else E, dtype=np.float64)
+    H4, H6 = np.zeros(9), np.zeros(9)
+    M4, M6 = np.zeros(3), np.zeros(3)
+    _check(lib.hx_fiber_structure(a, b, phi, _dptr(E), _dptr(H4), _dptr(H6), _dptr(M4), _dptr(M6)))
+    return H4.reshape(3, 3), H6.reshape(3, 3), M4, M6
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Operator:
+    """A context of the library: mesh, degree, material; owns device memory until close()."""
+
+    def __init__(self, nx, ny, nz, vertices, p, law="cnh", mu=1.0, lam=0.0, kappa=0.0, k1=0.0,
+                 k2=0.0, H4=None, H6=None, M4=None, M6=None, dirichlet_faces=(),
+                 periodic=(False, False, False), jpow_newton_iters=0):
+        V = np.ascontiguousarray(vertices, dtype=np.float64)
+        self._vert = V
+        mesh = _Mesh(int(nx), int(ny), int(nz),
+                     int(sum(1 << d for d in range(3) if periodic[d])), _dptr(V),
+                     int(sum(1 << f for f in dirichlet_faces)))
+        mat = _Material()
+        mat.law = LAWS[law]
+        mat.mu, mat.lam, mat.kappa, mat.k1, mat.k2 = mu, lam, kappa, k1, k2
+        for name, val, n in (("H4", H4, 9), ("H6", H6, 9), ("M4", M4, 3), ("M6", M6, 3)):
+            arr = np.zeros(n) if val is None else np.asarray(val, dtype=np.float64).ravel()
+            getattr(mat, name)[:] = arr.tolist()
+        opt = _Options()
+        opt.jpow_newton_iters = int(jpow_newton_iters)
+        ctx = ctypes.c_void_p()
+        _check(lib.hx_setup(ctypes.byref(mesh), int(p), ctypes.byref(mat), ctypes.byref(opt), ctypes.byref(ctx)))
+        self.ctx = ctx
+        self.p = int(p)
+        self.num_nodes = int(lib.hx_num_nodes(ctx))
+        self.num_dofs = int(lib.hx_num_dofs(ctx))
+        self.num_cells = int(lib.hx_num_cells(ctx))
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib.hx_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def node_coords(self):
+        out = np.zeros((self.num_nodes, 3))
+        _check(lib.hx_node_coords(self.ctx, _dptr(out)), self.ctx)
+        return out
+
+    def constrained_mask(self):
+        out = np.zeros(self.num_nodes, dtype=np.uint8)
+        _check(lib.hx_constrained_mask(self.ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))), self.ctx)
+        return out.astype(bool)
+
+    def _vec(self, t, dtype, name):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+        if t.dtype != dtype:
+            raise TypeError(f"{name} must be {dtype}")
+        if t.numel() != self.num_dofs or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with {self.num_dofs} entries ([3][n_nodes])")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def residual(self, u, r=None, stream=None):
+        import torch
+        r = torch.empty_like(u) if r is None else r
+        _check(lib.hx_residual(self.ctx, self._vec(u, torch.float64, "u"), self._vec(r, torch.float64, "r"),
+                               _stream_handle(stream)), self.ctx)
+        return r
+
+    def update_linearization(self, u, mode="tangent", precision="fp64", stream=None):
+        import torch
+        _check(lib.hx_update_linearization(self.ctx, self._vec(u, torch.float64, "u"), MODES[mode],
+                                           PRECISIONS[precision], _stream_handle(stream)), self.ctx)
+
+    def apply_tangent(self, du, dst=None, precision="fp64", stream=None):
+        import torch
+        dt = torch.float64 if precision == "fp64" else torch.float32
+        dst = torch.empty_like(du) if dst is None else dst
+        _check(lib.hx_apply_tangent(self.ctx, self._vec(du, dt, "du"), self._vec(dst, dt, "dst"),
+                                    PRECISIONS[precision], _stream_handle(stream)), self.ctx)
+        return dst
+
+    def linearization_bytes(self, precision="fp64"):
+        return int(lib.hx_linearization_bytes(self.ctx, PRECISIONS[precision]))

@@ -1,0 +1,70 @@
+"""Builds libhx.so for gfx950 in-tree: one translation unit per polynomial degree plus the host
+runtime, compiled in parallel with hipcc and linked into paper_2408_12479_amd/libhx.so."""
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+BUILD = os.path.join(ROOT, "_build")
+LIB = os.path.join(PKG, "libhx.so")
+DEGREES = range(1, 7)
+
+ARCH = "gfx950"
+FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    # packed FP32 instructions stay off
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-I" + INCLUDE, "-I" + CSRC,
+]
+
+
+def _hipcc():
+    h = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(h):
+        raise RuntimeError("hipcc not found")
+    return h
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    lines = [ln for ln in r.stdout.splitlines() if "packed-fp32-ops" not in ln]
+    if r.returncode != 0:
+        raise RuntimeError("command failed:\n" + " ".join(cmd) + "\n" + "\n".join(lines))
+    return "\n".join(lines)
+
+
+def build(jobs=None, verbose=False):
+    """Compiles every translation unit and links libhx.so; returns the library path."""
+    os.makedirs(BUILD, exist_ok=True)
+    hipcc = _hipcc()
+    units = []
+    for p in DEGREES:
+        units.append(([hipcc] + FLAGS + [f"-DHX_DEGREE={p}", "-c", os.path.join(CSRC, "hx_degree.hip"),
+                       "-o", os.path.join(BUILD, f"hx_p{p}.o")], f"p{p}"))
+    units.append(([hipcc] + FLAGS + ["-c", os.path.join(CSRC, "hx_api.hip"),
+                   "-o", os.path.join(BUILD, "hx_api.o")], "api"))
+    jobs = jobs or min(len(units), max(1, os.cpu_count() or 1), 16)
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        futs = {ex.submit(_run, cmd): name for cmd, name in units}
+        for f in cf.as_completed(futs):
+            out = f.result()
+            if verbose:
+                print(f"[build] {futs[f]} done", flush=True)
+                if out.strip():
+                    print(out)
+    objs = [os.path.join(BUILD, f"hx_p{p}.o") for p in DEGREES] + [os.path.join(BUILD, "hx_api.o")]
+    tmp = LIB + ".tmp"
+    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs)
+    os.replace(tmp, LIB)
+    if verbose:
+        print(f"[build] linked {LIB}", flush=True)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose="-q" not in sys.argv)

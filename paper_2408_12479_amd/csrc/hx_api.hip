@@ -1,0 +1,641 @@
+// Host runtime of libhx.so: context setup, device memory, 1D basis tables and the C ABI of hx.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hx.h"
+#include "hx_internal.hpp"
+
+namespace hx {
+
+// ------------------------------------------------------------------------------------------
+// 1D rules on [0, 1] (host, long double Newton iterations)
+// ------------------------------------------------------------------------------------------
+static void legendre_ld(int n, long double x, long double& P, long double& dP) {
+  long double p0 = 1.0L, p1 = x;
+  if (n == 0) {
+    P = 1.0L;
+    dP = 0.0L;
+    return;
+  }
+  for (int k = 2; k <= n; ++k) {
+    const long double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+    p0 = p1;
+    p1 = p2;
+  }
+  P = p1;
+  dP = n * (p0 - x * p1) / (1.0L - x * x);
+}
+
+// Gauss-Legendre points/weights of n points on [0, 1] (roots of P_n by Newton).
+static void gauss_points(int n, std::vector<double>& x, std::vector<double>& w) {
+  const long double pi = 3.141592653589793238462643383279503L;
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    long double z = std::cos(pi * (i + 0.75L) / (n + 0.5L));
+    long double P, dP;
+    for (int it = 0; it < 100; ++it) {
+      legendre_ld(n, z, P, dP);
+      const long double dz = P / dP;
+      z -= dz;
+      if (std::fabs(dz) < 1e-19L) break;
+    }
+    legendre_ld(n, z, P, dP);
+    // z descends with i; store ascending on [0, 1]
+    x[n - 1 - i] = static_cast<double>(0.5L * (1.0L + z));
+    w[n - 1 - i] = static_cast<double>(1.0L / ((1.0L - z * z) * dP * dP));
+  }
+}
+
+// Gauss-Lobatto points of degree p on [0, 1]: end points and the roots of P_p'.
+static std::vector<double> gll_points(int p) {
+  std::vector<double> x(p + 1);
+  x[0] = 0.0;
+  x[p] = 1.0;
+  const long double pi = 3.141592653589793238462643383279503L;
+  for (int i = 1; i < p; ++i) {
+    long double z = -std::cos(pi * i / p);  // Chebyshev-Lobatto guess, ascending
+    for (int it = 0; it < 100; ++it) {
+      long double P, dP;
+      legendre_ld(p, z, P, dP);
+      const long double d2P = (2.0L * z * dP - p * (p + 1) * P) / (1.0L - z * z);
+      const long double dz = dP / d2P;
+      z -= dz;
+      if (std::fabs(dz) < 1e-19L) break;
+    }
+    x[i] = static_cast<double>(0.5L * (1.0L + z));
+  }
+  return x;
+}
+
+static long double lagrange(const std::vector<double>& nodes, int i, long double x) {
+  long double v = 1.0L;
+  for (size_t m = 0; m < nodes.size(); ++m)
+    if (static_cast<int>(m) != i) v *= (x - nodes[m]) / ((long double)nodes[i] - nodes[m]);
+  return v;
+}
+
+static long double lagrange_deriv(const std::vector<double>& nodes, int i, long double x) {
+  long double s = 0.0L;
+  const int n = static_cast<int>(nodes.size());
+  for (int m = 0; m < n; ++m) {
+    if (m == i) continue;
+    long double t = 1.0L / ((long double)nodes[i] - nodes[m]);
+    for (int l = 0; l < n; ++l)
+      if (l != i && l != m) t *= (x - nodes[l]) / ((long double)nodes[i] - nodes[l]);
+    s += t;
+  }
+  return s;
+}
+
+static void basis_tables(int p, HostArgs& h, std::vector<double>& gll) {
+  const int n = p + 1;
+  std::vector<double> xq, wq;
+  gauss_points(n, xq, wq);
+  gll = gll_points(p);
+  for (int q = 0; q < n; ++q) {
+    h.x[q] = xq[q];
+    h.w[q] = wq[q];
+    for (int i = 0; i < n; ++i) {
+      h.B[q * n + i] = static_cast<double>(lagrange(gll, i, xq[q]));
+      h.D[q * n + i] = static_cast<double>(lagrange_deriv(xq, i, xq[q]));
+    }
+  }
+}
+
+// Modified Bessel functions I0, I1 by their power series (all terms positive).
+static double bessel_i(int order, double a) {
+  const double h = 0.5 * a;
+  double term = order == 0 ? 1.0 : h, sum = term;
+  for (int k = 1; k < 500; ++k) {
+    term *= h * h / (static_cast<double>(k) * (k + order));
+    sum += term;
+    if (term < 1e-18 * sum) break;
+  }
+  return sum;
+}
+
+}  // namespace hx
+
+using namespace hx;
+
+namespace {
+
+struct Slot {
+  bool valid = false;
+  hx_storage mode = HX_STORE_NONE;
+  int store = kStoreF64;
+  void* qdata = nullptr;
+  size_t qbytes = 0;
+  float* cscale = nullptr;
+  void* uk = nullptr;  // linearisation point (recompute mode): double or float
+};
+
+thread_local std::string g_setup_error;
+
+}  // namespace
+
+struct hx_ctx_s {
+  int device = 0;
+  int p = 0;
+  Lattice L{};
+  HostArgs base{};
+  std::vector<double> gll;
+  std::vector<double> vert_host;  // [V][3]
+  double* vert64 = nullptr;
+  float* vert32 = nullptr;
+  int* flag = nullptr;
+  void* cblk64 = nullptr;
+  void* cblk32 = nullptr;
+  Slot slot[2];  // 0: FP64 class, 1: FP32 class
+  std::string err;
+};
+
+namespace {
+
+hx_status fail(hx_ctx ctx, hx_status s, const std::string& msg) {
+  if (ctx)
+    ctx->err = msg;
+  else
+    g_setup_error = msg;
+  return s;
+}
+
+hx_status hip_fail(hx_ctx ctx, hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(ctx, e == hipErrorOutOfMemory ? HX_E_NOMEM : HX_E_HIP, m);
+}
+
+hipError_t dispatch(int p, const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok) {
+  switch (p) {
+    case 1: return dispatch_p1(op, h, s, ok);
+    case 2: return dispatch_p2(op, h, s, ok);
+    case 3: return dispatch_p3(op, h, s, ok);
+    case 4: return dispatch_p4(op, h, s, ok);
+    case 5: return dispatch_p5(op, h, s, ok);
+    case 6: return dispatch_p6(op, h, s, ok);
+    default: *ok = false; return hipSuccess;
+  }
+}
+
+hipError_t write_consts(int p, const HostArgs& h) {
+  switch (p) {
+    case 1: return consts_p1(h);
+    case 2: return consts_p2(h);
+    case 3: return consts_p3(h);
+    case 4: return consts_p4(h);
+    case 5: return consts_p5(h);
+    case 6: return consts_p6(h);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+bool is_constrained(const Lattice& L, int64_t node) {
+  const int I = static_cast<int>(node % L.Nx);
+  const int J = static_cast<int>((node / L.Nx) % L.Ny);
+  const int K = static_cast<int>(node / (static_cast<int64_t>(L.Nx) * L.Ny));
+  const uint32_t f = L.dir_faces;
+  return ((f & 1u) && I == 0) || ((f & 2u) && I == L.Nx - 1) || ((f & 4u) && J == 0) ||
+         ((f & 8u) && J == L.Ny - 1) || ((f & 16u) && K == 0) || ((f & 32u) && K == L.Nz - 1);
+}
+
+// vertex v = a + 2b + 4c of cell (ex, ey, ez)
+const double* cell_vertex(const hx_ctx_s* c, int ex, int ey, int ez, int v) {
+  const Lattice& L = c->L;
+  int vx = ex + (v & 1), vy = ey + ((v >> 1) & 1), vz = ez + (v >> 2);
+  vx = vx >= L.Vx ? vx - L.Vx : vx;
+  vy = vy >= L.Vy ? vy - L.Vy : vy;
+  vz = vz >= L.Vz ? vz - L.Vz : vz;
+  return &c->vert_host[3 * (vx + static_cast<int64_t>(L.Vx) * (vy + static_cast<int64_t>(L.Vy) * vz))];
+}
+
+void trilinear(const hx_ctx_s* c, int ex, int ey, int ez, double s, double t, double r, double* X) {
+  X[0] = X[1] = X[2] = 0.0;
+  for (int v = 0; v < 8; ++v) {
+    const double wv = ((v & 1) ? s : 1 - s) * (((v >> 1) & 1) ? t : 1 - t) * ((v >> 2) ? r : 1 - r);
+    const double* P = cell_vertex(c, ex, ey, ez, v);
+    for (int k = 0; k < 3; ++k) X[k] += wv * P[k];
+  }
+}
+
+// smallest det J0 over all Gauss points of all cells (trilinear maps)
+double min_detJ0(const hx_ctx_s* c) {
+  const Lattice& L = c->L;
+  const int n = c->p + 1;
+  double mn = 1e300;
+  for (int ez = 0; ez < L.nz; ++ez)
+    for (int ey = 0; ey < L.ny; ++ey)
+      for (int ex = 0; ex < L.nx; ++ex) {
+        const double* X[8];
+        for (int v = 0; v < 8; ++v) X[v] = cell_vertex(c, ex, ey, ez, v);
+        for (int qz = 0; qz < n; ++qz)
+          for (int qy = 0; qy < n; ++qy)
+            for (int qx = 0; qx < n; ++qx) {
+              const double s = c->base.x[qx], t = c->base.x[qy], r = c->base.x[qz];
+              double J[9];
+              for (int k = 0; k < 3; ++k) {
+                J[3 * k + 0] = (1 - t) * (1 - r) * (X[1][k] - X[0][k]) + t * (1 - r) * (X[3][k] - X[2][k]) +
+                               (1 - t) * r * (X[5][k] - X[4][k]) + t * r * (X[7][k] - X[6][k]);
+                J[3 * k + 1] = (1 - s) * (1 - r) * (X[2][k] - X[0][k]) + s * (1 - r) * (X[3][k] - X[1][k]) +
+                               (1 - s) * r * (X[6][k] - X[4][k]) + s * r * (X[7][k] - X[5][k]);
+                J[3 * k + 2] = (1 - s) * (1 - t) * (X[4][k] - X[0][k]) + s * (1 - t) * (X[5][k] - X[1][k]) +
+                               (1 - s) * t * (X[6][k] - X[2][k]) + s * t * (X[7][k] - X[3][k]);
+              }
+              const double det = J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) +
+                                 J[2] * (J[3] * J[7] - J[4] * J[6]);
+              mn = std::min(mn, det);
+            }
+      }
+  return mn;
+}
+
+template <typename T>
+__global__ void copy_convert(const double* __restrict__ src, T* __restrict__ dst, int64_t n) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    dst[i] = static_cast<T>(src[i]);
+}
+
+template <typename R>
+__global__ void init_output_kernel(R* __restrict__ out, const R* __restrict__ du, Lattice L,
+                                   int copy_constrained) {
+  const int64_t n = L.n_nodes;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < 3 * n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    R v = R(0);
+    if (copy_constrained && L.dir_faces) {
+      const int64_t node = i % n;
+      const int I = static_cast<int>(node % L.Nx);
+      const int J = static_cast<int>((node / L.Nx) % L.Ny);
+      const int K = static_cast<int>(node / (static_cast<int64_t>(L.Nx) * L.Ny));
+      const uint32_t f = L.dir_faces;
+      const bool cons = ((f & 1u) && I == 0) || ((f & 2u) && I == L.Nx - 1) ||
+                        ((f & 4u) && J == 0) || ((f & 8u) && J == L.Ny - 1) ||
+                        ((f & 16u) && K == 0) || ((f & 32u) && K == L.Nz - 1);
+      if (cons) v = du[i];
+    }
+    out[i] = v;
+  }
+}
+
+__global__ void clear_flag(int* f) { *f = 0; }
+
+int grid_for(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(b, 8192)));
+}
+
+HostArgs args_for(const hx_ctx_s* c) {
+  HostArgs h = c->base;
+  h.vert64 = c->vert64;
+  h.vert32 = c->vert32;
+  h.flag = c->flag;
+  h.cblk64 = c->cblk64;
+  h.cblk32 = c->cblk32;
+  return h;
+}
+
+int store_of(hx_precision p) {
+  switch (p) {
+    case HX_FP64: return kStoreF64;
+    case HX_FP32: return kStoreF32;
+    case HX_FP32_BF16DATA: return kStoreBF16;
+    case HX_FP32_FP16DATA: return kStoreF16;
+  }
+  return -1;
+}
+
+size_t store_bytes(int s) { return s == kStoreF64 ? 8 : (s == kStoreF32 ? 4 : 2); }
+
+void release_slot(Slot& s) {
+  if (s.qdata) (void)hipFree(s.qdata);
+  if (s.cscale) (void)hipFree(s.cscale);
+  if (s.uk) (void)hipFree(s.uk);
+  s = Slot();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hx_status_string(hx_status s) {
+  switch (s) {
+    case HX_OK: return "ok";
+    case HX_E_ARG: return "invalid argument";
+    case HX_E_HIP: return "HIP runtime error";
+    case HX_E_NOMEM: return "out of device memory";
+    case HX_E_STATE: return "call out of order";
+    case HX_E_INVERTED: return "inverted element or deformation (det <= 0)";
+    case HX_E_NONFINITE: return "non-finite linearisation data";
+    case HX_E_NOT_CONVERGED: return "not converged";
+    case HX_E_UNSUPPORTED: return "unsupported combination";
+  }
+  return "unknown status";
+}
+
+const char* hx_last_error(hx_ctx ctx) { return ctx ? ctx->err.c_str() : g_setup_error.c_str(); }
+
+hx_status hx_fiber_structure(double a, double b, double phi, const double* E, double* H4,
+                             double* H6, double* M4, double* M6) {
+  if (!E || !H4 || !H6 || !M4 || !M6 || !(a >= 0.0) || !(b > 0.0) || !std::isfinite(phi))
+    return fail(nullptr, HX_E_ARG, "hx_fiber_structure: invalid argument");
+  const double pi = 3.14159265358979323846;
+  const double H33 = 1.0 / (4.0 * b) - std::exp(-2.0 * b) / (std::sqrt(2.0 * pi * b) * std::erf(std::sqrt(2.0 * b)));
+  const double ratio = bessel_i(1, a) / bessel_i(0, a);
+  const double H11 = 0.5 * (1.0 - H33) * (1.0 + ratio);
+  const double H22 = 0.5 * (1.0 - H33) * (1.0 - ratio);
+  for (int fam = 0; fam < 2; ++fam) {
+    const double ang = fam == 0 ? phi : -phi;
+    const double c = std::cos(ang), s = std::sin(ang);
+    double M1[3], M2[3], M3[3];
+    for (int k = 0; k < 3; ++k) {
+      M1[k] = c * E[k] + s * E[3 + k];
+      M2[k] = -s * E[k] + c * E[3 + k];
+      M3[k] = E[6 + k];
+    }
+    double* H = fam == 0 ? H4 : H6;
+    double* M = fam == 0 ? M4 : M6;
+    for (int i = 0; i < 3; ++i) {
+      M[i] = M1[i];
+      for (int j = 0; j < 3; ++j)
+        H[3 * i + j] = H11 * M1[i] * M1[j] + H22 * M2[i] * M2[j] + H33 * M3[i] * M3[j];
+    }
+  }
+  return HX_OK;
+}
+
+hx_status hx_setup(const hx_mesh* mesh, int32_t p, const hx_material* mat, const hx_options* opt,
+                   hx_ctx* out) {
+  if (!out) return fail(nullptr, HX_E_ARG, "hx_setup: out is NULL");
+  *out = nullptr;
+  if (!mesh || !mat || !mesh->vertices) return fail(nullptr, HX_E_ARG, "hx_setup: NULL mesh, vertices or material");
+  if (p < 1 || p > kMaxDegree) return fail(nullptr, HX_E_UNSUPPORTED, "hx_setup: degree must be in [1, 6]");
+  if (mesh->nx < 1 || mesh->ny < 1 || mesh->nz < 1) return fail(nullptr, HX_E_ARG, "hx_setup: empty lattice");
+  if (mat->law != HX_LAW_CNH && mat->law != HX_LAW_INH && mat->law != HX_LAW_FIBER)
+    return fail(nullptr, HX_E_ARG, "hx_setup: unknown law");
+  if (opt) {
+    for (int i = 0; i < 7; ++i)
+      if (opt->reserved[i]) return fail(nullptr, HX_E_ARG, "hx_setup: reserved option fields must be zero");
+    if (opt->jpow_newton_iters < 0 || opt->jpow_newton_iters > 16)
+      return fail(nullptr, HX_E_ARG, "hx_setup: jpow_newton_iters out of [0, 16]");
+  }
+  if (mesh->dirichlet_faces >> 6) return fail(nullptr, HX_E_ARG, "hx_setup: dirichlet_faces has bits above 5");
+
+  hx_ctx_s* c = new (std::nothrow) hx_ctx_s();
+  if (!c) return fail(nullptr, HX_E_NOMEM, "hx_setup: host allocation failed");
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return fail(nullptr, HX_E_HIP, "hx_setup: no HIP device");
+  }
+  c->p = p;
+  Lattice& L = c->L;
+  L.nx = mesh->nx;
+  L.ny = mesh->ny;
+  L.nz = mesh->nz;
+  L.p = p;
+  const int per = mesh->periodic;
+  const int64_t cells = static_cast<int64_t>(L.nx) * L.ny * L.nz;
+  L.Vx = L.nx + ((per & 1) ? 0 : 1);
+  L.Vy = L.ny + ((per & 2) ? 0 : 1);
+  L.Vz = L.nz + ((per & 4) ? 0 : 1);
+  const int64_t Nx = static_cast<int64_t>(L.nx) * p + ((per & 1) ? 0 : 1);
+  const int64_t Ny = static_cast<int64_t>(L.ny) * p + ((per & 2) ? 0 : 1);
+  const int64_t Nz = static_cast<int64_t>(L.nz) * p + ((per & 4) ? 0 : 1);
+  const int64_t nodes = Nx * Ny * Nz;
+  const int64_t q = static_cast<int64_t>(p + 1) * (p + 1) * (p + 1);
+  if (cells * q > (int64_t(1) << 31) - 1 || Nx > (1 << 30) || Ny > (1 << 30) || Nz > (1 << 30)) {
+    delete c;
+    return fail(nullptr, HX_E_ARG, "hx_setup: mesh too large (cells * (p+1)^3 must fit in int32)");
+  }
+  L.Nx = static_cast<int32_t>(Nx);
+  L.Ny = static_cast<int32_t>(Ny);
+  L.Nz = static_cast<int32_t>(Nz);
+  L.n_cells = static_cast<int32_t>(cells);
+  L.n_nodes = nodes;
+  uint32_t faces = mesh->dirichlet_faces;
+  if (per & 1) faces &= ~3u;
+  if (per & 2) faces &= ~12u;
+  if (per & 4) faces &= ~48u;
+  L.dir_faces = faces;
+
+  HostArgs& h = c->base;
+  std::memset(&h, 0, sizeof(h));
+  h.L = L;
+  basis_tables(p, h, c->gll);
+  h.mat = *mat;
+  h.jpow_iters = opt ? opt->jpow_newton_iters : 0;
+
+  const int64_t nv = static_cast<int64_t>(L.Vx) * L.Vy * L.Vz;
+  c->vert_host.assign(mesh->vertices, mesh->vertices + 3 * nv);
+  for (double v : c->vert_host)
+    if (!std::isfinite(v)) {
+      delete c;
+      return fail(nullptr, HX_E_ARG, "hx_setup: non-finite vertex coordinate");
+    }
+  if (!(min_detJ0(c) > 0.0)) {
+    delete c;
+    return fail(nullptr, HX_E_INVERTED, "hx_setup: det J0 <= 0 at a Gauss point of some cell");
+  }
+
+  std::vector<float> v32(c->vert_host.begin(), c->vert_host.end());
+  hipError_t e;
+  if ((e = hipMalloc(&c->vert64, 3 * nv * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc(&c->vert32, 3 * nv * sizeof(float))) != hipSuccess ||
+      (e = hipMalloc(&c->flag, sizeof(int))) != hipSuccess ||
+      (e = hipMalloc(&c->cblk64, kConstBlockBytes)) != hipSuccess ||
+      (e = hipMalloc(&c->cblk32, kConstBlockBytes)) != hipSuccess) {
+    hx_destroy(c);
+    return hip_fail(nullptr, e, "hx_setup: allocation");
+  }
+  if ((e = hipMemcpy(c->vert64, c->vert_host.data(), 3 * nv * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(c->vert32, v32.data(), 3 * nv * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemset(c->flag, 0, sizeof(int))) != hipSuccess) {
+    hx_destroy(c);
+    return hip_fail(nullptr, e, "hx_setup: copy");
+  }
+  HostArgs ha = args_for(c);
+  if ((e = write_consts(p, ha)) != hipSuccess) {
+    hx_destroy(c);
+    return hip_fail(nullptr, e, "hx_setup: constants");
+  }
+  *out = c;
+  return HX_OK;
+}
+
+hx_status hx_destroy(hx_ctx ctx) {
+  if (!ctx) return HX_OK;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(ctx->device);
+  for (Slot& s : ctx->slot) release_slot(s);
+  if (ctx->vert64) (void)hipFree(ctx->vert64);
+  if (ctx->vert32) (void)hipFree(ctx->vert32);
+  if (ctx->flag) (void)hipFree(ctx->flag);
+  if (ctx->cblk64) (void)hipFree(ctx->cblk64);
+  if (ctx->cblk32) (void)hipFree(ctx->cblk32);
+  (void)hipSetDevice(cur);
+  delete ctx;
+  return HX_OK;
+}
+
+int64_t hx_num_nodes(hx_ctx ctx) { return ctx ? ctx->L.n_nodes : -1; }
+int64_t hx_num_dofs(hx_ctx ctx) { return ctx ? 3 * ctx->L.n_nodes : -1; }
+int64_t hx_num_cells(hx_ctx ctx) { return ctx ? ctx->L.n_cells : -1; }
+
+hx_status hx_node_coords(hx_ctx ctx, double* xyz) {
+  if (!ctx || !xyz) return fail(ctx, HX_E_ARG, "hx_node_coords: NULL argument");
+  const Lattice& L = ctx->L;
+  const int p = ctx->p;
+  for (int64_t node = 0; node < L.n_nodes; ++node) {
+    const int lat[3] = {static_cast<int>(node % L.Nx), static_cast<int>((node / L.Nx) % L.Ny),
+                        static_cast<int>(node / (static_cast<int64_t>(L.Nx) * L.Ny))};
+    const int nc[3] = {L.nx, L.ny, L.nz};
+    int cell[3];
+    double loc[3];
+    for (int d = 0; d < 3; ++d) {
+      cell[d] = std::min(lat[d] / p, nc[d] - 1);
+      loc[d] = ctx->gll[lat[d] - cell[d] * p];
+    }
+    trilinear(ctx, cell[0], cell[1], cell[2], loc[0], loc[1], loc[2], xyz + 3 * node);
+  }
+  return HX_OK;
+}
+
+hx_status hx_constrained_mask(hx_ctx ctx, uint8_t* mask) {
+  if (!ctx || !mask) return fail(ctx, HX_E_ARG, "hx_constrained_mask: NULL argument");
+  for (int64_t node = 0; node < ctx->L.n_nodes; ++node) mask[node] = is_constrained(ctx->L, node) ? 1 : 0;
+  return HX_OK;
+}
+
+hx_status hx_residual(hx_ctx ctx, const double* u, double* r, void* stream) {
+  if (!ctx || !u || !r) return fail(ctx, HX_E_ARG, "hx_residual: NULL argument");
+  if (static_cast<const void*>(u) == static_cast<const void*>(r)) return fail(ctx, HX_E_ARG, "hx_residual: u and r alias");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t n = 3 * ctx->L.n_nodes;
+  init_output_kernel<double><<<grid_for(n), 256, 0, s>>>(r, nullptr, ctx->L, 0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(ctx, e, "hx_residual: init");
+  HostArgs h = args_for(ctx);
+  h.in0 = u;
+  h.out = r;
+  HostOp op{OpKind::Residual, ctx->base.mat.law, HX_STORE_NONE, kStoreF64, false};
+  bool ok = false;
+  e = dispatch(ctx->p, op, h, s, &ok);
+  if (!ok) return fail(ctx, HX_E_UNSUPPORTED, "hx_residual: not built");
+  if (e != hipSuccess) return hip_fail(ctx, e, "hx_residual: launch");
+  return HX_OK;
+}
+
+hx_status hx_update_linearization(hx_ctx ctx, const double* u, hx_storage mode, hx_precision prec,
+                                  void* stream) {
+  if (!ctx || !u) return fail(ctx, HX_E_ARG, "hx_update_linearization: NULL argument");
+  if (mode != HX_STORE_NONE && mode != HX_STORE_FINV_J && mode != HX_STORE_TANGENT)
+    return fail(ctx, HX_E_ARG, "hx_update_linearization: unknown storage mode");
+  const int st = store_of(prec);
+  if (st < 0) return fail(ctx, HX_E_ARG, "hx_update_linearization: unknown precision");
+  if ((st == kStoreBF16 || st == kStoreF16) && mode != HX_STORE_TANGENT)
+    return fail(ctx, HX_E_UNSUPPORTED, "hx_update_linearization: 16-bit data only for the stored tangent");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Slot& sl = ctx->slot[prec == HX_FP64 ? 0 : 1];
+  const Lattice& L = ctx->L;
+  const int64_t Q = static_cast<int64_t>(ctx->p + 1) * (ctx->p + 1) * (ctx->p + 1);
+  const size_t need = static_cast<size_t>(mode_words(mode)) * L.n_cells * Q * store_bytes(st);
+  hipError_t e = hipStreamSynchronize(s);  // the slot's buffers may still be in use
+  if (e != hipSuccess) return hip_fail(ctx, e, "hx_update_linearization: sync");
+  if (sl.qbytes != need || (need && !sl.qdata)) {
+    if (sl.qdata) (void)hipFree(sl.qdata);
+    sl.qdata = nullptr;
+    sl.qbytes = 0;
+    if (need) {
+      if ((e = hipMalloc(&sl.qdata, need)) != hipSuccess) {
+        sl.valid = false;
+        return hip_fail(ctx, e, "hx_update_linearization: q-point data");
+      }
+    }
+    sl.qbytes = need;
+  }
+  if (st == kStoreF16 && !sl.cscale) {
+    if ((e = hipMalloc(&sl.cscale, L.n_cells * sizeof(float))) != hipSuccess) {
+      sl.valid = false;
+      return hip_fail(ctx, e, "hx_update_linearization: cell scales");
+    }
+  }
+  const int64_t n = 3 * L.n_nodes;
+  if (mode == HX_STORE_NONE) {
+    const size_t ub = n * (prec == HX_FP64 ? sizeof(double) : sizeof(float));
+    if (!sl.uk) {
+      if ((e = hipMalloc(&sl.uk, ub)) != hipSuccess) {
+        sl.valid = false;
+        return hip_fail(ctx, e, "hx_update_linearization: u_k");
+      }
+    }
+    if (prec == HX_FP64)
+      copy_convert<double><<<grid_for(n), 256, 0, s>>>(u, static_cast<double*>(sl.uk), n);
+    else
+      copy_convert<float><<<grid_for(n), 256, 0, s>>>(u, static_cast<float*>(sl.uk), n);
+  }
+  clear_flag<<<1, 1, 0, s>>>(ctx->flag);
+  HostArgs h = args_for(ctx);
+  h.in0 = u;
+  h.qdata_w = sl.qdata;
+  h.cscale_w = sl.cscale;
+  HostOp op{OpKind::Update, ctx->base.mat.law, mode, st, false};
+  bool ok = false;
+  e = dispatch(ctx->p, op, h, s, &ok);
+  if (!ok) return fail(ctx, HX_E_UNSUPPORTED, "hx_update_linearization: combination not built");
+  if (e != hipSuccess) return hip_fail(ctx, e, "hx_update_linearization: launch");
+  int flag = 0;
+  if ((e = hipMemcpyAsync(&flag, ctx->flag, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess)
+    return hip_fail(ctx, e, "hx_update_linearization: status read");
+  sl.valid = true;
+  sl.mode = mode;
+  sl.store = st;
+  if (flag & kFlagInverted) return fail(ctx, HX_E_INVERTED, "hx_update_linearization: J <= 0 at a q-point");
+  if (flag & kFlagNonFinite) return fail(ctx, HX_E_NONFINITE, "hx_update_linearization: non-finite data");
+  return HX_OK;
+}
+
+hx_status hx_apply_tangent(hx_ctx ctx, const void* du, void* dst, hx_precision prec, void* stream) {
+  if (!ctx || !du || !dst) return fail(ctx, HX_E_ARG, "hx_apply_tangent: NULL argument");
+  if (du == dst) return fail(ctx, HX_E_ARG, "hx_apply_tangent: du and dst alias");
+  if (store_of(prec) < 0) return fail(ctx, HX_E_ARG, "hx_apply_tangent: unknown precision");
+  const bool fp32 = prec != HX_FP64;
+  const Slot& sl = ctx->slot[fp32 ? 1 : 0];
+  if (!sl.valid) return fail(ctx, HX_E_STATE, "hx_apply_tangent: no linearisation stored for this precision");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t n = 3 * ctx->L.n_nodes;
+  if (fp32)
+    init_output_kernel<float><<<grid_for(n), 256, 0, s>>>(static_cast<float*>(dst), static_cast<const float*>(du), ctx->L, 1);
+  else
+    init_output_kernel<double><<<grid_for(n), 256, 0, s>>>(static_cast<double*>(dst), static_cast<const double*>(du), ctx->L, 1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(ctx, e, "hx_apply_tangent: init");
+  HostArgs h = args_for(ctx);
+  h.in0 = du;
+  h.in1 = sl.uk;
+  h.out = dst;
+  h.qdata = sl.qdata;
+  h.cscale = sl.cscale;
+  HostOp op{OpKind::Apply, ctx->base.mat.law, sl.mode, sl.store, fp32};
+  bool ok = false;
+  e = dispatch(ctx->p, op, h, s, &ok);
+  if (!ok) return fail(ctx, HX_E_UNSUPPORTED, "hx_apply_tangent: combination not built");
+  if (e != hipSuccess) return hip_fail(ctx, e, "hx_apply_tangent: launch");
+  return HX_OK;
+}
+
+int64_t hx_linearization_bytes(hx_ctx ctx, hx_precision prec) {
+  if (!ctx || store_of(prec) < 0) return -1;
+  const Slot& sl = ctx->slot[prec == HX_FP64 ? 0 : 1];
+  return sl.valid ? static_cast<int64_t>(sl.qbytes) : 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,171 @@
+// Kernel instantiations and launch dispatch for one polynomial degree (HX_DEGREE, set by the
+// build). Each degree is its own translation unit so degrees compile in parallel.
+#include <type_traits>
+
+#include "hx_kernels.hpp"
+
+#ifndef HX_DEGREE
+#error "HX_DEGREE must be defined"
+#endif
+
+#define HX_CAT2(a, b) a##b
+#define HX_CAT(a, b) HX_CAT2(a, b)
+
+namespace hx {
+namespace {
+
+constexpr int N = HX_DEGREE + 1;
+
+// Cells per workgroup: the workgroup holds EB * N^3 q-threads; chosen so that the thread count
+// is close to a multiple of the 64-wide wavefront.
+template <int n> struct Blocking { static constexpr int EB = 1; };
+template <> struct Blocking<2> { static constexpr int EB = 8; };   //  64 threads
+template <> struct Blocking<3> { static constexpr int EB = 7; };   // 189 of 192
+template <> struct Blocking<4> { static constexpr int EB = 2; };   // 128
+template <> struct Blocking<5> { static constexpr int EB = 2; };   // 250 of 256
+template <> struct Blocking<6> { static constexpr int EB = 1; };   // 216 of 256
+template <> struct Blocking<7> { static constexpr int EB = 1; };   // 343 of 384
+
+template <typename R>
+Consts<N, R> make_consts(const HostArgs& h) {
+  Consts<N, R> c{};
+  for (int i = 0; i < N * N; ++i) {
+    c.b.B[i] = static_cast<R>(h.B[i]);
+    c.b.D[i] = static_cast<R>(h.D[i]);
+  }
+  for (int i = 0; i < N; ++i) {
+    c.b.w[i] = static_cast<R>(h.w[i]);
+    c.b.x[i] = static_cast<R>(h.x[i]);
+  }
+  c.m.mu = static_cast<R>(h.mat.mu);
+  c.m.lam = static_cast<R>(h.mat.lambda);
+  c.m.kappa = static_cast<R>(h.mat.kappa);
+  c.m.k1 = static_cast<R>(h.mat.k1);
+  c.m.k2 = static_cast<R>(h.mat.k2);
+  for (int i = 0; i < 9; ++i) {
+    c.m.H4[i] = static_cast<R>(h.mat.H4[i]);
+    c.m.H6[i] = static_cast<R>(h.mat.H6[i]);
+  }
+  for (int i = 0; i < 3; ++i) {
+    c.m.M4[i] = static_cast<R>(h.mat.M4[i]);
+    c.m.M6[i] = static_cast<R>(h.mat.M6[i]);
+  }
+  c.m.jpow_iters = h.jpow_iters;
+  return c;
+}
+
+static_assert(sizeof(Consts<N, double>) <= kConstBlockBytes, "constant block too small");
+
+template <typename R>
+KernelArgs<N, R> make_args(const HostArgs& h) {
+  KernelArgs<N, R> a{};
+  a.L = h.L;
+  if constexpr (std::is_same<R, double>::value) {
+    a.c = static_cast<const Consts<N, R>*>(h.cblk64);
+    a.vert = h.vert64;
+  } else {
+    a.c = static_cast<const Consts<N, R>*>(h.cblk32);
+    a.vert = h.vert32;
+  }
+  a.in0 = static_cast<const R*>(h.in0);
+  a.in1 = static_cast<const R*>(h.in1);
+  a.out = static_cast<R*>(h.out);
+  a.qdata = h.qdata;
+  a.qdata_w = h.qdata_w;
+  a.cscale = h.cscale;
+  a.cscale_w = h.cscale_w;
+  a.flag = h.flag;
+  a.qstride = static_cast<int64_t>(h.L.n_cells) * N * N * N;
+  return a;
+}
+
+template <typename R, int KIND, int MODE, int LAW, int S>
+hipError_t launch(const HostArgs& h, hipStream_t s) {
+  constexpr int EB = Blocking<N>::EB;
+  const KernelArgs<N, R> a = make_args<R>(h);
+  const int nblk = (h.L.n_cells + EB - 1) / EB;
+  if (nblk == 0) return hipSuccess;
+  element_kernel<N, EB, R, KIND, MODE, LAW, S><<<dim3(nblk), dim3(EB * N * N * N), 0, s>>>(a);
+  return hipGetLastError();
+}
+
+template <int LAW>
+hipError_t by_law(const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok) {
+  *ok = true;
+  switch (op.kind) {
+    case OpKind::Residual:
+      return launch<double, 1, HX_STORE_NONE, LAW, kStoreF64>(h, s);
+    case OpKind::Update:
+      if (op.mode == HX_STORE_NONE) return launch<double, 2, HX_STORE_NONE, LAW, kStoreF64>(h, s);
+      if (op.mode == HX_STORE_FINV_J) {
+        if (op.store == kStoreF64) return launch<double, 2, HX_STORE_FINV_J, LAW, kStoreF64>(h, s);
+        if (op.store == kStoreF32) return launch<double, 2, HX_STORE_FINV_J, LAW, kStoreF32>(h, s);
+      }
+      if (op.mode == HX_STORE_TANGENT) {
+        switch (op.store) {
+          case kStoreF64: return launch<double, 2, HX_STORE_TANGENT, LAW, kStoreF64>(h, s);
+          case kStoreF32: return launch<double, 2, HX_STORE_TANGENT, LAW, kStoreF32>(h, s);
+          case kStoreBF16: return launch<double, 2, HX_STORE_TANGENT, LAW, kStoreBF16>(h, s);
+          case kStoreF16: return launch<double, 2, HX_STORE_TANGENT, LAW, kStoreF16>(h, s);
+          default: break;
+        }
+      }
+      break;
+    case OpKind::Apply:
+      if (op.mode == HX_STORE_NONE) {
+        return op.fp32 ? launch<float, 0, HX_STORE_NONE, LAW, kStoreF32>(h, s)
+                       : launch<double, 0, HX_STORE_NONE, LAW, kStoreF64>(h, s);
+      }
+      if (op.mode == HX_STORE_FINV_J) {
+        if (!op.fp32 && op.store == kStoreF64)
+          return launch<double, 0, HX_STORE_FINV_J, LAW, kStoreF64>(h, s);
+        if (op.fp32 && op.store == kStoreF32)
+          return launch<float, 0, HX_STORE_FINV_J, LAW, kStoreF32>(h, s);
+      }
+      break;
+  }
+  *ok = false;
+  return hipSuccess;
+}
+
+// The stored-tangent apply does not depend on the law.
+hipError_t apply_tangent_mode(const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok) {
+  *ok = true;
+  if (!op.fp32 && op.store == kStoreF64)
+    return launch<double, 0, HX_STORE_TANGENT, kCNH, kStoreF64>(h, s);
+  if (op.fp32) {
+    switch (op.store) {
+      case kStoreF32: return launch<float, 0, HX_STORE_TANGENT, kCNH, kStoreF32>(h, s);
+      case kStoreBF16: return launch<float, 0, HX_STORE_TANGENT, kCNH, kStoreBF16>(h, s);
+      case kStoreF16: return launch<float, 0, HX_STORE_TANGENT, kCNH, kStoreF16>(h, s);
+      default: break;
+    }
+  }
+  *ok = false;
+  return hipSuccess;
+}
+
+}  // namespace
+
+// Writes the constant blocks of a context (synchronous; called once at setup).
+hipError_t HX_CAT(consts_p, HX_DEGREE)(const HostArgs& h) {
+  const Consts<N, double> c64 = make_consts<double>(h);
+  const Consts<N, float> c32 = make_consts<float>(h);
+  hipError_t e = hipMemcpy(h.cblk64, &c64, sizeof(c64), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  return hipMemcpy(h.cblk32, &c32, sizeof(c32), hipMemcpyHostToDevice);
+}
+
+hipError_t HX_CAT(dispatch_p, HX_DEGREE)(const HostOp& op, const HostArgs& h, hipStream_t s,
+                                          bool* ok) {
+  if (op.kind == OpKind::Apply && op.mode == HX_STORE_TANGENT) return apply_tangent_mode(op, h, s, ok);
+  switch (op.law) {
+    case HX_LAW_CNH: return by_law<kCNH>(op, h, s, ok);
+    case HX_LAW_INH: return by_law<kINH>(op, h, s, ok);
+    case HX_LAW_FIBER: return by_law<kFIBER>(op, h, s, ok);
+  }
+  *ok = false;
+  return hipSuccess;
+}
+
+}  // namespace hx

@@ -1,0 +1,125 @@
+// Internal declarations shared by the host runtime (hx_api.cpp) and the per-degree kernel
+// translation units (hx_degree.hip, compiled once per polynomial degree).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "hx.h"
+
+namespace hx {
+
+constexpr int kMaxDegree = 6;
+
+// Structured lattice: cells, node lattice (Gauss-Lobatto points) and vertex lattice.
+struct Lattice {
+  int32_t nx, ny, nz;     // cells per direction
+  int32_t Nx, Ny, Nz;     // nodes per direction
+  int32_t Vx, Vy, Vz;     // vertices per direction
+  int32_t p;              // polynomial degree
+  uint32_t dir_faces;     // Dirichlet face bits, periodic directions cleared
+  int32_t n_cells;
+  int64_t n_nodes;
+};
+
+// 1D tables of degree p = N-1 on [0, 1]. B maps nodal values at the N Gauss-Lobatto points to
+// values at the N Gauss points; D differentiates a degree-p polynomial given by its values at
+// the Gauss points (collocation derivative), so grad = (D_d)(B x B x B) u.
+template <int N, typename R>
+struct Basis1D {
+  R B[N * N];  // B[q*N + i] = l_i(x_q)
+  R D[N * N];  // D[q*N + r] = l~_r'(x_q), l~ the Lagrange basis on the Gauss points
+  R w[N];      // Gauss weights
+  R x[N];      // Gauss points
+};
+
+template <typename R>
+struct MaterialK {
+  R mu, lam, kappa, k1, k2;
+  R H4[9], H6[9];
+  R M4[3], M6[3];
+  int32_t jpow_iters;
+};
+
+// Degree- and material-dependent constants, kept in device memory per context and read by
+// the kernels through a wave-uniform pointer (scalar loads).
+template <int N, typename R>
+struct Consts {
+  Basis1D<N, R> b;
+  MaterialK<R> m;
+};
+
+constexpr size_t kConstBlockBytes = 4096;
+
+// Everything a kernel needs, passed by value.
+template <int N, typename R>
+struct KernelArgs {
+  Lattice L;
+  const Consts<N, R>* __restrict__ c;
+  const R* vert;        // vertices [Vz][Vy][Vx][3]
+  const R* in0;         // gathered vector (du, or u for residual/update)
+  const R* in1;         // linearisation point u_k (recompute mode)
+  R* out;               // output vector (apply, residual)
+  const void* qdata;    // stored per-q-point planes [W][n_cells*Q]
+  void* qdata_w;        // planes written by the update
+  const float* cscale;  // per-cell power-of-two scale of binary16 data
+  float* cscale_w;
+  int* flag;            // status bits (kFlagInverted | kFlagNonFinite)
+  int64_t qstride;      // n_cells * Q
+};
+
+constexpr int kFlagInverted = 1;
+constexpr int kFlagNonFinite = 2;
+
+enum StoreType : int { kStoreF64 = 0, kStoreF32 = 1, kStoreBF16 = 2, kStoreF16 = 3 };
+enum class OpKind : int { Apply = 0, Residual = 1, Update = 2 };
+
+// Host-side description of one launch.
+struct HostOp {
+  OpKind kind;
+  hx_law law;
+  hx_storage mode;
+  int store;         // StoreType of the data (apply, update)
+  bool fp32;         // apply arithmetic and vector type (Apply only)
+};
+
+struct HostArgs {
+  Lattice L;
+  double B[64], D[64], w[8], x[8];   // 1D tables, row-major N x N
+  hx_material mat;
+  int32_t jpow_iters;
+  const double* vert64;
+  const float* vert32;
+  const void* in0;
+  const void* in1;
+  void* out;
+  const void* qdata;
+  void* qdata_w;
+  const float* cscale;
+  float* cscale_w;
+  int* flag;
+  void* cblk64;   // device block holding Consts<N, double>
+  void* cblk32;   // device block holding Consts<N, float>
+};
+
+// Words per q-point of each storage mode.
+inline int mode_words(hx_storage m) {
+  return m == HX_STORE_TANGENT ? 45 : (m == HX_STORE_FINV_J ? 10 : 0);
+}
+
+// One per degree, defined in hx_degree.hip compiled with HX_DEGREE = p.
+hipError_t consts_p1(const HostArgs&);
+hipError_t consts_p2(const HostArgs&);
+hipError_t consts_p3(const HostArgs&);
+hipError_t consts_p4(const HostArgs&);
+hipError_t consts_p5(const HostArgs&);
+hipError_t consts_p6(const HostArgs&);
+hipError_t dispatch_p1(const HostOp&, const HostArgs&, hipStream_t, bool*);
+hipError_t dispatch_p2(const HostOp&, const HostArgs&, hipStream_t, bool*);
+hipError_t dispatch_p3(const HostOp&, const HostArgs&, hipStream_t, bool*);
+hipError_t dispatch_p4(const HostOp&, const HostArgs&, hipStream_t, bool*);
+hipError_t dispatch_p5(const HostOp&, const HostArgs&, hipStream_t, bool*);
+hipError_t dispatch_p6(const HostOp&, const HostArgs&, hipStream_t, bool*);
+
+}  // namespace hx

@@ -1,0 +1,871 @@
+// Device code: sum-factorised element kernels for the residual, the linearisation update and the
+// linearised operator of finite-strain hyperelasticity (material configuration).
+//
+// Thread layout. A workgroup processes EB cells; it has EB * (p+1)^3 threads, one per Gauss
+// point of each cell ("q-threads"). The tensor-product contractions run as pencil jobs: a job
+// owns one 1D line of one field of one cell, keeps it in registers and applies a 1D matrix whose
+// coefficients are uniform across the wavefront (scalar registers). Jobs are spread over all
+// threads of the workgroup; fields live in LDS between the sweeps. The q-point physics runs one
+// q-point per thread with everything in registers.
+//
+// Interpolation (Section 6: sum factorisation): values at Gauss points v = (B x B x B) u, then
+// reference derivatives g_d = D_d v with the collocation derivative D on the Gauss points. The
+// transposed sequence integrates the test-function gradients: s = sum_d D_d^T t_d, out =
+// (B^T x B^T x B^T) s. Cost per field: 6 sweeps of n^4 fused multiply-adds.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "hx_internal.hpp"
+
+namespace hx {
+
+// ------------------------------------------------------------------------------------------
+// Storage element types
+// ------------------------------------------------------------------------------------------
+struct bf16_t {
+  uint16_t v;
+};
+
+__device__ __forceinline__ double load_val(const double* p) { return *p; }
+__device__ __forceinline__ float load_val(const float* p) { return *p; }
+__device__ __forceinline__ float load_val(const bf16_t* p) {
+  return __uint_as_float(static_cast<uint32_t>(p->v) << 16);
+}
+__device__ __forceinline__ float load_val(const _Float16* p) { return static_cast<float>(*p); }
+
+__device__ __forceinline__ void store_val(double* p, double v) { *p = v; }
+__device__ __forceinline__ void store_val(float* p, double v) { *p = static_cast<float>(v); }
+__device__ __forceinline__ void store_val(bf16_t* p, double v) {
+  // round to nearest even from the float value (NaN kept quiet)
+  uint32_t u = __float_as_uint(static_cast<float>(v));
+  if ((u & 0x7fffffffu) > 0x7f800000u) {
+    p->v = static_cast<uint16_t>((u >> 16) | 0x40u);
+    return;
+  }
+  u += 0x7fffu + ((u >> 16) & 1u);
+  p->v = static_cast<uint16_t>(u >> 16);
+}
+__device__ __forceinline__ void store_val(_Float16* p, double v) {
+  *p = static_cast<_Float16>(static_cast<float>(v));
+}
+
+template <int S> struct StoreOf;
+template <> struct StoreOf<kStoreF64> { using T = double; };
+template <> struct StoreOf<kStoreF32> { using T = float; };
+template <> struct StoreOf<kStoreBF16> { using T = bf16_t; };
+template <> struct StoreOf<kStoreF16> { using T = _Float16; };
+
+// ------------------------------------------------------------------------------------------
+// Scalar math, per arithmetic type
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ double m_log1p(double x) { return log1p(x); }
+__device__ __forceinline__ float m_log1p(float x) { return log1pf(x); }
+__device__ __forceinline__ double m_exp(double x) { return exp(x); }
+// FP32: the hardware base-2 exponential after scaling by log2(e)
+__device__ __forceinline__ float m_exp(float x) { return __expf(x); }
+
+// J^(-2/3): FP64 by the cube root; FP32 by Newton steps on f(x) = x^-3 - J^2 from x0 = 1
+// (Algorithm 2, Section 4) when iters > 0.
+__device__ __forceinline__ double jpow(double Jm, int) {
+  const double c = cbrt(1.0 + Jm);
+  return 1.0 / (c * c);
+}
+__device__ __forceinline__ float jpow(float Jm, int iters) {
+  if (iters > 0) {
+    const float alpha = ((Jm + 2.0f) * Jm + 1.0f) * (1.0f / 3.0f);  // J^2 / 3
+    float beta = (4.0f / 3.0f) - alpha;                            // first step from x0 = 1
+    for (int n = 1; n < iters; ++n) {
+      const float b2 = beta * beta;
+      beta = (4.0f / 3.0f) * beta - alpha * (b2 * b2);
+    }
+    return beta;
+  }
+  const float c = cbrtf(1.0f + Jm);
+  return 1.0f / (c * c);
+}
+
+// ------------------------------------------------------------------------------------------
+// 3x3 tensors, row-major A[3*i + j]
+// ------------------------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ R det3(const R* A) {
+  return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+         A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+
+// adjugate (transpose of the cofactor matrix): A^-1 = adj(A) / det(A)
+template <typename R>
+__device__ __forceinline__ void adj3(const R* A, R* C) {
+  C[0] = A[4] * A[8] - A[5] * A[7];
+  C[1] = A[2] * A[7] - A[1] * A[8];
+  C[2] = A[1] * A[5] - A[2] * A[4];
+  C[3] = A[5] * A[6] - A[3] * A[8];
+  C[4] = A[0] * A[8] - A[2] * A[6];
+  C[5] = A[2] * A[3] - A[0] * A[5];
+  C[6] = A[3] * A[7] - A[4] * A[6];
+  C[7] = A[1] * A[6] - A[0] * A[7];
+  C[8] = A[0] * A[4] - A[1] * A[3];
+}
+
+// H[c][J] = sum_d g[c][d] K[d][J]  (reference -> physical gradient, K = J0^-1)
+template <typename R>
+__device__ __forceinline__ void to_physical(const R* g, const R* K, R* H) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int J = 0; J < 3; ++J)
+      H[3 * c + J] = g[3 * c] * K[J] + g[3 * c + 1] * K[3 + J] + g[3 * c + 2] * K[6 + J];
+}
+
+// t[c][d] = w sum_J P[c][J] K[d][J]  (stress -> test coefficients on reference gradients)
+template <typename R>
+__device__ __forceinline__ void to_reference(const R* P, const R* K, R w, R* t) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      t[3 * c + d] =
+          w * (P[3 * c] * K[3 * d] + P[3 * c + 1] * K[3 * d + 1] + P[3 * c + 2] * K[3 * d + 2]);
+}
+
+// Trilinear geometry at reference point (s, t, r): K = J0^-1, returns det J0.
+// X[3*v + c] is coordinate c of vertex v = a + 2b + 4c'.
+template <typename R>
+__device__ __forceinline__ R trilinear_geometry(const R* X, R s, R t, R r, R* K) {
+  R J[9];
+  const R s1 = R(1) - s, t1 = R(1) - t, r1 = R(1) - r;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    J[3 * c + 0] = t1 * r1 * (X[3 + c] - X[c]) + t * r1 * (X[9 + c] - X[6 + c]) +
+                   t1 * r * (X[15 + c] - X[12 + c]) + t * r * (X[21 + c] - X[18 + c]);
+    J[3 * c + 1] = s1 * r1 * (X[6 + c] - X[c]) + s * r1 * (X[9 + c] - X[3 + c]) +
+                   s1 * r * (X[18 + c] - X[12 + c]) + s * r * (X[21 + c] - X[15 + c]);
+    J[3 * c + 2] = s1 * t1 * (X[12 + c] - X[c]) + s * t1 * (X[15 + c] - X[3 + c]) +
+                   s1 * t * (X[18 + c] - X[6 + c]) + s * t * (X[21 + c] - X[9 + c]);
+  }
+  R A[9];
+  adj3(J, A);
+  const R det = J[0] * A[0] + J[1] * A[3] + J[2] * A[6];
+  const R inv = R(1) / det;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) K[i] = A[i] * inv;
+  return det;
+}
+
+// ------------------------------------------------------------------------------------------
+// Constitutive laws (Sections 3-5), material configuration, stable forms.
+// ------------------------------------------------------------------------------------------
+enum : int { kCNH = 0, kINH = 1, kFIBER = 2 };
+
+template <typename R>
+struct QState {
+  R F[9], Fi[9];
+  R Jm, lnJ, Jp, c1, c2;
+  R c3[2], Ei[2], dfac[2];
+};
+
+template <int LAW, typename R>
+__device__ __forceinline__ void fiber_scalars(const MaterialK<R>& m, const R* Hf, const R* M,
+                                              R Ei, R ImOne, int f, QState<R>& s) {
+  // c3 = 2 k1 exp(k2 E_i^2) if I*_i > 1 (strict), else 0  (fibre model, c3 definition)
+  const bool active = ImOne > R(0);
+  const R e2 = Ei * Ei;
+  s.Ei[f] = Ei;
+  s.c3[f] = active ? R(2) * m.k1 * m_exp(m.k2 * e2) : R(0);
+  s.dfac[f] = R(2) * m.k2 * e2 + R(1);
+}
+
+// State from the displacement gradient H = Grad u (stable forms of Section 4):
+// E = (H + H^T + H^T H)/2, J - 1 from the invariants of H, C^-1 via F^-1.
+// Returns false when J <= 0. E is written to Eout (for the residual).
+template <int LAW, typename R>
+__device__ __forceinline__ bool state_from_H(const R* H, const MaterialK<R>& m, QState<R>& s,
+                                             R* E) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) s.F[i] = H[i];
+  s.F[0] += R(1);
+  s.F[4] += R(1);
+  s.F[8] += R(1);
+  const R trH = H[0] + H[4] + H[8];
+  const R I2 = H[0] * H[4] + H[0] * H[8] + H[4] * H[8] - H[1] * H[3] - H[2] * H[6] - H[5] * H[7];
+  const R I3 = det3(H);
+  s.Jm = I3 + I2 + trH;  // det(I + H) - 1 = I1(H) + I2(H) + I3(H)
+  const R J = R(1) + s.Jm;
+  R A[9];
+  adj3(s.F, A);
+  const R invJ = R(1) / J;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) s.Fi[i] = A[i] * invJ;
+  // E = (H + H^T + H^T H) / 2
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      E[3 * i + j] = R(0.5) * (H[3 * i + j] + H[3 * j + i] + H[i] * H[j] + H[3 + i] * H[3 + j] +
+                               H[6 + i] * H[6 + j]);
+  if constexpr (LAW == kCNH) {
+    s.lnJ = m_log1p(s.Jm);
+  } else {
+    s.Jp = jpow(s.Jm, m.jpow_iters);
+    const R I1 = R(3) + R(2) * (E[0] + E[4] + E[8]);
+    s.c1 = R(0.5) * m.kappa * s.Jm * (s.Jm + R(2)) - m.mu / R(3) * s.Jp * I1;
+    s.c2 = R(2) * m.mu / R(9) * s.Jp * I1 + m.kappa * J * J;
+    if constexpr (LAW == kFIBER) {
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        const R* Hf = f == 0 ? m.H4 : m.H6;
+        const R* M = f == 0 ? m.M4 : m.M6;
+        R Ei = R(0), mem = R(0);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Ei += Hf[i] * E[i];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) mem += M[i] * E[3 * i + j] * M[j];
+        // E_i = 2 H_i : E,  I*_i - 1 = 2 (M (x) M) : E
+        fiber_scalars<LAW>(m, Hf, M, R(2) * Ei, R(2) * mem, f, s);
+      }
+    }
+  }
+  return J > R(0);
+}
+
+// State from stored F^-1 and J - 1: F = J adj(F^-1).
+template <int LAW, typename R>
+__device__ __forceinline__ void state_from_finv(const R* Fi, R Jm, const MaterialK<R>& m,
+                                                QState<R>& s) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) s.Fi[i] = Fi[i];
+  s.Jm = Jm;
+  if constexpr (LAW == kCNH) {
+    s.lnJ = m_log1p(Jm);
+  } else {
+    const R J = R(1) + Jm;
+    R A[9];
+    adj3(Fi, A);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) s.F[i] = A[i] * J;
+    s.Jp = jpow(Jm, m.jpow_iters);
+    R I1 = R(0);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) I1 += s.F[i] * s.F[i];
+    s.c1 = R(0.5) * m.kappa * Jm * (Jm + R(2)) - m.mu / R(3) * s.Jp * I1;
+    s.c2 = R(2) * m.mu / R(9) * s.Jp * I1 + m.kappa * J * J;
+    if constexpr (LAW == kFIBER) {
+      R C[9];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          C[3 * i + j] = s.F[i] * s.F[j] + s.F[3 + i] * s.F[3 + j] + s.F[6 + i] * s.F[6 + j];
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        const R* Hf = f == 0 ? m.H4 : m.H6;
+        const R* M = f == 0 ? m.M4 : m.M6;
+        R Ei = -(Hf[0] + Hf[4] + Hf[8]), mcm = R(0);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Ei += Hf[i] * C[i];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) mcm += M[i] * C[3 * i + j] * M[j];
+        fiber_scalars<LAW>(m, Hf, M, Ei, mcm - R(1), f, s);
+      }
+    }
+  }
+}
+
+// First Piola-Kirchhoff stress P = F S, stable forms:
+//   cNH  P = F^-T (2 mu E + 2 lambda ln J I)
+//   iNH  P = F^-T [kappa/2 (J-1)(J+1) I + 2 mu J^-2/3 (E - tr E / 3 I)]
+//   fibre adds sum_i c3 E_i F H_i
+template <int LAW, typename R>
+__device__ __forceinline__ void stress_P(const QState<R>& s, const R* E, const MaterialK<R>& m,
+                                         R* P) {
+  R Sv[9];
+  if constexpr (LAW == kCNH) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Sv[i] = R(2) * m.mu * E[i];
+    const R d = R(2) * m.lam * s.lnJ;
+    Sv[0] += d;
+    Sv[4] += d;
+    Sv[8] += d;
+  } else {
+    const R trE3 = (E[0] + E[4] + E[8]) / R(3);
+    const R a = R(2) * m.mu * s.Jp;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Sv[i] = a * E[i];
+    const R d = R(0.5) * m.kappa * s.Jm * (s.Jm + R(2)) - a * trE3;
+    Sv[0] += d;
+    Sv[4] += d;
+    Sv[8] += d;
+  }
+  // P = F^-T Sv
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      P[3 * i + j] = s.Fi[i] * Sv[j] + s.Fi[3 + i] * Sv[3 + j] + s.Fi[6 + i] * Sv[6 + j];
+  if constexpr (LAW == kFIBER) {
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      const R* Hf = f == 0 ? m.H4 : m.H6;
+      const R c = s.c3[f] * s.Ei[f];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          P[3 * i + j] += c * (s.F[3 * i] * Hf[j] + s.F[3 * i + 1] * Hf[3 + j] +
+                               s.F[3 * i + 2] * Hf[6 + j]);
+    }
+  }
+}
+
+// Linearised stress P' = Grad du S + F D_u S (Section 5 forms, with the c1 sign of the appendix
+// derivation), rearranged using F C^-1 = F^-T and S = mu I - a C^-1 (cNH) or
+// S = mu J^-2/3 I + c1 C^-1 (iNH) so that no S needs forming:
+//   cNH  P' = mu G + a F^-T G^T F^-T + 2 lambda tr(F^-1 G) F^-T,  a = mu - 2 lambda ln J
+//   iNH  P' = mu Jp G - c1 F^-T G^T F^-T - 2mu/3 Jp tr(F^-1 G) F
+//             + (c2 tr(F^-1 G) - 2mu/3 Jp F:G) F^-T
+//   fibre adds sum_i c3 [E_i G H_i + 2 (2 k2 E_i^2 + 1) ((F H_i):G) F H_i]
+template <int LAW, typename R>
+__device__ __forceinline__ void action(const QState<R>& s, const MaterialK<R>& m, const R* G,
+                                       R* Pd) {
+  // X = (F^-1 G)^T, Y = F^-T X = F^-T G^T F^-T, tr = tr(F^-1 G)
+  R X[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      X[3 * i + j] = s.Fi[3 * j] * G[i] + s.Fi[3 * j + 1] * G[3 + i] + s.Fi[3 * j + 2] * G[6 + i];
+  const R tr = X[0] + X[4] + X[8];
+  R Y[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      Y[3 * i + j] = s.Fi[i] * X[j] + s.Fi[3 + i] * X[3 + j] + s.Fi[6 + i] * X[6 + j];
+  if constexpr (LAW == kCNH) {
+    const R a = m.mu - R(2) * m.lam * s.lnJ;
+    const R b = R(2) * m.lam * tr;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        Pd[3 * i + j] = m.mu * G[3 * i + j] + a * Y[3 * i + j] + b * s.Fi[3 * j + i];
+  } else {
+    R FG = R(0);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) FG += s.F[i] * G[i];
+    const R a = m.mu * s.Jp;
+    const R b = R(2) / R(3) * a * tr;
+    const R c = s.c2 * tr - R(2) / R(3) * a * FG;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        Pd[3 * i + j] = a * G[3 * i + j] - s.c1 * Y[3 * i + j] - b * s.F[3 * i + j] +
+                        c * s.Fi[3 * j + i];
+    if constexpr (LAW == kFIBER) {
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        const R* Hf = f == 0 ? m.H4 : m.H6;
+        R FH[9], GH[9];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            FH[3 * i + j] = s.F[3 * i] * Hf[j] + s.F[3 * i + 1] * Hf[3 + j] +
+                            s.F[3 * i + 2] * Hf[6 + j];
+            GH[3 * i + j] =
+                G[3 * i] * Hf[j] + G[3 * i + 1] * Hf[3 + j] + G[3 * i + 2] * Hf[6 + j];
+          }
+        R fhg = R(0);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) fhg += FH[i] * G[i];
+        const R ce = s.c3[f] * s.Ei[f];
+        const R cf = R(2) * s.c3[f] * s.dfac[f] * fhg;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Pd[i] += ce * GH[i] + cf * FH[i];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Lattice addressing
+// ------------------------------------------------------------------------------------------
+struct CellPos {
+  int ex, ey, ez;
+};
+
+__device__ __forceinline__ CellPos cell_pos(const Lattice& L, int e) {
+  CellPos c;
+  c.ex = e % L.nx;
+  const int r = e / L.nx;
+  c.ey = r % L.ny;
+  c.ez = r / L.ny;
+  return c;
+}
+
+// node index and constraint flag of local node (i, j, k)
+__device__ __forceinline__ int64_t node_of(const Lattice& L, const CellPos& c, int i, int j, int k,
+                                           bool& cons) {
+  int I = c.ex * L.p + i, J = c.ey * L.p + j, K = c.ez * L.p + k;
+  I = I >= L.Nx ? I - L.Nx : I;
+  J = J >= L.Ny ? J - L.Ny : J;
+  K = K >= L.Nz ? K - L.Nz : K;
+  const uint32_t f = L.dir_faces;
+  cons = ((f & 1u) && I == 0) || ((f & 2u) && I == L.Nx - 1) || ((f & 4u) && J == 0) ||
+         ((f & 8u) && J == L.Ny - 1) || ((f & 16u) && K == 0) || ((f & 32u) && K == L.Nz - 1);
+  return static_cast<int64_t>(I) + static_cast<int64_t>(L.Nx) * (J + static_cast<int64_t>(L.Ny) * K);
+}
+
+// ------------------------------------------------------------------------------------------
+// Pencil machinery
+// ------------------------------------------------------------------------------------------
+// index of point m on pencil (a, b) along direction DIR in an N^3 block (x fastest)
+template <int N, int DIR>
+__device__ __forceinline__ int pidx(int a, int b, int m) {
+  if constexpr (DIR == 0) return m + N * a + N * N * b;
+  else if constexpr (DIR == 1) return a + N * m + N * N * b;
+  else return a + N * b + N * N * m;
+}
+
+// out = M in (TR: M^T in), M row-major N x N with wave-uniform coefficients
+template <int N, bool TR, typename R>
+__device__ __forceinline__ void apply1d(const R* M, const R* in, R* out) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    R acc = R(0);
+#pragma unroll
+    for (int m = 0; m < N; ++m) acc = fma(TR ? M[m * N + i] : M[i * N + m], in[m], acc);
+    out[i] = acc;
+  }
+}
+
+// Runs fn(le, set, a, b) for every pencil of NSETS fields of EB cells, spread over the
+// workgroup's threads.
+template <int N, int EB, int NSETS, typename Fn>
+__device__ __forceinline__ void pencil_jobs(Fn&& fn) {
+  constexpr int N2 = N * N;
+  constexpr int NT = EB * N * N * N;
+  constexpr int PER = NSETS * N2;
+  for (int job = threadIdx.x; job < EB * PER; job += NT) {
+    const int le = job / PER;
+    const int r = job - le * PER;
+    const int set = r / N2;
+    const int pl = r - set * N2;
+    fn(le, set, pl % N, pl / N);
+  }
+}
+
+// Forward pass for one 3-component vector V: writes the 9 reference derivatives at this
+// thread's q-point into g[c*3 + d]. Uses LDS buffers 0..8 of each cell (9 * N^3 values).
+template <int N, int EB, bool MASK, typename R>
+__device__ __forceinline__ void forward_vector(const KernelArgs<N, R>& a, R* sb, const R* V,
+                                               int e0, int le_me, int q_me, R* g) {
+  constexpr int Q = N * N * N;
+  constexpr int CB = 9 * Q;  // per-cell stride in LDS
+  const Lattice& L = a.L;
+  // F1: gather x-pencils from global memory, interpolate along x
+  pencil_jobs<N, EB, 3>([&](int le, int c, int j, int k) __attribute__((always_inline)) {
+    R in[N], out[N];
+    const int e = e0 + le;
+    if (e < L.n_cells) {
+      const CellPos cp = cell_pos(L, e);
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        bool cons;
+        const int64_t node = node_of(L, cp, i, j, k, cons);
+        const R v = V[c * L.n_nodes + node];
+        in[i] = (MASK && cons) ? R(0) : v;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < N; ++i) in[i] = R(0);
+    }
+    apply1d<N, false>(a.c->b.B, in, out);
+    R* buf = sb + le * CB + c * Q;
+#pragma unroll
+    for (int i = 0; i < N; ++i) buf[pidx<N, 0>(j, k, i)] = out[i];
+  });
+  __syncthreads();
+  // F2: interpolate along y
+  pencil_jobs<N, EB, 3>([&](int le, int c, int i, int k) __attribute__((always_inline)) {
+    R in[N], out[N];
+    R* buf = sb + le * CB + c * Q;
+#pragma unroll
+    for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 1>(i, k, m)];
+    apply1d<N, false>(a.c->b.B, in, out);
+#pragma unroll
+    for (int m = 0; m < N; ++m) buf[pidx<N, 1>(i, k, m)] = out[m];
+  });
+  __syncthreads();
+  // F3: interpolate along z (values at Gauss points) and differentiate along z
+  pencil_jobs<N, EB, 3>([&](int le, int c, int i, int j) __attribute__((always_inline)) {
+    R in[N], v[N], d[N];
+    R* buf = sb + le * CB + c * Q;
+    R* bz = sb + le * CB + (6 + c) * Q;
+#pragma unroll
+    for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 2>(i, j, m)];
+    apply1d<N, false>(a.c->b.B, in, v);
+    apply1d<N, false>(a.c->b.D, v, d);
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      buf[pidx<N, 2>(i, j, m)] = v[m];
+      bz[pidx<N, 2>(i, j, m)] = d[m];
+    }
+  });
+  __syncthreads();
+  // F4: differentiate along x into buffer 3 + c
+  pencil_jobs<N, EB, 3>([&](int le, int c, int j, int k) __attribute__((always_inline)) {
+    R in[N], d[N];
+    const R* buf = sb + le * CB + c * Q;
+    R* bx = sb + le * CB + (3 + c) * Q;
+#pragma unroll
+    for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 0>(j, k, m)];
+    apply1d<N, false>(a.c->b.D, in, d);
+#pragma unroll
+    for (int m = 0; m < N; ++m) bx[pidx<N, 0>(j, k, m)] = d[m];
+  });
+  __syncthreads();
+  // F5: differentiate along y in place
+  pencil_jobs<N, EB, 3>([&](int le, int c, int i, int k) __attribute__((always_inline)) {
+    R in[N], d[N];
+    R* buf = sb + le * CB + c * Q;
+#pragma unroll
+    for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 1>(i, k, m)];
+    apply1d<N, false>(a.c->b.D, in, d);
+#pragma unroll
+    for (int m = 0; m < N; ++m) buf[pidx<N, 1>(i, k, m)] = d[m];
+  });
+  __syncthreads();
+  // F6: this thread's q-point
+  const R* cb = sb + le_me * CB;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    g[3 * c + 0] = cb[(3 + c) * Q + q_me];
+    g[3 * c + 1] = cb[c * Q + q_me];
+    g[3 * c + 2] = cb[(6 + c) * Q + q_me];
+  }
+}
+
+// Backward pass: integrates the test coefficients t[c*3 + d] of every q-thread against the
+// reference gradients of the basis and adds the element vectors into a.out.
+// Element-interior nodes belong to one cell only and are stored; shared nodes use atomics.
+template <int N, int EB, typename R>
+__device__ __forceinline__ void backward_scatter(const KernelArgs<N, R>& a, R* sb, int e0,
+                                                 int le_me, int q_me, const R* t) {
+  constexpr int Q = N * N * N;
+  constexpr int CB = 9 * Q;
+  const Lattice& L = a.L;
+  __syncthreads();  // buffers may still be read by the forward pass
+  {
+    R* cb = sb + le_me * CB;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) cb[i * Q + q_me] = t[i];
+  }
+  __syncthreads();
+  // B2: D^T along x on t[c][0], D^T along y on t[c][1]
+  pencil_jobs<N, EB, 6>([&](int le, int set, int a1, int b1) __attribute__((always_inline)) {
+    const int c = set >> 1;
+    R in[N], out[N];
+    if ((set & 1) == 0) {
+      R* buf = sb + le * CB + (3 * c) * Q;
+#pragma unroll
+      for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 0>(a1, b1, m)];
+      apply1d<N, true>(a.c->b.D, in, out);
+#pragma unroll
+      for (int m = 0; m < N; ++m) buf[pidx<N, 0>(a1, b1, m)] = out[m];
+    } else {
+      R* buf = sb + le * CB + (3 * c + 1) * Q;
+#pragma unroll
+      for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 1>(a1, b1, m)];
+      apply1d<N, true>(a.c->b.D, in, out);
+#pragma unroll
+      for (int m = 0; m < N; ++m) buf[pidx<N, 1>(a1, b1, m)] = out[m];
+    }
+  });
+  __syncthreads();
+  // B3: along z: s = tx' + ty' + D^T tz, then B^T
+  pencil_jobs<N, EB, 3>([&](int le, int c, int i, int j) __attribute__((always_inline)) {
+    R tz[N], s[N], out[N];
+    R* bx = sb + le * CB + (3 * c) * Q;
+    const R* by = sb + le * CB + (3 * c + 1) * Q;
+    const R* bzp = sb + le * CB + (3 * c + 2) * Q;
+#pragma unroll
+    for (int m = 0; m < N; ++m) tz[m] = bzp[pidx<N, 2>(i, j, m)];
+    apply1d<N, true>(a.c->b.D, tz, s);
+#pragma unroll
+    for (int m = 0; m < N; ++m) s[m] += bx[pidx<N, 2>(i, j, m)] + by[pidx<N, 2>(i, j, m)];
+    apply1d<N, true>(a.c->b.B, s, out);
+#pragma unroll
+    for (int m = 0; m < N; ++m) bx[pidx<N, 2>(i, j, m)] = out[m];
+  });
+  __syncthreads();
+  // B4: B^T along y
+  pencil_jobs<N, EB, 3>([&](int le, int c, int i, int k) __attribute__((always_inline)) {
+    R in[N], out[N];
+    R* buf = sb + le * CB + (3 * c) * Q;
+#pragma unroll
+    for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 1>(i, k, m)];
+    apply1d<N, true>(a.c->b.B, in, out);
+#pragma unroll
+    for (int m = 0; m < N; ++m) buf[pidx<N, 1>(i, k, m)] = out[m];
+  });
+  __syncthreads();
+  // B5: B^T along x and scatter
+  constexpr int P = N - 1;
+  pencil_jobs<N, EB, 3>([&](int le, int c, int j, int k) __attribute__((always_inline)) {
+    const int e = e0 + le;
+    if (e >= L.n_cells) return;
+    R in[N], out[N];
+    const R* buf = sb + le * CB + (3 * c) * Q;
+#pragma unroll
+    for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 0>(j, k, m)];
+    apply1d<N, true>(a.c->b.B, in, out);
+    const CellPos cp = cell_pos(L, e);
+    const bool inner_jk = j > 0 && j < P && k > 0 && k < P;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      bool cons;
+      const int64_t node = node_of(L, cp, i, j, k, cons);
+      if (cons) continue;
+      R* dst = a.out + c * L.n_nodes + node;
+      if (inner_jk && i > 0 && i < P)
+        *dst = out[i];
+      else
+        unsafeAtomicAdd(dst, out[i]);
+    }
+  });
+}
+
+// ------------------------------------------------------------------------------------------
+// Operations (what happens at the q-point)
+// ------------------------------------------------------------------------------------------
+// Geometry of this q-point from the cell's vertices in LDS.
+// arr[idx] for a lane-dependent idx without dynamic indexing of kernel arguments (which would
+// force a private copy of the argument block)
+template <int N, typename R>
+__device__ __forceinline__ R pick(const R* arr, int idx) {
+  R v = arr[0];
+#pragma unroll
+  for (int i = 1; i < N; ++i) v = idx == i ? arr[i] : v;
+  return v;
+}
+
+template <int N, typename R>
+__device__ __forceinline__ R qpoint_geometry(const KernelArgs<N, R>& a, const R* X, int q, R* K) {
+  const int qx = q % N, qy = (q / N) % N, qz = q / (N * N);
+  const R det = trilinear_geometry(X, pick<N>(a.c->b.x, qx), pick<N>(a.c->b.x, qy), pick<N>(a.c->b.x, qz), K);
+  return det * (pick<N>(a.c->b.w, qx) * pick<N>(a.c->b.w, qy) * pick<N>(a.c->b.w, qz));
+}
+
+template <int N, int EB, typename R>
+__device__ __forceinline__ void load_vertices(const KernelArgs<N, R>& a, R* sv, int e0) {
+  // 24 values per cell (8 vertices x 3 coordinates), spread over the workgroup
+  constexpr int NT = EB * N * N * N;
+  for (int idx = threadIdx.x; idx < EB * 24; idx += NT) {
+    const int le = idx / 24, q = idx - 24 * le;
+    const int e = e0 + le;
+    if (e >= a.L.n_cells) continue;
+    const CellPos cp = cell_pos(a.L, e);
+    const int v = q / 3, comp = q - 3 * v;
+    int vx = cp.ex + (v & 1), vy = cp.ey + ((v >> 1) & 1), vz = cp.ez + (v >> 2);
+    vx = vx >= a.L.Vx ? vx - a.L.Vx : vx;
+    vy = vy >= a.L.Vy ? vy - a.L.Vy : vy;
+    vz = vz >= a.L.Vz ? vz - a.L.Vz : vz;
+    const int64_t vid = vx + static_cast<int64_t>(a.L.Vx) * (vy + static_cast<int64_t>(a.L.Vy) * vz);
+    sv[le * 24 + q] = a.vert[3 * vid + comp];
+  }
+}
+
+// Kernel: ops = residual, apply (three storage modes) and update (three storage modes).
+//   KIND 0 apply, 1 residual, 2 update; MODE = hx_storage; S = StoreType; LAW
+template <int N, int EB, typename R, int KIND, int MODE, int LAW, int S>
+__global__ void __launch_bounds__(EB * N * N * N)
+    element_kernel(KernelArgs<N, R> a) {
+  constexpr int Q = N * N * N;
+  using ST = typename StoreOf<S>::T;
+  __shared__ R sb[EB * 9 * Q];
+  __shared__ R sv[EB * 24];
+  __shared__ float sred[EB];
+  const int le = threadIdx.x / Q;
+  const int q = threadIdx.x - le * Q;
+  const int e0 = blockIdx.x * EB;
+  const int e = e0 + le;
+  const bool valid = e < a.L.n_cells;
+  const int64_t qi = static_cast<int64_t>(e) * Q + q;
+
+  constexpr bool kGeom = !(KIND == 0 && MODE == HX_STORE_TANGENT);
+  if constexpr (kGeom) load_vertices<N, EB>(a, sv, e0);
+  if constexpr (KIND == 2 && S == kStoreF16) {
+    if (q == 0) sred[le] = 0.0f;
+  }
+
+  R g0[9], g1[9], t[9];
+  if constexpr (KIND == 0 && MODE == HX_STORE_NONE) {
+    // linearisation point first (not masked), then the direction (masked)
+    forward_vector<N, EB, false>(a, sb, a.in1, e0, le, q, g1);
+    __syncthreads();
+    forward_vector<N, EB, true>(a, sb, a.in0, e0, le, q, g0);
+  } else if constexpr (KIND == 0) {
+    forward_vector<N, EB, true>(a, sb, a.in0, e0, le, q, g0);
+  } else {
+    forward_vector<N, EB, false>(a, sb, a.in0, e0, le, q, g0);
+  }
+
+  const MaterialK<R>& m = a.c->m;
+  if constexpr (KIND == 0 && MODE == HX_STORE_TANGENT) {
+    // t = D g with the stored symmetric 9x9 tangent (45 planes, upper triangle row by row)
+    const ST* qd = static_cast<const ST*>(a.qdata);
+    R Dv[45];
+    if (valid) {
+#pragma unroll
+      for (int w = 0; w < 45; ++w) Dv[w] = static_cast<R>(load_val(qd + w * a.qstride + qi));
+    } else {
+#pragma unroll
+      for (int w = 0; w < 45; ++w) Dv[w] = R(0);
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) t[i] = R(0);
+    int w = 0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      t[i] += Dv[w] * g0[i];
+      ++w;
+#pragma unroll
+      for (int j = i + 1; j < 9; ++j) {
+        t[i] += Dv[w] * g0[j];
+        t[j] += Dv[w] * g0[i];
+        ++w;
+      }
+    }
+    if constexpr (S == kStoreF16) {
+      if (valid) {
+        const R inv = R(1) / static_cast<R>(a.cscale[e]);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) t[i] *= inv;
+      }
+    }
+  } else if constexpr (KIND == 0) {
+    R K[9];
+    const R wdet = valid ? qpoint_geometry(a, sv + le * 24, q, K) : R(0);
+    QState<R> st;
+    if constexpr (MODE == HX_STORE_NONE) {
+      R H[9], E[9];
+      to_physical(g1, K, H);
+      state_from_H<LAW>(H, m, st, E);
+    } else {
+      const ST* qd = static_cast<const ST*>(a.qdata);
+      R Fi[9], Jm;
+      if (valid) {
+#pragma unroll
+        for (int w = 0; w < 9; ++w) Fi[w] = static_cast<R>(load_val(qd + w * a.qstride + qi));
+        Jm = static_cast<R>(load_val(qd + 9 * a.qstride + qi));
+      } else {
+#pragma unroll
+        for (int w = 0; w < 9; ++w) Fi[w] = R(w % 4 == 0);
+        Jm = R(0);
+      }
+      state_from_finv<LAW>(Fi, Jm, m, st);
+    }
+    R G[9], Pd[9];
+    to_physical(g0, K, G);
+    action<LAW>(st, m, G, Pd);
+    to_reference(Pd, K, wdet, t);
+  } else if constexpr (KIND == 1) {
+    R K[9], H[9], E[9], P[9];
+    const R wdet = valid ? qpoint_geometry(a, sv + le * 24, q, K) : R(0);
+    to_physical(g0, K, H);
+    QState<R> st;
+    state_from_H<LAW>(H, m, st, E);
+    stress_P<LAW>(st, E, m, P);
+    to_reference(P, K, wdet, t);
+  } else {
+    // linearisation update (always FP64 arithmetic)
+    R K[9], H[9], E[9];
+    const R wdet = valid ? qpoint_geometry(a, sv + le * 24, q, K) : R(0);
+    to_physical(g0, K, H);
+    QState<R> st;
+    const bool ok = state_from_H<LAW>(H, m, st, E);
+    int bad = 0;
+    if (valid && !ok) bad |= kFlagInverted;
+    ST* qw = static_cast<ST*>(a.qdata_w);
+    if constexpr (MODE == HX_STORE_FINV_J) {
+      R chk = st.Jm;
+#pragma unroll
+      for (int w = 0; w < 9; ++w) chk += st.Fi[w];
+      if (valid && !isfinite(chk)) bad |= kFlagNonFinite;
+      if (valid) {
+#pragma unroll
+        for (int w = 0; w < 9; ++w) store_val(qw + w * a.qstride + qi, st.Fi[w]);
+        store_val(qw + 9 * a.qstride + qi, st.Jm);
+      }
+    } else if constexpr (MODE == HX_STORE_TANGENT) {
+      // columns of the reference tangent: unit reference gradient e_k (x) e_b maps to the
+      // physical gradient G[k][J] = K[b][J]
+      R Dm[81];
+#pragma unroll
+      for (int col = 0; col < 9; ++col) {
+        const int kk = col / 3, bb = col % 3;
+        R G[9], Pd[9], tc[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) G[i] = R(0);
+#pragma unroll
+        for (int J = 0; J < 3; ++J) G[3 * kk + J] = K[3 * bb + J];
+        action<LAW>(st, m, G, Pd);
+        to_reference(Pd, K, wdet, tc);
+#pragma unroll
+        for (int r = 0; r < 9; ++r) Dm[9 * r + col] = tc[r];
+      }
+      R Dsym[45];
+      int w = 0;
+      R chk = R(0), amax = R(0);
+#pragma unroll
+      for (int i = 0; i < 9; ++i)
+#pragma unroll
+        for (int j = i; j < 9; ++j) {
+          Dsym[w] = R(0.5) * (Dm[9 * i + j] + Dm[9 * j + i]);
+          chk += Dsym[w];
+          amax = fmax(amax, fabs(Dsym[w]));
+          ++w;
+        }
+      if (valid && !isfinite(chk)) bad |= kFlagNonFinite;
+      R scale = R(1);
+      if constexpr (S == kStoreF16) {
+        // per-cell power-of-two scale: largest magnitude maps below 2^14
+        if (valid && isfinite(amax)) atomicMax(reinterpret_cast<unsigned*>(&sred[le]),
+                                               __float_as_uint(static_cast<float>(amax)));
+        __syncthreads();
+        const float cm = sred[le];
+        int ex2 = 0;
+        if (cm > 0.0f) frexpf(cm, &ex2);
+        const float sc = ldexpf(1.0f, 14 - ex2);
+        scale = static_cast<R>(sc);
+        if (valid && q == 0) a.cscale_w[e] = sc;
+      }
+      if (valid) {
+#pragma unroll
+        for (int i = 0; i < 45; ++i) store_val(qw + i * a.qstride + qi, Dsym[i] * scale);
+      }
+    } else {
+      R chk = st.Jm;
+      if (valid && !isfinite(chk)) bad |= kFlagNonFinite;
+    }
+    if (bad) atomicOr(a.flag, bad);
+    return;
+  }
+  if constexpr (KIND != 2) {
+    if (!valid) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) t[i] = R(0);
+    }
+    backward_scatter<N, EB>(a, sb, e0, le, q, t);
+  }
+}
+
+}  // namespace hx

@@ -156,6 +156,24 @@ def fiber_fields(coords, seed_du=4, target=0.05):
     return u, du
 
 
+def tube_vertices(n_theta, n_wall, n_axial, r_in=1.0, wall=0.2, length=10.0, bend=1.0):
+    """Vertices of a curved tube, periodic in the first lattice direction: [n_wall+1][n_theta]... x fastest.
+
+    Lattice index 1 runs around the circumference (periodic, so n_theta vertices), index 2
+    through the wall from r_in to r_in + wall, index 3 along the centreline
+    x_c(s) = (bend sin(pi s / length), 0, s), s in [0, length]; each cross-section lies in the
+    x-y plane. The angle decreases with the first index so that the lattice frame
+    (circumferential, radial, axial) is right-handed.
+    """
+    th = -2.0 * np.pi * np.arange(n_theta) / n_theta
+    r = r_in + wall * np.arange(n_wall + 1) / n_wall
+    s = length * np.arange(n_axial + 1) / n_axial
+    S, Rr, Th = np.meshgrid(s, r, th, indexing="ij")
+    X = bend * np.sin(np.pi * S / length) + Rr * np.cos(Th)
+    Y = Rr * np.sin(Th)
+    return np.stack([X.ravel(), Y.ravel(), S.ravel()], axis=1)
+
+
 def random_direction(n_nodes, seed, mask=None):
     du = np.random.default_rng(seed).standard_normal((3, n_nodes))
     if mask is not None:
