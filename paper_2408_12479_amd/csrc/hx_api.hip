@@ -185,6 +185,18 @@ hipError_t dispatch(int p, const HostOp& op, const HostArgs& h, hipStream_t s, b
   }
 }
 
+int cells_per_block(int p) {
+  switch (p) {
+    case 1: return cells_per_block_p1();
+    case 2: return cells_per_block_p2();
+    case 3: return cells_per_block_p3();
+    case 4: return cells_per_block_p4();
+    case 5: return cells_per_block_p5();
+    case 6: return cells_per_block_p6();
+    default: return 1;
+  }
+}
+
 hipError_t write_consts(int p, const HostArgs& h) {
   switch (p) {
     case 1: return consts_p1(h);
@@ -546,7 +558,10 @@ hx_status hx_update_linearization(hx_ctx ctx, const double* u, hx_storage mode, 
   Slot& sl = ctx->slot[prec == HX_FP64 ? 0 : 1];
   const Lattice& L = ctx->L;
   const int64_t Q = static_cast<int64_t>(ctx->p + 1) * (ctx->p + 1) * (ctx->p + 1);
-  const size_t need = static_cast<size_t>(mode_words(mode)) * L.n_cells * Q * store_bytes(st);
+  // whole workgroup blocks of cells (the last one may be partly unused)
+  const int64_t eb = cells_per_block(ctx->p);
+  const int64_t padded_cells = (L.n_cells + eb - 1) / eb * eb;
+  const size_t need = static_cast<size_t>(mode_words(mode)) * padded_cells * Q * store_bytes(st);
   hipError_t e = hipStreamSynchronize(s);  // the slot's buffers may still be in use
   if (e != hipSuccess) return hip_fail(ctx, e, "hx_update_linearization: sync");
   if (sl.qbytes != need || (need && !sl.qdata)) {

@@ -75,7 +75,6 @@ KernelArgs<N, R> make_args(const HostArgs& h) {
   a.cscale = h.cscale;
   a.cscale_w = h.cscale_w;
   a.flag = h.flag;
-  a.qstride = static_cast<int64_t>(h.L.n_cells) * N * N * N;
   return a;
 }
 
@@ -146,6 +145,9 @@ hipError_t apply_tangent_mode(const HostOp& op, const HostArgs& h, hipStream_t s
 }
 
 }  // namespace
+
+// Cells per workgroup: the stored q-point data is laid out in blocks of this many cells.
+int HX_CAT(cells_per_block_p, HX_DEGREE)() { return Blocking<N>::EB; }
 
 // Writes the constant blocks of a context (synchronous; called once at setup).
 hipError_t HX_CAT(consts_p, HX_DEGREE)(const HostArgs& h) {

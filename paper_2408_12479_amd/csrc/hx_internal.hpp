@@ -61,12 +61,11 @@ struct KernelArgs {
   const R* in0;         // gathered vector (du, or u for residual/update)
   const R* in1;         // linearisation point u_k (recompute mode)
   R* out;               // output vector (apply, residual)
-  const void* qdata;    // stored per-q-point planes [W][n_cells*Q]
+  const void* qdata;    // stored per-q-point planes [block][W][cells_per_block * Q]
   void* qdata_w;        // planes written by the update
   const float* cscale;  // per-cell power-of-two scale of binary16 data
   float* cscale_w;
   int* flag;            // status bits (kFlagInverted | kFlagNonFinite)
-  int64_t qstride;      // n_cells * Q
 };
 
 constexpr int kFlagInverted = 1;
@@ -109,6 +108,12 @@ inline int mode_words(hx_storage m) {
 }
 
 // One per degree, defined in hx_degree.hip compiled with HX_DEGREE = p.
+int cells_per_block_p1();
+int cells_per_block_p2();
+int cells_per_block_p3();
+int cells_per_block_p4();
+int cells_per_block_p5();
+int cells_per_block_p6();
 hipError_t consts_p1(const HostArgs&);
 hipError_t consts_p2(const HostArgs&);
 hipError_t consts_p3(const HostArgs&);

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include "hx_internal.hpp"
+#include "hx_tables.hpp"
 
 namespace hx {
 
@@ -410,16 +411,38 @@ __device__ __forceinline__ CellPos cell_pos(const Lattice& L, int e) {
   return c;
 }
 
+// position of cell e0 + le from the position of e0 (carry along the lattice; le is small)
+__device__ __forceinline__ CellPos cell_advance(const Lattice& L, CellPos c, int le) {
+  c.ex += le;
+  while (c.ex >= L.nx) {
+    c.ex -= L.nx;
+    if (++c.ey >= L.ny) {
+      c.ey = 0;
+      ++c.ez;
+    }
+  }
+  return c;
+}
+
+__device__ __forceinline__ int wrap(int I, int n) { return I >= n ? I - n : I; }
+
+// Dirichlet membership split by lattice direction (faces -x,+x | -y,+y,-z,+z)
+__device__ __forceinline__ bool cons_x(const Lattice& L, int I) {
+  const uint32_t f = L.dir_faces;
+  return ((f & 1u) && I == 0) || ((f & 2u) && I == L.Nx - 1);
+}
+__device__ __forceinline__ bool cons_yz(const Lattice& L, int J, int K) {
+  const uint32_t f = L.dir_faces;
+  return ((f & 4u) && J == 0) || ((f & 8u) && J == L.Ny - 1) || ((f & 16u) && K == 0) ||
+         ((f & 32u) && K == L.Nz - 1);
+}
+
 // node index and constraint flag of local node (i, j, k)
 __device__ __forceinline__ int64_t node_of(const Lattice& L, const CellPos& c, int i, int j, int k,
                                            bool& cons) {
-  int I = c.ex * L.p + i, J = c.ey * L.p + j, K = c.ez * L.p + k;
-  I = I >= L.Nx ? I - L.Nx : I;
-  J = J >= L.Ny ? J - L.Ny : J;
-  K = K >= L.Nz ? K - L.Nz : K;
-  const uint32_t f = L.dir_faces;
-  cons = ((f & 1u) && I == 0) || ((f & 2u) && I == L.Nx - 1) || ((f & 4u) && J == 0) ||
-         ((f & 8u) && J == L.Ny - 1) || ((f & 16u) && K == 0) || ((f & 32u) && K == L.Nz - 1);
+  const int I = wrap(c.ex * L.p + i, L.Nx), J = wrap(c.ey * L.p + j, L.Ny),
+            K = wrap(c.ez * L.p + k, L.Nz);
+  cons = cons_x(L, I) || cons_yz(L, J, K);
   return static_cast<int64_t>(I) + static_cast<int64_t>(L.Nx) * (J + static_cast<int64_t>(L.Ny) * K);
 }
 
@@ -462,35 +485,50 @@ __device__ __forceinline__ void pencil_jobs(Fn&& fn) {
   }
 }
 
+// LDS per cell: 12 fields of N^3 values (values at Gauss points and the three derivatives of the
+// three components; the backward pass reuses the first nine).
+constexpr int kBuffers = 12;
+
 // Forward pass for one 3-component vector V: writes the 9 reference derivatives at this
-// thread's q-point into g[c*3 + d]. Uses LDS buffers 0..8 of each cell (9 * N^3 values).
+// thread's q-point into g[c*3 + d]. Buffers per component c: c (values, then unused),
+// 3 + c (d/dx), 6 + c (d/dz), 9 + c (d/dy).
 template <int N, int EB, bool MASK, typename R>
 __device__ __forceinline__ void forward_vector(const KernelArgs<N, R>& a, R* sb, const R* V,
-                                               int e0, int le_me, int q_me, R* g) {
+                                               int e0, const CellPos& c0, int le_me, int q_me,
+                                               R* g) {
   constexpr int Q = N * N * N;
-  constexpr int CB = 9 * Q;  // per-cell stride in LDS
+  constexpr int CB = kBuffers * Q;  // per-cell stride in LDS
   const Lattice& L = a.L;
-  // F1: gather x-pencils from global memory, interpolate along x
-  pencil_jobs<N, EB, 3>([&](int le, int c, int j, int k) __attribute__((always_inline)) {
-    R in[N], out[N];
-    const int e = e0 + le;
-    if (e < L.n_cells) {
-      const CellPos cp = cell_pos(L, e);
+  // F0: gather, one node per thread: the lanes of a wavefront walk contiguous x-rows of the
+  // lattice, so each load instruction touches few cache lines (a pencil-per-lane gather touches
+  // one line per lane and was the most expensive part of the kernel)
+  {
+    R* cb = sb + le_me * CB;
+    if (e0 + le_me < L.n_cells) {
+      const int i = q_me % N, j = (q_me / N) % N, k = q_me / (N * N);
+      const CellPos cp = cell_advance(L, c0, le_me);
+      bool cons;
+      const int64_t node = node_of(L, cp, i, j, k, cons);
 #pragma unroll
-      for (int i = 0; i < N; ++i) {
-        bool cons;
-        const int64_t node = node_of(L, cp, i, j, k, cons);
+      for (int c = 0; c < 3; ++c) {
         const R v = V[c * L.n_nodes + node];
-        in[i] = (MASK && cons) ? R(0) : v;
+        cb[c * Q + q_me] = (MASK && cons) ? R(0) : v;
       }
     } else {
 #pragma unroll
-      for (int i = 0; i < N; ++i) in[i] = R(0);
+      for (int c = 0; c < 3; ++c) cb[c * Q + q_me] = R(0);
     }
-    apply1d<N, false>(a.c->b.B, in, out);
+  }
+  __syncthreads();
+  // F1: interpolate along x
+  pencil_jobs<N, EB, 3>([&](int le, int c, int j, int k) __attribute__((always_inline)) {
+    R in[N], out[N];
     R* buf = sb + le * CB + c * Q;
 #pragma unroll
-    for (int i = 0; i < N; ++i) buf[pidx<N, 0>(j, k, i)] = out[i];
+    for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 0>(j, k, m)];
+    apply1d<N, false>(Tab1D<N, R>::B, in, out);
+#pragma unroll
+    for (int m = 0; m < N; ++m) buf[pidx<N, 0>(j, k, m)] = out[m];
   });
   __syncthreads();
   // F2: interpolate along y
@@ -499,7 +537,7 @@ __device__ __forceinline__ void forward_vector(const KernelArgs<N, R>& a, R* sb,
     R* buf = sb + le * CB + c * Q;
 #pragma unroll
     for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 1>(i, k, m)];
-    apply1d<N, false>(a.c->b.B, in, out);
+    apply1d<N, false>(Tab1D<N, R>::B, in, out);
 #pragma unroll
     for (int m = 0; m < N; ++m) buf[pidx<N, 1>(i, k, m)] = out[m];
   });
@@ -511,8 +549,8 @@ __device__ __forceinline__ void forward_vector(const KernelArgs<N, R>& a, R* sb,
     R* bz = sb + le * CB + (6 + c) * Q;
 #pragma unroll
     for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 2>(i, j, m)];
-    apply1d<N, false>(a.c->b.B, in, v);
-    apply1d<N, false>(a.c->b.D, v, d);
+    apply1d<N, false>(Tab1D<N, R>::B, in, v);
+    apply1d<N, false>(Tab1D<N, R>::D, v, d);
 #pragma unroll
     for (int m = 0; m < N; ++m) {
       buf[pidx<N, 2>(i, j, m)] = v[m];
@@ -520,47 +558,50 @@ __device__ __forceinline__ void forward_vector(const KernelArgs<N, R>& a, R* sb,
     }
   });
   __syncthreads();
-  // F4: differentiate along x into buffer 3 + c
-  pencil_jobs<N, EB, 3>([&](int le, int c, int j, int k) __attribute__((always_inline)) {
+  // F4: differentiate along x (into 3 + c) and along y (into 9 + c) in one phase
+  pencil_jobs<N, EB, 6>([&](int le, int set, int a1, int b1) __attribute__((always_inline)) {
+    const int c = set >> 1;
     R in[N], d[N];
     const R* buf = sb + le * CB + c * Q;
-    R* bx = sb + le * CB + (3 + c) * Q;
+    if ((set & 1) == 0) {
+      R* bx = sb + le * CB + (3 + c) * Q;
 #pragma unroll
-    for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 0>(j, k, m)];
-    apply1d<N, false>(a.c->b.D, in, d);
+      for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 0>(a1, b1, m)];
+      apply1d<N, false>(Tab1D<N, R>::D, in, d);
 #pragma unroll
-    for (int m = 0; m < N; ++m) bx[pidx<N, 0>(j, k, m)] = d[m];
+      for (int m = 0; m < N; ++m) bx[pidx<N, 0>(a1, b1, m)] = d[m];
+    } else {
+      R* by = sb + le * CB + (9 + c) * Q;
+#pragma unroll
+      for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 1>(a1, b1, m)];
+      apply1d<N, false>(Tab1D<N, R>::D, in, d);
+#pragma unroll
+      for (int m = 0; m < N; ++m) by[pidx<N, 1>(a1, b1, m)] = d[m];
+    }
   });
   __syncthreads();
-  // F5: differentiate along y in place
-  pencil_jobs<N, EB, 3>([&](int le, int c, int i, int k) __attribute__((always_inline)) {
-    R in[N], d[N];
-    R* buf = sb + le * CB + c * Q;
-#pragma unroll
-    for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 1>(i, k, m)];
-    apply1d<N, false>(a.c->b.D, in, d);
-#pragma unroll
-    for (int m = 0; m < N; ++m) buf[pidx<N, 1>(i, k, m)] = d[m];
-  });
-  __syncthreads();
-  // F6: this thread's q-point
+  // F5: this thread's q-point
   const R* cb = sb + le_me * CB;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     g[3 * c + 0] = cb[(3 + c) * Q + q_me];
-    g[3 * c + 1] = cb[c * Q + q_me];
+    g[3 * c + 1] = cb[(9 + c) * Q + q_me];
     g[3 * c + 2] = cb[(6 + c) * Q + q_me];
   }
 }
 
 // Backward pass: integrates the test coefficients t[c*3 + d] of every q-thread against the
 // reference gradients of the basis and adds the element vectors into a.out.
+// The last contraction is written back to LDS so that the scatter runs one node per thread: the
+// lanes of a wavefront then cover contiguous x-rows and their atomics combine into few cache-line
+// requests (scattering straight from the pencil jobs costs about twice the kernel time).
 // Element-interior nodes belong to one cell only and are stored; shared nodes use atomics.
 template <int N, int EB, typename R>
 __device__ __forceinline__ void backward_scatter(const KernelArgs<N, R>& a, R* sb, int e0,
-                                                 int le_me, int q_me, const R* t) {
+                                                 const CellPos& c0, int le_me, int q_me,
+                                                 const R* t) {
   constexpr int Q = N * N * N;
-  constexpr int CB = 9 * Q;
+  constexpr int CB = kBuffers * Q;
   const Lattice& L = a.L;
   __syncthreads();  // buffers may still be read by the forward pass
   {
@@ -577,14 +618,14 @@ __device__ __forceinline__ void backward_scatter(const KernelArgs<N, R>& a, R* s
       R* buf = sb + le * CB + (3 * c) * Q;
 #pragma unroll
       for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 0>(a1, b1, m)];
-      apply1d<N, true>(a.c->b.D, in, out);
+      apply1d<N, true>(Tab1D<N, R>::D, in, out);
 #pragma unroll
       for (int m = 0; m < N; ++m) buf[pidx<N, 0>(a1, b1, m)] = out[m];
     } else {
       R* buf = sb + le * CB + (3 * c + 1) * Q;
 #pragma unroll
       for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 1>(a1, b1, m)];
-      apply1d<N, true>(a.c->b.D, in, out);
+      apply1d<N, true>(Tab1D<N, R>::D, in, out);
 #pragma unroll
       for (int m = 0; m < N; ++m) buf[pidx<N, 1>(a1, b1, m)] = out[m];
     }
@@ -598,10 +639,10 @@ __device__ __forceinline__ void backward_scatter(const KernelArgs<N, R>& a, R* s
     const R* bzp = sb + le * CB + (3 * c + 2) * Q;
 #pragma unroll
     for (int m = 0; m < N; ++m) tz[m] = bzp[pidx<N, 2>(i, j, m)];
-    apply1d<N, true>(a.c->b.D, tz, s);
+    apply1d<N, true>(Tab1D<N, R>::D, tz, s);
 #pragma unroll
     for (int m = 0; m < N; ++m) s[m] += bx[pidx<N, 2>(i, j, m)] + by[pidx<N, 2>(i, j, m)];
-    apply1d<N, true>(a.c->b.B, s, out);
+    apply1d<N, true>(Tab1D<N, R>::B, s, out);
 #pragma unroll
     for (int m = 0; m < N; ++m) bx[pidx<N, 2>(i, j, m)] = out[m];
   });
@@ -612,35 +653,42 @@ __device__ __forceinline__ void backward_scatter(const KernelArgs<N, R>& a, R* s
     R* buf = sb + le * CB + (3 * c) * Q;
 #pragma unroll
     for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 1>(i, k, m)];
-    apply1d<N, true>(a.c->b.B, in, out);
+    apply1d<N, true>(Tab1D<N, R>::B, in, out);
 #pragma unroll
     for (int m = 0; m < N; ++m) buf[pidx<N, 1>(i, k, m)] = out[m];
   });
   __syncthreads();
-  // B5: B^T along x and scatter
-  constexpr int P = N - 1;
+  // B5: B^T along x in place, then one node per thread scatters (contiguous rows per wave)
   pencil_jobs<N, EB, 3>([&](int le, int c, int j, int k) __attribute__((always_inline)) {
-    const int e = e0 + le;
-    if (e >= L.n_cells) return;
     R in[N], out[N];
-    const R* buf = sb + le * CB + (3 * c) * Q;
+    R* buf = sb + le * CB + (3 * c) * Q;
 #pragma unroll
     for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 0>(j, k, m)];
-    apply1d<N, true>(a.c->b.B, in, out);
-    const CellPos cp = cell_pos(L, e);
-    const bool inner_jk = j > 0 && j < P && k > 0 && k < P;
+    apply1d<N, true>(Tab1D<N, R>::B, in, out);
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
+    for (int m = 0; m < N; ++m) buf[pidx<N, 0>(j, k, m)] = out[m];
+  });
+  __syncthreads();
+  constexpr int P = N - 1;
+  {
+    const int e = e0 + le_me;
+    if (e < L.n_cells) {
+      const int i = q_me % N, j = (q_me / N) % N, k = q_me / (N * N);
+      const CellPos cp = cell_advance(L, c0, le_me);
       bool cons;
       const int64_t node = node_of(L, cp, i, j, k, cons);
-      if (cons) continue;
-      R* dst = a.out + c * L.n_nodes + node;
-      if (inner_jk && i > 0 && i < P)
-        *dst = out[i];
-      else
-        unsafeAtomicAdd(dst, out[i]);
+      if (!cons) {
+        const bool inner = i > 0 && i < P && j > 0 && j < P && k > 0 && k < P;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const R v = sb[le_me * CB + (3 * c) * Q + q_me];
+          R* dst = a.out + c * L.n_nodes + node;
+          if (inner) *dst = v;
+          else unsafeAtomicAdd(dst, v);
+        }
+      }
     }
-  });
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -660,19 +708,20 @@ __device__ __forceinline__ R pick(const R* arr, int idx) {
 template <int N, typename R>
 __device__ __forceinline__ R qpoint_geometry(const KernelArgs<N, R>& a, const R* X, int q, R* K) {
   const int qx = q % N, qy = (q / N) % N, qz = q / (N * N);
-  const R det = trilinear_geometry(X, pick<N>(a.c->b.x, qx), pick<N>(a.c->b.x, qy), pick<N>(a.c->b.x, qz), K);
-  return det * (pick<N>(a.c->b.w, qx) * pick<N>(a.c->b.w, qy) * pick<N>(a.c->b.w, qz));
+  const R det = trilinear_geometry(X, pick<N>(Tab1D<N, R>::x, qx), pick<N>(Tab1D<N, R>::x, qy), pick<N>(Tab1D<N, R>::x, qz), K);
+  return det * (pick<N>(Tab1D<N, R>::w, qx) * pick<N>(Tab1D<N, R>::w, qy) * pick<N>(Tab1D<N, R>::w, qz));
 }
 
 template <int N, int EB, typename R>
-__device__ __forceinline__ void load_vertices(const KernelArgs<N, R>& a, R* sv, int e0) {
+__device__ __forceinline__ void load_vertices(const KernelArgs<N, R>& a, R* sv, int e0,
+                                              const CellPos& c0) {
   // 24 values per cell (8 vertices x 3 coordinates), spread over the workgroup
   constexpr int NT = EB * N * N * N;
   for (int idx = threadIdx.x; idx < EB * 24; idx += NT) {
     const int le = idx / 24, q = idx - 24 * le;
     const int e = e0 + le;
     if (e >= a.L.n_cells) continue;
-    const CellPos cp = cell_pos(a.L, e);
+    const CellPos cp = cell_advance(a.L, c0, le);
     const int v = q / 3, comp = q - 3 * v;
     int vx = cp.ex + (v & 1), vy = cp.ey + ((v >> 1) & 1), vz = cp.ez + (v >> 2);
     vx = vx >= a.L.Vx ? vx - a.L.Vx : vx;
@@ -685,12 +734,14 @@ __device__ __forceinline__ void load_vertices(const KernelArgs<N, R>& a, R* sv, 
 
 // Kernel: ops = residual, apply (three storage modes) and update (three storage modes).
 //   KIND 0 apply, 1 residual, 2 update; MODE = hx_storage; S = StoreType; LAW
+// The apply and residual kernels are held to at most 128 VGPRs (4 waves per SIMD); the update
+// runs once per Newton step and may use the whole register file.
 template <int N, int EB, typename R, int KIND, int MODE, int LAW, int S>
-__global__ void __launch_bounds__(EB * N * N * N)
+__global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
     element_kernel(KernelArgs<N, R> a) {
   constexpr int Q = N * N * N;
   using ST = typename StoreOf<S>::T;
-  __shared__ R sb[EB * 9 * Q];
+  __shared__ R sb[EB * kBuffers * Q];
   __shared__ R sv[EB * 24];
   __shared__ float sred[EB];
   const int le = threadIdx.x / Q;
@@ -698,10 +749,16 @@ __global__ void __launch_bounds__(EB * N * N * N)
   const int e0 = blockIdx.x * EB;
   const int e = e0 + le;
   const bool valid = e < a.L.n_cells;
-  const int64_t qi = static_cast<int64_t>(e) * Q + q;
+  const CellPos c0 = cell_pos(a.L, e0);
+  // stored data: block-interleaved planes [block][word][EB * Q]; the plane base is uniform
+  // across the workgroup and the lane offset is the thread index
+  constexpr int W = MODE == HX_STORE_TANGENT ? 45 : (MODE == HX_STORE_FINV_J ? 10 : 0);
+  constexpr int EBQ = EB * Q;
+  const int64_t qblk = static_cast<int64_t>(blockIdx.x) * W * EBQ;
+  const int qi = threadIdx.x;
 
   constexpr bool kGeom = !(KIND == 0 && MODE == HX_STORE_TANGENT);
-  if constexpr (kGeom) load_vertices<N, EB>(a, sv, e0);
+  if constexpr (kGeom) load_vertices<N, EB>(a, sv, e0, c0);
   if constexpr (KIND == 2 && S == kStoreF16) {
     if (q == 0) sred[le] = 0.0f;
   }
@@ -709,23 +766,23 @@ __global__ void __launch_bounds__(EB * N * N * N)
   R g0[9], g1[9], t[9];
   if constexpr (KIND == 0 && MODE == HX_STORE_NONE) {
     // linearisation point first (not masked), then the direction (masked)
-    forward_vector<N, EB, false>(a, sb, a.in1, e0, le, q, g1);
+    forward_vector<N, EB, false>(a, sb, a.in1, e0, c0, le, q, g1);
     __syncthreads();
-    forward_vector<N, EB, true>(a, sb, a.in0, e0, le, q, g0);
+    forward_vector<N, EB, true>(a, sb, a.in0, e0, c0, le, q, g0);
   } else if constexpr (KIND == 0) {
-    forward_vector<N, EB, true>(a, sb, a.in0, e0, le, q, g0);
+    forward_vector<N, EB, true>(a, sb, a.in0, e0, c0, le, q, g0);
   } else {
-    forward_vector<N, EB, false>(a, sb, a.in0, e0, le, q, g0);
+    forward_vector<N, EB, false>(a, sb, a.in0, e0, c0, le, q, g0);
   }
 
   const MaterialK<R>& m = a.c->m;
   if constexpr (KIND == 0 && MODE == HX_STORE_TANGENT) {
     // t = D g with the stored symmetric 9x9 tangent (45 planes, upper triangle row by row)
-    const ST* qd = static_cast<const ST*>(a.qdata);
+    const ST* qd = static_cast<const ST*>(a.qdata) + qblk;
     R Dv[45];
     if (valid) {
 #pragma unroll
-      for (int w = 0; w < 45; ++w) Dv[w] = static_cast<R>(load_val(qd + w * a.qstride + qi));
+      for (int w = 0; w < 45; ++w) Dv[w] = static_cast<R>(load_val(qd + w * EBQ + qi));
     } else {
 #pragma unroll
       for (int w = 0; w < 45; ++w) Dv[w] = R(0);
@@ -760,12 +817,12 @@ __global__ void __launch_bounds__(EB * N * N * N)
       to_physical(g1, K, H);
       state_from_H<LAW>(H, m, st, E);
     } else {
-      const ST* qd = static_cast<const ST*>(a.qdata);
+      const ST* qd = static_cast<const ST*>(a.qdata) + qblk;
       R Fi[9], Jm;
       if (valid) {
 #pragma unroll
-        for (int w = 0; w < 9; ++w) Fi[w] = static_cast<R>(load_val(qd + w * a.qstride + qi));
-        Jm = static_cast<R>(load_val(qd + 9 * a.qstride + qi));
+        for (int w = 0; w < 9; ++w) Fi[w] = static_cast<R>(load_val(qd + w * EBQ + qi));
+        Jm = static_cast<R>(load_val(qd + 9 * EBQ + qi));
       } else {
 #pragma unroll
         for (int w = 0; w < 9; ++w) Fi[w] = R(w % 4 == 0);
@@ -794,7 +851,7 @@ __global__ void __launch_bounds__(EB * N * N * N)
     const bool ok = state_from_H<LAW>(H, m, st, E);
     int bad = 0;
     if (valid && !ok) bad |= kFlagInverted;
-    ST* qw = static_cast<ST*>(a.qdata_w);
+    ST* qw = static_cast<ST*>(a.qdata_w) + qblk;
     if constexpr (MODE == HX_STORE_FINV_J) {
       R chk = st.Jm;
 #pragma unroll
@@ -802,8 +859,8 @@ __global__ void __launch_bounds__(EB * N * N * N)
       if (valid && !isfinite(chk)) bad |= kFlagNonFinite;
       if (valid) {
 #pragma unroll
-        for (int w = 0; w < 9; ++w) store_val(qw + w * a.qstride + qi, st.Fi[w]);
-        store_val(qw + 9 * a.qstride + qi, st.Jm);
+        for (int w = 0; w < 9; ++w) store_val(qw + w * EBQ + qi, st.Fi[w]);
+        store_val(qw + 9 * EBQ + qi, st.Jm);
       }
     } else if constexpr (MODE == HX_STORE_TANGENT) {
       // columns of the reference tangent: unit reference gradient e_k (x) e_b maps to the
@@ -850,7 +907,7 @@ __global__ void __launch_bounds__(EB * N * N * N)
       }
       if (valid) {
 #pragma unroll
-        for (int i = 0; i < 45; ++i) store_val(qw + i * a.qstride + qi, Dsym[i] * scale);
+        for (int i = 0; i < 45; ++i) store_val(qw + i * EBQ + qi, Dsym[i] * scale);
       }
     } else {
       R chk = st.Jm;
@@ -864,7 +921,7 @@ __global__ void __launch_bounds__(EB * N * N * N)
 #pragma unroll
       for (int i = 0; i < 9; ++i) t[i] = R(0);
     }
-    backward_scatter<N, EB>(a, sb, e0, le, q, t);
+    backward_scatter<N, EB>(a, sb, e0, c0, le, q, t);
   }
 }
 
