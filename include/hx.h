@@ -170,6 +170,85 @@ hx_status hx_fiber_structure(double a, double b, double phi, const double* E,
                              double* H4, double* H6, double* M4, double* M6);
 
 /* Message for the last error on ctx (or of the last failed hx_setup when ctx is NULL). */
+/* ------------------------------------------------------------------------------------------
+ * p-multigrid preconditioner and Newton-Krylov solve (Section 6 and Algorithm 1).
+ * ------------------------------------------------------------------------------------------ */
+typedef struct hx_mg_s* hx_mg;
+
+typedef struct {
+  int32_t smoother_degree; /* Chebyshev degree of the Jacobi smoother on all but the coarsest
+                              level (default 4) */
+  int32_t coarse_degree;   /* Chebyshev degree of the approximate coarse solve (default 30) */
+  double smoothing_range;  /* lambda_min = lambda_max / range (default 20) */
+  int32_t eig_iters;       /* power iterations for lambda_max of D^-1 A (default 20) */
+  double eig_safety;       /* the estimate is multiplied by this factor (default 1.2) */
+  hx_precision precision;  /* HX_FP32: levels apply in FP32 with FP32 stored tangents (the
+                              mixed-precision preconditioner); HX_FP64: everything in FP64 */
+  int32_t use_graph;       /* 1: one V-cycle is captured into a HIP graph per update */
+} hx_mg_options;
+
+/* Builds a V-cycle over contexts on the same lattice with strictly decreasing degrees
+ * (levels[0] finest). The contexts stay owned by the caller and must outlive the hierarchy.
+ * opt may be NULL (defaults). Levels store the TANGENT mode in the multigrid precision; with
+ * HX_FP64 the finest level's FP64 slot is shared with the outer operator. */
+hx_status hx_mg_create(const hx_ctx* levels, int32_t n_levels, const hx_mg_options* opt,
+                       hx_mg* out);
+hx_status hx_mg_destroy(hx_mg mg);
+const char* hx_mg_last_error(hx_mg mg);
+
+/* Linearisation of every level at the finest-level displacement u (device FP64 [3][n_nodes]):
+ * u is interpolated onto the coarser nodes, each level stores its tangent, its inverse diagonal
+ * and a lambda_max estimate; the V-cycle is then captured into a graph. Synchronous. */
+hx_status hx_mg_update(hx_mg mg, const double* u, void* stream);
+
+/* z = M^-1 r with one V-cycle (pre/post Chebyshev smoothing, restriction by the transpose of the
+ * polynomial prolongation). r, z: device [3][n_nodes] of the finest level, float for HX_FP32
+ * hierarchies and double for HX_FP64. */
+hx_status hx_mg_vcycle(hx_mg mg, const void* r, void* z, void* stream);
+int64_t hx_mg_vcycle_count(hx_mg mg);
+double hx_mg_lambda_max(hx_mg mg, int32_t level);
+
+/* Transfers between level `level` (fine) and level + 1 (coarse), device vectors [3][n_nodes]:
+ *   kind 0: out_fine += P in_coarse   (P embeds the coarse polynomial space; every fine node is
+ *           written once, by its owning cell, so the result is deterministic)
+ *   kind 1: out_coarse += P^T in_fine (constrained coarse rows untouched; atomics)
+ *   kind 2: out_coarse = the fine field in_fine evaluated at the coarse nodes (FP64 vectors)
+ * Kinds 0 and 1 use the hierarchy's precision (float for HX_FP32). Asynchronous. */
+hx_status hx_mg_transfer(hx_mg mg, int32_t level, int32_t kind, const void* in, void* out,
+                         void* stream);
+
+/* Copies the inverse diagonal of level `level` (identity on constrained rows) into out
+ * (device [3][n_nodes], hierarchy precision). */
+hx_status hx_mg_inverse_diagonal(hx_mg mg, int32_t level, void* out, void* stream);
+
+typedef struct {
+  double newton_rel_tol;  /* per load step: stop when ||r|| <= max(abs, rel * ||r_0||) */
+  double newton_abs_tol;
+  int32_t max_newton;     /* Newton iterations per load step */
+  double krylov_rel_tol;  /* inner flexible CG: ||b - K x|| <= rel * ||b|| */
+  int32_t max_krylov;
+  int32_t load_steps;     /* the external load is applied in this many equal increments */
+  hx_storage outer_mode;  /* storage mode of the FP64 outer operator (mixed precision only) */
+} hx_newton_opts;
+
+typedef struct {
+  int32_t newton_iters, krylov_iters, vcycles, load_steps_done;
+  double initial_residual, final_residual, seconds;
+} hx_newton_report;
+
+/* Solves r(u) = f_ext (Problem 2.1 with a dead load) by Newton's method with load stepping
+ * (Algorithm 1), each step by flexible CG in FP64 on the finest FP64 operator preconditioned by
+ * one V-cycle of mg. u: device FP64 [3][n_nodes], in/out (its constrained entries are the
+ * homogeneous Dirichlet data). f_ext: device FP64 [3][n_nodes] or NULL. Synchronous; returns
+ * HX_E_NOT_CONVERGED if a load step does not reach its tolerance (u holds the last iterate). */
+hx_status hx_newton_solve(hx_mg mg, double* u, const double* f_ext, const hx_newton_opts* opt,
+                          hx_newton_report* report, void* stream);
+
+/* Host helper: dead-load pressure on boundary face `face` (0..5 = -x,+x,-y,+y,-z,+z):
+ * f_(c,a) = -p int_face phi_a N_c dA with N the outward unit normal of the reference body
+ * (Section 2, Neumann term of the residual). f: HOST array [3][n_nodes], overwritten. */
+hx_status hx_surface_load(hx_ctx ctx, int32_t face, double pressure, double* f);
+
 const char* hx_last_error(hx_ctx ctx);
 const char* hx_status_string(hx_status s);
 

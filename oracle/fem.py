@@ -17,10 +17,16 @@ is identity rows and columns on constrained DoFs): r~ = P_f r,  K~ du = P_f K P_
 All functions accept complex displacement vectors so that tests can take complex-step derivatives.
 Work proceeds over chunks of cells; arrays are the plain [cells, q-points, ...] tensors.
 
-Test infrastructure only. Pinned in tests/test_oracle_fem.py (patch test, rigid rotation,
-translation invariance, residual = complex-step gradient of the energy, tangent = complex-step
-derivative of the residual, symmetry, linear elasticity at u = 0 against an independent
-Voigt-notation stiffness).
+Also: the dead-load surface vector of a pressure on a boundary face, and the dense transfer
+matrices between two degrees on one lattice (prolongation = coarse basis at the fine nodes;
+interpolation of a fine field onto the coarse nodes).
+
+Test infrastructure only. Pinned in tests/test_oracle_fem.py and tests/test_oracle_transfer.py
+(patch test, rigid rotation, translation invariance, residual = complex-step gradient of the
+energy, tangent = complex-step derivative of the residual, symmetry, linear elasticity at u = 0
+against an independent Voigt-notation stiffness; face resultant of a pressure on a planar face,
+zero resultant on a closed surface; exact reproduction of polynomials by the transfers and
+J P = I).
 """
 import numpy as np
 
@@ -177,3 +183,95 @@ class Problem:
             K[:, cdofs] = 0.0
             K[cdofs, cdofs] = 1.0
         return K
+
+
+def surface_load(problem, face, pressure):
+    """Dead-load pressure vector f_(c,a) = -p sum over boundary cells of int phi_a N_c dA.
+
+    Section 2 residual, Neumann term: h_N = -p N with N the outward unit normal of the reference
+    body; integrated with (p+1)^2 Gauss points on each cell face of the trilinear map.
+    """
+    m = problem.mesh
+    d, side = face // 2, face % 2
+    if m.periodic[d]:
+        raise ValueError("face of a periodic direction")
+    p, n = m.p, m.n
+    xg = basis.gll_points(p)
+    xq, wq = basis.gauss_rule(n)
+    L = basis.lagrange_values(xg, xq)             # L[q, i]
+    da, db = (d + 1) % 3, (d + 2) % 3
+    ncells = (m.nx, m.ny, m.nz)
+    f = np.zeros((3, m.n_nodes))
+    cd = ncells[d] - 1 if side else 0
+    for c2 in range(ncells[db]):
+        for c1 in range(ncells[da]):
+            cell = [0, 0, 0]
+            cell[d], cell[da], cell[db] = cd, c1, c2
+            e = cell[0] + m.nx * (cell[1] + m.ny * cell[2])
+            X8 = m.cell_vertex_xyz[e]
+            for q2 in range(n):
+                for q1 in range(n):
+                    xi = [0.0, 0.0, 0.0]
+                    xi[d], xi[da], xi[db] = (1.0 if side else 0.0), xq[q1], xq[q2]
+                    ta, tb = np.zeros(3), np.zeros(3)
+                    for v in range(8):
+                        bit = (v & 1, (v >> 1) & 1, v >> 2)
+                        phi = [xi[k] if bit[k] else 1.0 - xi[k] for k in range(3)]
+                        dphi = [1.0 if bit[k] else -1.0 for k in range(3)]
+                        ta += dphi[da] * phi[db] * phi[d] * X8[v]
+                        tb += phi[da] * dphi[db] * phi[d] * X8[v]
+                    NdA = np.cross(ta, tb) * (1.0 if side else -1.0)
+                    w = wq[q1] * wq[q2]
+                    for j2 in range(n):
+                        for j1 in range(n):
+                            loc = [0, 0, 0]
+                            loc[d], loc[da], loc[db] = (n - 1 if side else 0), j1, j2
+                            node = m.cell_nodes[e, loc[0] + n * (loc[1] + n * loc[2])]
+                            f[:, node] += -pressure * NdA * w * L[q1, j1] * L[q2, j2]
+    return f
+
+
+def _owner_local(mesh, node):
+    """(cell, local lattice index (i, j, k)) of the owning cell of a node (node-coordinate rule)."""
+    Nx, Ny, _ = mesh.ndims
+    lat = (node % Nx, (node // Nx) % Ny, node // (Nx * Ny))
+    cell, loc = [], []
+    for dd, nd in enumerate((mesh.nx, mesh.ny, mesh.nz)):
+        c = min(lat[dd] // mesh.p, nd - 1)
+        cell.append(c)
+        loc.append(lat[dd] - c * mesh.p)
+    return cell[0] + mesh.nx * (cell[1] + mesh.ny * cell[2]), loc
+
+
+def prolongation_matrix(mesh_f, mesh_c):
+    """Dense P [fine nodes, coarse nodes]: the coarse nodal basis evaluated at each fine node,
+    through the reference coordinates of the node in an owning cell (scalar field; the vector
+    operator applies it to each component)."""
+    xf = basis.gll_points(mesh_f.p)
+    xc = basis.gll_points(mesh_c.p)
+    P = np.zeros((mesh_f.n_nodes, mesh_c.n_nodes))
+    nc = mesh_c.n
+    for node in range(mesh_f.n_nodes):
+        e, loc = _owner_local(mesh_f, node)
+        vals = [basis.lagrange_values(xc, [xf[loc[dd]]])[0] for dd in range(3)]
+        for k in range(nc):
+            for j in range(nc):
+                for i in range(nc):
+                    P[node, mesh_c.cell_nodes[e, i + nc * (j + nc * k)]] = vals[0][i] * vals[1][j] * vals[2][k]
+    return P
+
+
+def interpolation_matrix(mesh_f, mesh_c):
+    """Dense J [coarse nodes, fine nodes]: the fine nodal basis evaluated at each coarse node."""
+    xf = basis.gll_points(mesh_f.p)
+    xc = basis.gll_points(mesh_c.p)
+    J = np.zeros((mesh_c.n_nodes, mesh_f.n_nodes))
+    nf = mesh_f.n
+    for node in range(mesh_c.n_nodes):
+        e, loc = _owner_local(mesh_c, node)
+        vals = [basis.lagrange_values(xf, [xc[loc[dd]]])[0] for dd in range(3)]
+        for k in range(nf):
+            for j in range(nf):
+                for i in range(nf):
+                    J[node, mesh_f.cell_nodes[e, i + nf * (j + nf * k)]] = vals[0][i] * vals[1][j] * vals[2][k]
+    return J

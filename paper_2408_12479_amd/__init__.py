@@ -45,6 +45,25 @@ class _Options(ctypes.Structure):
     _fields_ = [("jpow_newton_iters", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
 
 
+class _MgOptions(ctypes.Structure):
+    _fields_ = [("smoother_degree", ctypes.c_int32), ("coarse_degree", ctypes.c_int32),
+                ("smoothing_range", ctypes.c_double), ("eig_iters", ctypes.c_int32),
+                ("eig_safety", ctypes.c_double), ("precision", ctypes.c_int), ("use_graph", ctypes.c_int32)]
+
+
+class _NewtonOpts(ctypes.Structure):
+    _fields_ = [("newton_rel_tol", ctypes.c_double), ("newton_abs_tol", ctypes.c_double),
+                ("max_newton", ctypes.c_int32), ("krylov_rel_tol", ctypes.c_double),
+                ("max_krylov", ctypes.c_int32), ("load_steps", ctypes.c_int32), ("outer_mode", ctypes.c_int)]
+
+
+class _NewtonReport(ctypes.Structure):
+    _fields_ = [("newton_iters", ctypes.c_int32), ("krylov_iters", ctypes.c_int32),
+                ("vcycles", ctypes.c_int32), ("load_steps_done", ctypes.c_int32),
+                ("initial_residual", ctypes.c_double), ("final_residual", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2408_12479_amd.build")
@@ -65,6 +84,19 @@ def _load():
         "hx_linearization_bytes": (i64, [vp, ctypes.c_int]),
         "hx_fiber_structure": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double]
                                + [ctypes.POINTER(ctypes.c_double)] * 5),
+        "hx_mg_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(_MgOptions),
+                                        ctypes.POINTER(vp)]),
+        "hx_mg_destroy": (ctypes.c_int, [vp]),
+        "hx_mg_last_error": (ctypes.c_char_p, [vp]),
+        "hx_mg_update": (ctypes.c_int, [vp, vp, vp]),
+        "hx_mg_vcycle": (ctypes.c_int, [vp, vp, vp, vp]),
+        "hx_mg_vcycle_count": (i64, [vp]),
+        "hx_mg_lambda_max": (ctypes.c_double, [vp, ctypes.c_int32]),
+        "hx_mg_transfer": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]),
+        "hx_mg_inverse_diagonal": (ctypes.c_int, [vp, ctypes.c_int32, vp, vp]),
+        "hx_newton_solve": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(_NewtonOpts),
+                                           ctypes.POINTER(_NewtonReport), vp]),
+        "hx_surface_load": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
         "hx_last_error": (ctypes.c_char_p, [vp]),
         "hx_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     }
@@ -182,3 +214,94 @@ class Operator:
 
     def linearization_bytes(self, precision="fp64"):
         return int(lib.hx_linearization_bytes(self.ctx, PRECISIONS[precision]))
+
+    def surface_load(self, face, pressure):
+        """Dead-load pressure vector on a boundary face, host array (3, n_nodes)."""
+        out = np.zeros(3 * self.num_nodes)
+        _check(lib.hx_surface_load(self.ctx, int(face), float(pressure), _dptr(out)), self.ctx)
+        return out.reshape(3, self.num_nodes)
+
+
+def _check_mg(status, mg):
+    if status != HX_OK:
+        raise HxError(status, lib.hx_mg_last_error(mg).decode())
+
+
+class Multigrid:
+    """p-multigrid V-cycle over operators on the same lattice with decreasing degrees."""
+
+    def __init__(self, levels, smoother_degree=4, coarse_degree=30, smoothing_range=20.0, eig_iters=20,
+                 eig_safety=1.2, precision="fp32", use_graph=True):
+        self.levels = list(levels)
+        arr = (ctypes.c_void_p * len(self.levels))(*[op.ctx.value for op in self.levels])
+        o = _MgOptions(int(smoother_degree), int(coarse_degree), float(smoothing_range), int(eig_iters),
+                       float(eig_safety), PRECISIONS[precision], int(bool(use_graph)))
+        mg = ctypes.c_void_p()
+        _check(lib.hx_mg_create(arr, len(self.levels), ctypes.byref(o), ctypes.byref(mg)))
+        self.mg = mg
+        self.precision = precision
+
+    def close(self):
+        if getattr(self, "mg", None):
+            lib.hx_mg_destroy(self.mg)
+            self.mg = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def update(self, u, stream=None):
+        import torch
+        _check_mg(lib.hx_mg_update(self.mg, self.levels[0]._vec(u, torch.float64, "u"), _stream_handle(stream)),
+                  self.mg)
+
+    def vcycle(self, r, z=None, stream=None):
+        import torch
+        dt = torch.float32 if self.precision == "fp32" else torch.float64
+        z = torch.empty_like(r) if z is None else z
+        _check_mg(lib.hx_mg_vcycle(self.mg, self.levels[0]._vec(r, dt, "r"), self.levels[0]._vec(z, dt, "z"),
+                                   _stream_handle(stream)), self.mg)
+        return z
+
+    @property
+    def vcycle_count(self):
+        return int(lib.hx_mg_vcycle_count(self.mg))
+
+    def lambda_max(self, level):
+        return float(lib.hx_mg_lambda_max(self.mg, int(level)))
+
+    def transfer(self, level, kind, x, out, stream=None):
+        """kind 0: out += P x (fine <- coarse); 1: out += P^T x (coarse <- fine); 2: out = J x."""
+        import torch
+        dt = torch.float64 if (kind == 2 or self.precision == "fp64") else torch.float32
+        lf, lc = self.levels[level], self.levels[level + 1]
+        src_op, dst_op = (lc, lf) if kind == 0 else (lf, lc)
+        _check_mg(lib.hx_mg_transfer(self.mg, int(level), int(kind), src_op._vec(x, dt, "x"),
+                                     dst_op._vec(out, dt, "out"), _stream_handle(stream)), self.mg)
+        return out
+
+    def inverse_diagonal(self, level, stream=None):
+        import torch
+        dt = torch.float32 if self.precision == "fp32" else torch.float64
+        op = self.levels[level]
+        out = torch.empty(op.num_dofs, dtype=dt, device="cuda")
+        _check_mg(lib.hx_mg_inverse_diagonal(self.mg, int(level), op._vec(out, dt, "out"),
+                                             _stream_handle(stream)), self.mg)
+        return out
+
+    def newton_solve(self, u, f_ext=None, rel_tol=1e-8, abs_tol=0.0, max_newton=20, krylov_rel_tol=1e-3,
+                     max_krylov=500, load_steps=1, outer_mode="tangent", stream=None, check=True):
+        import torch
+        o = _NewtonOpts(float(rel_tol), float(abs_tol), int(max_newton), float(krylov_rel_tol), int(max_krylov),
+                        int(load_steps), MODES[outer_mode])
+        rep = _NewtonReport()
+        f = None if f_ext is None else self.levels[0]._vec(f_ext, torch.float64, "f_ext")
+        st = lib.hx_newton_solve(self.mg, self.levels[0]._vec(u, torch.float64, "u"), f, ctypes.byref(o),
+                                 ctypes.byref(rep), _stream_handle(stream))
+        out = {k: getattr(rep, k) for k, _ in _NewtonReport._fields_}
+        out["status"] = STATUS.get(st, st)
+        if check:
+            _check_mg(st, self.mg)
+        return out

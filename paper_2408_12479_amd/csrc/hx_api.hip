@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "hx.h"
+#include "hx_context.hpp"
 #include "hx_internal.hpp"
 
 namespace hx {
@@ -128,35 +129,9 @@ using namespace hx;
 
 namespace {
 
-struct Slot {
-  bool valid = false;
-  hx_storage mode = HX_STORE_NONE;
-  int store = kStoreF64;
-  void* qdata = nullptr;
-  size_t qbytes = 0;
-  float* cscale = nullptr;
-  void* uk = nullptr;  // linearisation point (recompute mode): double or float
-};
-
 thread_local std::string g_setup_error;
 
 }  // namespace
-
-struct hx_ctx_s {
-  int device = 0;
-  int p = 0;
-  Lattice L{};
-  HostArgs base{};
-  std::vector<double> gll;
-  std::vector<double> vert_host;  // [V][3]
-  double* vert64 = nullptr;
-  float* vert32 = nullptr;
-  int* flag = nullptr;
-  void* cblk64 = nullptr;
-  void* cblk32 = nullptr;
-  Slot slot[2];  // 0: FP64 class, 1: FP32 class
-  std::string err;
-};
 
 namespace {
 
@@ -173,7 +148,9 @@ hx_status hip_fail(hx_ctx ctx, hipError_t e, const char* what) {
   return fail(ctx, e == hipErrorOutOfMemory ? HX_E_NOMEM : HX_E_HIP, m);
 }
 
-hipError_t dispatch(int p, const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok) {
+}  // namespace
+
+hipError_t hx::dispatch(int p, const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok) {
   switch (p) {
     case 1: return dispatch_p1(op, h, s, ok);
     case 2: return dispatch_p2(op, h, s, ok);
@@ -185,7 +162,7 @@ hipError_t dispatch(int p, const HostOp& op, const HostArgs& h, hipStream_t s, b
   }
 }
 
-int cells_per_block(int p) {
+int hx::cells_per_block(int p) {
   switch (p) {
     case 1: return cells_per_block_p1();
     case 2: return cells_per_block_p2();
@@ -196,6 +173,8 @@ int cells_per_block(int p) {
     default: return 1;
   }
 }
+
+namespace {
 
 hipError_t write_consts(int p, const HostArgs& h) {
   switch (p) {
@@ -304,7 +283,9 @@ int grid_for(int64_t n) {
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(b, 8192)));
 }
 
-HostArgs args_for(const hx_ctx_s* c) {
+}  // namespace
+
+HostArgs hx::args_for(const hx_ctx_s* c) {
   HostArgs h = c->base;
   h.vert64 = c->vert64;
   h.vert32 = c->vert32;
@@ -313,6 +294,13 @@ HostArgs args_for(const hx_ctx_s* c) {
   h.cblk32 = c->cblk32;
   return h;
 }
+
+hx_status hx::set_error(hx_ctx_s* ctx, hx_status s, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return s;
+}
+
+namespace {
 
 int store_of(hx_precision p) {
   switch (p) {

@@ -110,6 +110,8 @@ hipError_t by_law(const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok) 
         }
       }
       break;
+    case OpKind::Diagonal:
+      break;
     case OpKind::Apply:
       if (op.mode == HX_STORE_NONE) {
         return op.fp32 ? launch<float, 0, HX_STORE_NONE, LAW, kStoreF32>(h, s)
@@ -122,6 +124,33 @@ hipError_t by_law(const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok) 
           return launch<float, 0, HX_STORE_FINV_J, LAW, kStoreF32>(h, s);
       }
       break;
+  }
+  *ok = false;
+  return hipSuccess;
+}
+
+template <typename R, int S>
+hipError_t launch_diag(const HostArgs& h, hipStream_t s) {
+  constexpr int EB = Blocking<N>::EB;
+  const KernelArgs<N, R> a = make_args<R>(h);
+  const int nblk = (h.L.n_cells + EB - 1) / EB;
+  if (nblk == 0) return hipSuccess;
+  diag_kernel<N, EB, R, S><<<dim3(nblk), dim3(EB * N * N * N), 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t diagonal(const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok) {
+  *ok = true;
+  if (op.mode == HX_STORE_TANGENT) {
+    if (!op.fp32 && op.store == kStoreF64) return launch_diag<double, kStoreF64>(h, s);
+    if (op.fp32) {
+      switch (op.store) {
+        case kStoreF32: return launch_diag<float, kStoreF32>(h, s);
+        case kStoreBF16: return launch_diag<float, kStoreBF16>(h, s);
+        case kStoreF16: return launch_diag<float, kStoreF16>(h, s);
+        default: break;
+      }
+    }
   }
   *ok = false;
   return hipSuccess;
@@ -160,6 +189,7 @@ hipError_t HX_CAT(consts_p, HX_DEGREE)(const HostArgs& h) {
 
 hipError_t HX_CAT(dispatch_p, HX_DEGREE)(const HostOp& op, const HostArgs& h, hipStream_t s,
                                           bool* ok) {
+  if (op.kind == OpKind::Diagonal) return diagonal(op, h, s, ok);
   if (op.kind == OpKind::Apply && op.mode == HX_STORE_TANGENT) return apply_tangent_mode(op, h, s, ok);
   switch (op.law) {
     case HX_LAW_CNH: return by_law<kCNH>(op, h, s, ok);

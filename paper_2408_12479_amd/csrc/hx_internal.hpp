@@ -72,7 +72,7 @@ constexpr int kFlagInverted = 1;
 constexpr int kFlagNonFinite = 2;
 
 enum StoreType : int { kStoreF64 = 0, kStoreF32 = 1, kStoreBF16 = 2, kStoreF16 = 3 };
-enum class OpKind : int { Apply = 0, Residual = 1, Update = 2 };
+enum class OpKind : int { Apply = 0, Residual = 1, Update = 2, Diagonal = 3 };
 
 // Host-side description of one launch.
 struct HostOp {

@@ -925,4 +925,123 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
   }
 }
 
+// ------------------------------------------------------------------------------------------
+// Diagonal of the linearised operator from the stored reference tangent (multigrid smoothers).
+// For node a = (i,j,k) and component c:
+//   diag = sum_q sum_{al,be} D_(c al)(c be)(q) dphi_a/dxi_al(q) dphi_a/dxi_be(q),
+// and dphi_a/dxi_al dphi_a/dxi_be factorises per direction into products of the 1D tables
+// B (values) and G (derivatives of the nodal basis at the Gauss points), so each of the six
+// unique (al, be) pairs is three transposed 1D sweeps.
+// ------------------------------------------------------------------------------------------
+template <int N, int AL, int BE, int DIR, typename R>
+__device__ __forceinline__ R diag_coef(int q, int i) {
+  const R x = (DIR == AL) ? Tab1D<N, R>::G[q * N + i] : Tab1D<N, R>::B[q * N + i];
+  const R y = (DIR == BE) ? Tab1D<N, R>::G[q * N + i] : Tab1D<N, R>::B[q * N + i];
+  return x * y;
+}
+
+template <int N, int AL, int BE, int DIR, typename R>
+__device__ __forceinline__ void diag_apply1d(const R* in, R* out) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    R acc = R(0);
+#pragma unroll
+    for (int m = 0; m < N; ++m) acc = fma(diag_coef<N, AL, BE, DIR, R>(m, i), in[m], acc);
+    out[i] = acc;
+  }
+}
+
+__host__ __device__ constexpr int packed_index(int a, int b) { return a * 9 - a * (a + 1) / 2 + b; }
+
+template <int N, int EB, int AL, int BE, typename R>
+__device__ __forceinline__ void diag_pair(R* sb, const R* Dv, int le_me, int q_me) {
+  constexpr int Q = N * N * N;
+  constexpr int CB = 6 * Q;
+  constexpr R fac = AL == BE ? R(1) : R(2);
+  R* cb = sb + le_me * CB;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) cb[c * Q + q_me] = fac * Dv[packed_index(3 * c + AL, 3 * c + BE)];
+  __syncthreads();
+  pencil_jobs<N, EB, 3>([&](int le, int c, int i, int j) __attribute__((always_inline)) {
+    R in[N], out[N];
+    R* buf = sb + le * CB + c * Q;
+#pragma unroll
+    for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 2>(i, j, m)];
+    diag_apply1d<N, AL, BE, 2>(in, out);
+#pragma unroll
+    for (int m = 0; m < N; ++m) buf[pidx<N, 2>(i, j, m)] = out[m];
+  });
+  __syncthreads();
+  pencil_jobs<N, EB, 3>([&](int le, int c, int i, int k) __attribute__((always_inline)) {
+    R in[N], out[N];
+    R* buf = sb + le * CB + c * Q;
+#pragma unroll
+    for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 1>(i, k, m)];
+    diag_apply1d<N, AL, BE, 1>(in, out);
+#pragma unroll
+    for (int m = 0; m < N; ++m) buf[pidx<N, 1>(i, k, m)] = out[m];
+  });
+  __syncthreads();
+  pencil_jobs<N, EB, 3>([&](int le, int c, int j, int k) __attribute__((always_inline)) {
+    R in[N], out[N];
+    R* buf = sb + le * CB + c * Q;
+    R* acc = sb + le * CB + (3 + c) * Q;
+#pragma unroll
+    for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 0>(j, k, m)];
+    diag_apply1d<N, AL, BE, 0>(in, out);
+#pragma unroll
+    for (int m = 0; m < N; ++m) acc[pidx<N, 0>(j, k, m)] += out[m];
+  });
+  __syncthreads();
+}
+
+template <int N, int EB, typename R, int S>
+__global__ void __launch_bounds__(EB * N * N * N) diag_kernel(KernelArgs<N, R> a) {
+  constexpr int Q = N * N * N;
+  constexpr int EBQ = EB * Q;
+  using ST = typename StoreOf<S>::T;
+  __shared__ R sb[EB * 6 * Q];
+  const int le = threadIdx.x / Q;
+  const int q = threadIdx.x - le * Q;
+  const int e0 = blockIdx.x * EB;
+  const int e = e0 + le;
+  const bool valid = e < a.L.n_cells;
+  const CellPos c0 = cell_pos(a.L, e0);
+  const ST* qd = static_cast<const ST*>(a.qdata) + static_cast<int64_t>(blockIdx.x) * 45 * EBQ;
+  R Dv[45];
+  R inv = R(1);
+  if constexpr (S == kStoreF16) {
+    if (valid) inv = R(1) / static_cast<R>(a.cscale[e]);
+  }
+#pragma unroll
+  for (int w = 0; w < 45; ++w) Dv[w] = valid ? static_cast<R>(load_val(qd + w * EBQ + threadIdx.x)) * inv : R(0);
+  R* cb = sb + le * 6 * Q;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) cb[(3 + c) * Q + q] = R(0);
+  diag_pair<N, EB, 0, 0>(sb, Dv, le, q);
+  diag_pair<N, EB, 1, 1>(sb, Dv, le, q);
+  diag_pair<N, EB, 2, 2>(sb, Dv, le, q);
+  diag_pair<N, EB, 0, 1>(sb, Dv, le, q);
+  diag_pair<N, EB, 0, 2>(sb, Dv, le, q);
+  diag_pair<N, EB, 1, 2>(sb, Dv, le, q);
+  if (!valid) return;
+  const Lattice& L = a.L;
+  const int i = q % N, j = (q / N) % N, k = q / (N * N);
+  constexpr int P = N - 1;
+  const CellPos cp = cell_advance(L, c0, le);
+  bool cons;
+  const int64_t node = node_of(L, cp, i, j, k, cons);
+  if (cons) return;
+  const bool inner = i > 0 && i < P && j > 0 && j < P && k > 0 && k < P;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const R v = cb[(3 + c) * Q + q];
+    R* dst = a.out + c * L.n_nodes + node;
+    if (inner)
+      *dst = v;
+    else
+      unsafeAtomicAdd(dst, v);
+  }
+}
+
 }  // namespace hx
