@@ -95,6 +95,13 @@ typedef struct {
                                x fastest; copied by hx_setup */
   uint32_t dirichlet_faces; /* bit f set: face f is constrained, f = 0..5 = -x,+x,-y,+y,-z,+z;
                                bits of periodic directions are ignored */
+  const double* frames;     /* HOST array [n_cells][3][3] or NULL: per cell the rows E1, E2, E3 of
+                               an orthonormal right-handed local frame (fibre frame of Section 3;
+                               cells in lattice order, x fastest); copied by hx_setup. With frames,
+                               the FIBER law's H4, H6, M4, M6 are components in the local frame,
+                               H_i = sum_ab H_i[a][b] E_a (x) E_b in each cell; NULL = the global
+                               axes. Ignored by the other laws. A frame that is not orthonormal
+                               to 1e-8 or not right-handed gives HX_E_ARG. */
 } hx_mesh;
 
 /* Material parameters (Section 3). cNH uses mu, lambda with Psi = mu/2 (I1 - 3 - 2 ln J) +

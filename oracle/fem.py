@@ -28,6 +28,8 @@ against an independent Voigt-notation stiffness; face resultant of a pressure on
 zero resultant on a closed surface; exact reproduction of polynomials by the transfers and
 J P = I).
 """
+import dataclasses
+
 import numpy as np
 
 from . import basis, material
@@ -74,13 +76,31 @@ class ElementTables:
 
 
 class Problem:
-    """A mesh, a material and the element tables; the operator evaluations act on (3, n_nodes)."""
+    """A mesh, a material and the element tables; the operator evaluations act on (3, n_nodes).
 
-    def __init__(self, mesh, mat, chunk=256):
+    cell_fibers: optional (H4 [E, 3, 3], H6, M4 [E, 3], M6) per cell (fibre law with fibre frames
+    that vary over the mesh); they replace the material's uniform tensors cell by cell.
+    """
+
+    def __init__(self, mesh, mat, chunk=256, cell_fibers=None):
         self.mesh = mesh
         self.mat = mat
         self.tab = ElementTables(mesh.p)
         self.chunk = chunk
+        self.cell_fibers = None
+        if cell_fibers is not None:
+            H4, H6, M4, M6 = (np.asarray(a, dtype=np.float64) for a in cell_fibers)
+            if H4.shape != (mesh.n_cells, 3, 3) or M4.shape != (mesh.n_cells, 3):
+                raise ValueError("cell_fibers must be ([E,3,3], [E,3,3], [E,3], [E,3])")
+            self.cell_fibers = (H4, H6, M4, M6)
+
+    def material_of(self, cells):
+        """The material seen by the q-points of ``cells`` (tensors shaped [E, 1, ...])."""
+        if self.cell_fibers is None:
+            return self.mat
+        H4, H6, M4, M6 = self.cell_fibers
+        return dataclasses.replace(self.mat, H4=H4[cells][:, None], H6=H6[cells][:, None],
+                                   M4=M4[cells][:, None], M6=M6[cells][:, None])
 
     # -- geometry -----------------------------------------------------------------------------
     def geometry(self, cells):
@@ -126,7 +146,7 @@ class Problem:
         for cells in self._chunks():
             F, _, wdet = self.deformation_gradient(u, cells)
             C = np.einsum("...ki,...kj->...ij", F, F)
-            total = total + np.sum(wdet * material.psi(C, self.mat))
+            total = total + np.sum(wdet * material.psi(C, self.material_of(cells)))
         return total
 
     def residual(self, u, cells=None, constrain=True):
@@ -135,7 +155,7 @@ class Problem:
         out = np.zeros((3, self.mesh.n_nodes), dtype=np.result_type(u.dtype, np.float64))
         for ch in self._chunks(cells):
             F, Gphi, wdet = self.deformation_gradient(u, ch)
-            P = material.first_pk(F, self.mat)
+            P = material.first_pk(F, self.material_of(ch))
             contrib = np.einsum("eq,eqcJ,eqaJ->eca", wdet, P, Gphi)
             self._scatter(out, ch, contrib)
         if constrain:
@@ -152,7 +172,7 @@ class Problem:
         out = np.zeros((3, self.mesh.n_nodes), dtype=np.result_type(u.dtype, du.dtype, np.float64))
         for ch in self._chunks(cells):
             F, Gphi, wdet = self.deformation_gradient(u, ch)
-            A = material.first_elasticity(F, self.mat)
+            A = material.first_elasticity(F, self.material_of(ch))
             G = np.einsum("eka,eqaL->eqkL", self._cell_values(du_f, ch), Gphi)
             Pdot = np.einsum("eqiJkL,eqkL->eqiJ", A, G)
             contrib = np.einsum("eq,eqcJ,eqaJ->eca", wdet, Pdot, Gphi)
@@ -171,7 +191,7 @@ class Problem:
         K = np.zeros((3 * nn, 3 * nn))
         for ch in self._chunks():
             F, Gphi, wdet = self.deformation_gradient(u, ch)
-            A = material.first_elasticity(F, self.mat)
+            A = material.first_elasticity(F, self.material_of(ch))
             Ke = np.einsum("eq,eqaJ,eqiJkL,eqbL->eiakb", wdet, Gphi, A, Gphi)
             nodes = self.mesh.cell_nodes[ch]
             for e in range(len(ch)):

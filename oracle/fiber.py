@@ -43,3 +43,14 @@ def structure_tensors(E1, E2, E3, phi, H11, H22, H33):
         Hs.append(H11 * np.outer(M1, M1) + H22 * np.outer(M2, M2) + H33 * np.outer(M3, M3))
         Ms.append(M1)
     return Hs[0], Hs[1], Ms[0], Ms[1]
+
+
+def cell_structure_tensors(frames, phi, H11, H22, H33):
+    """Per-cell (H4 [E,3,3], H6, M4 [E,3], M6) from local frames [E, 3, 3] (rows E1, E2, E3)."""
+    frames = np.asarray(frames, dtype=np.float64)
+    out = [np.zeros((len(frames), 3, 3)), np.zeros((len(frames), 3, 3)),
+           np.zeros((len(frames), 3)), np.zeros((len(frames), 3))]
+    for e, (E1, E2, E3) in enumerate(frames):
+        for k, t in enumerate(structure_tensors(E1, E2, E3, phi, H11, H22, H33)):
+            out[k][e] = t
+    return tuple(out)

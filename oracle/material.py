@@ -15,6 +15,9 @@ Laws (Section 3):
 Second Piola-Kirchhoff stress S = 2 dPsi/dC (Section 3, standard forms), fourth-order moduli
 CC = 4 d^2Psi/dCdC (appendix) and the first elasticity tensor A_iJkL = dP_iJ/dF_kL with P = F S.
 
+The structure tensors H_i [..., 3, 3] and directions M_i [..., 3] may carry leading dimensions that
+broadcast against those of F (fibre frames that vary from cell to cell).
+
 Reading of the appendix: the iNH second derivative is printed with the single term
 -mu/3 J^(-2/3) I (x) C^-1, which lacks major symmetry and disagrees with the directional
 derivative of Section 5 that the same appendix derives; differentiating Psi gives the symmetric
@@ -78,8 +81,8 @@ def psi(C, mat):
     J2 = detC
     out = 0.5 * mat.mu * (Jm23 * I1 - 3.0) + 0.25 * mat.kappa * (J2 - 1.0 - 2.0 * lnJ)
     for H, M in mat.families():
-        Ei = _ddot(np.broadcast_to(H, C.shape), C) - np.trace(H)
-        Istar = np.einsum("i,...ij,j->...", M, C, M)
+        Ei = _ddot(np.broadcast_to(H, C.shape), C) - np.trace(H, axis1=-2, axis2=-1)
+        Istar = np.einsum("...i,...ij,...j->...", M, C, M)
         term = mat.k1 / (2.0 * mat.k2) * (np.exp(mat.k2 * Ei ** 2) - 1.0)
         out = out + np.where(np.real(Istar) > 1.0, term, 0.0)
     return out
@@ -103,8 +106,8 @@ def second_pk(F, mat):
     c1 = 0.5 * mat.kappa * (J ** 2 - 1.0) - mat.mu / 3.0 * Jp * I1
     S = mat.mu * Jp[..., None, None] * I + c1[..., None, None] * Ci
     for H, M in mat.families():
-        Ei = _ddot(np.broadcast_to(H, C.shape), C) - np.trace(H)
-        Istar = np.einsum("i,...ij,j->...", M, C, M)
+        Ei = _ddot(np.broadcast_to(H, C.shape), C) - np.trace(H, axis1=-2, axis2=-1)
+        Istar = np.einsum("...i,...ij,...j->...", M, C, M)
         c3 = np.where(np.real(Istar) > 1.0, 2.0 * mat.k1 * np.exp(mat.k2 * Ei ** 2), 0.0)
         S = S + (c3 * Ei)[..., None, None] * H
     return S
@@ -129,11 +132,11 @@ def moduli(F, mat):
         + s(2.0 * mat.mu / 3.0 * Jp * I1 - mat.kappa * (J ** 2 - 1.0)) * CiCi_sym \
         + s(2.0 * mat.mu / 9.0 * Jp * I1 + mat.kappa * J ** 2) * CixCi
     for H, M in mat.families():
-        Ei = _ddot(np.broadcast_to(H, C.shape), C) - np.trace(H)
-        Istar = np.einsum("i,...ij,j->...", M, C, M)
+        Ei = _ddot(np.broadcast_to(H, C.shape), C) - np.trace(H, axis1=-2, axis2=-1)
+        Istar = np.einsum("...i,...ij,...j->...", M, C, M)
         coef = np.where(np.real(Istar) > 1.0,
                         4.0 * mat.k1 * np.exp(mat.k2 * Ei ** 2) * (2.0 * mat.k2 * Ei ** 2 + 1.0), 0.0)
-        CC = CC + s(coef) * np.einsum("ab,cd->abcd", H, H)
+        CC = CC + s(coef) * np.einsum("...ab,...cd->...abcd", H, H)
     return CC
 
 

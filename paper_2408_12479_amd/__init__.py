@@ -31,7 +31,7 @@ class HxError(RuntimeError):
 class _Mesh(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("periodic", ctypes.c_int32), ("vertices", ctypes.POINTER(ctypes.c_double)),
-                ("dirichlet_faces", ctypes.c_uint32)]
+                ("dirichlet_faces", ctypes.c_uint32), ("frames", ctypes.POINTER(ctypes.c_double))]
 
 
 class _Material(ctypes.Structure):
@@ -139,12 +139,20 @@ class Operator:
 
     def __init__(self, nx, ny, nz, vertices, p, law="cnh", mu=1.0, lam=0.0, kappa=0.0, k1=0.0,
                  k2=0.0, H4=None, H6=None, M4=None, M6=None, dirichlet_faces=(),
-                 periodic=(False, False, False), jpow_newton_iters=0):
+                 periodic=(False, False, False), jpow_newton_iters=0, frames=None):
+        """frames: optional [n_cells, 3, 3] local fibre frames (rows E1, E2, E3); H4..M6 are then
+        components in each cell's frame."""
         V = np.ascontiguousarray(vertices, dtype=np.float64)
         self._vert = V
+        fr = None
+        if frames is not None:
+            fr = np.ascontiguousarray(frames, dtype=np.float64)
+            if fr.shape != (int(nx) * int(ny) * int(nz), 3, 3):
+                raise ValueError("frames must have shape [n_cells, 3, 3]")
+        self._frames = fr
         mesh = _Mesh(int(nx), int(ny), int(nz),
                      int(sum(1 << d for d in range(3) if periodic[d])), _dptr(V),
-                     int(sum(1 << f for f in dirichlet_faces)))
+                     int(sum(1 << f for f in dirichlet_faces)), None if fr is None else _dptr(fr))
         mat = _Material()
         mat.law = LAWS[law]
         mat.mu, mat.lam, mat.kappa, mat.k1, mat.k2 = mu, lam, kappa, k1, k2

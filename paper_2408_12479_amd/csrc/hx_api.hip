@@ -292,6 +292,8 @@ HostArgs hx::args_for(const hx_ctx_s* c) {
   h.flag = c->flag;
   h.cblk64 = c->cblk64;
   h.cblk32 = c->cblk32;
+  h.fib64 = c->fib64;
+  h.fib32 = c->fib32;
   return h;
 }
 
@@ -319,6 +321,44 @@ void release_slot(Slot& s) {
   if (s.cscale) (void)hipFree(s.cscale);
   if (s.uk) (void)hipFree(s.uk);
   s = Slot();
+}
+
+// Per-cell structure tensors in global coordinates from the local frames (rows E1, E2, E3) and
+// the material's local components: H = Q^T H_loc Q and M = Q^T M_loc with Q[a][i] = (E_a)_i.
+// Output [cell][kFibWords] = H4 (9), H6 (9), M4 (3), M6 (3). False if a frame is not orthonormal
+// to 1e-8 or not right-handed.
+bool cell_fibers(const double* frames, int64_t cells, const hx_material& m, std::vector<double>& out) {
+  out.assign(static_cast<size_t>(cells) * kFibWords, 0.0);
+  for (int64_t e = 0; e < cells; ++e) {
+    const double* Q = frames + 9 * e;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        double d = 0.0;
+        for (int i = 0; i < 3; ++i) d += Q[3 * a + i] * Q[3 * b + i];
+        if (!(std::fabs(d - (a == b ? 1.0 : 0.0)) <= 1e-8)) return false;
+      }
+    const double det = Q[0] * (Q[4] * Q[8] - Q[5] * Q[7]) - Q[1] * (Q[3] * Q[8] - Q[5] * Q[6]) +
+                       Q[2] * (Q[3] * Q[7] - Q[4] * Q[6]);
+    if (!(det > 0.0)) return false;
+    double* o = out.data() + kFibWords * e;
+    const double* Hl[2] = {m.H4, m.H6};
+    const double* Ml[2] = {m.M4, m.M6};
+    for (int f = 0; f < 2; ++f) {
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          double v = 0.0;
+          for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) v += Q[3 * a + i] * Hl[f][3 * a + b] * Q[3 * b + j];
+          o[9 * f + 3 * i + j] = v;
+        }
+      for (int i = 0; i < 3; ++i) {
+        double v = 0.0;
+        for (int a = 0; a < 3; ++a) v += Q[3 * a + i] * Ml[f][a];
+        o[18 + 3 * f + i] = v;
+      }
+    }
+  }
+  return true;
 }
 
 }  // namespace
@@ -460,6 +500,21 @@ hx_status hx_setup(const hx_mesh* mesh, int32_t p, const hx_material* mat, const
     hx_destroy(c);
     return hip_fail(nullptr, e, "hx_setup: copy");
   }
+  if (mat->law == HX_LAW_FIBER && mesh->frames) {
+    std::vector<double> fib;
+    if (!cell_fibers(mesh->frames, cells, *mat, fib)) {
+      hx_destroy(c);
+      return fail(nullptr, HX_E_ARG, "hx_setup: a cell frame is not orthonormal and right-handed");
+    }
+    std::vector<float> fib32(fib.begin(), fib.end());
+    if ((e = hipMalloc(&c->fib64, fib.size() * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&c->fib32, fib.size() * sizeof(float))) != hipSuccess ||
+        (e = hipMemcpy(c->fib64, fib.data(), fib.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(c->fib32, fib32.data(), fib.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) {
+      hx_destroy(c);
+      return hip_fail(nullptr, e, "hx_setup: cell frames");
+    }
+  }
   HostArgs ha = args_for(c);
   if ((e = write_consts(p, ha)) != hipSuccess) {
     hx_destroy(c);
@@ -480,6 +535,8 @@ hx_status hx_destroy(hx_ctx ctx) {
   if (ctx->flag) (void)hipFree(ctx->flag);
   if (ctx->cblk64) (void)hipFree(ctx->cblk64);
   if (ctx->cblk32) (void)hipFree(ctx->cblk32);
+  if (ctx->fib64) (void)hipFree(ctx->fib64);
+  if (ctx->fib32) (void)hipFree(ctx->fib32);
   (void)hipSetDevice(cur);
   delete ctx;
   return HX_OK;

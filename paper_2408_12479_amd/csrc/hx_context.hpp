@@ -36,6 +36,8 @@ struct hx_ctx_s {
   int* flag = nullptr;
   void* cblk64 = nullptr;
   void* cblk32 = nullptr;
+  double* fib64 = nullptr;  // per-cell fibre tensors (frames given), else NULL
+  float* fib32 = nullptr;
   hx::Slot slot[2];  // 0: FP64 class, 1: FP32 class
   std::string err;
 };

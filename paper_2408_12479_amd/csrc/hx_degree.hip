@@ -63,9 +63,11 @@ KernelArgs<N, R> make_args(const HostArgs& h) {
   if constexpr (std::is_same<R, double>::value) {
     a.c = static_cast<const Consts<N, R>*>(h.cblk64);
     a.vert = h.vert64;
+    a.fib = h.fib64;
   } else {
     a.c = static_cast<const Consts<N, R>*>(h.cblk32);
     a.vert = h.vert32;
+    a.fib = h.fib32;
   }
   a.in0 = static_cast<const R*>(h.in0);
   a.in1 = static_cast<const R*>(h.in1);
@@ -194,7 +196,8 @@ hipError_t HX_CAT(dispatch_p, HX_DEGREE)(const HostOp& op, const HostArgs& h, hi
   switch (op.law) {
     case HX_LAW_CNH: return by_law<kCNH>(op, h, s, ok);
     case HX_LAW_INH: return by_law<kINH>(op, h, s, ok);
-    case HX_LAW_FIBER: return by_law<kFIBER>(op, h, s, ok);
+    case HX_LAW_FIBER:
+      return h.fib64 ? by_law<kFIBERC>(op, h, s, ok) : by_law<kFIBER>(op, h, s, ok);
   }
   *ok = false;
   return hipSuccess;

@@ -66,7 +66,11 @@ struct KernelArgs {
   const float* cscale;  // per-cell power-of-two scale of binary16 data
   float* cscale_w;
   int* flag;            // status bits (kFlagInverted | kFlagNonFinite)
+  const R* fib;         // per-cell fibre tensors [cell][kFibWords] (fibre law with cell frames)
 };
+
+// Per-cell fibre data: H4 (3x3), H6 (3x3), M4, M6 in global coordinates.
+constexpr int kFibWords = 24;
 
 constexpr int kFlagInverted = 1;
 constexpr int kFlagNonFinite = 2;
@@ -100,6 +104,8 @@ struct HostArgs {
   int* flag;
   void* cblk64;   // device block holding Consts<N, double>
   void* cblk32;   // device block holding Consts<N, float>
+  const double* fib64;  // per-cell fibre tensors, or NULL (material tensors everywhere)
+  const float* fib32;
 };
 
 // Words per q-point of each storage mode.

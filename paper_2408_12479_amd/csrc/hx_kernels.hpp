@@ -158,7 +158,21 @@ __device__ __forceinline__ R trilinear_geometry(const R* X, R s, R t, R r, R* K)
 // ------------------------------------------------------------------------------------------
 // Constitutive laws (Sections 3-5), material configuration, stable forms.
 // ------------------------------------------------------------------------------------------
-enum : int { kCNH = 0, kINH = 1, kFIBER = 2 };
+// kFIBERC: the fibre law with structure tensors that vary from cell to cell (local frames).
+enum : int { kCNH = 0, kINH = 1, kFIBER = 2, kFIBERC = 3 };
+
+template <int LAW>
+constexpr bool kIsFiber = LAW == kFIBER || LAW == kFIBERC;
+
+// Structure tensors H_4, H_6 and mean directions M_4, M_6 seen by one q-point: the material's
+// (uniform over the workgroup) or those of the thread's cell.
+template <typename R>
+struct Fib {
+  const R* H4;
+  const R* H6;
+  const R* M4;
+  const R* M6;
+};
 
 template <typename R>
 struct QState {
@@ -182,8 +196,8 @@ __device__ __forceinline__ void fiber_scalars(const MaterialK<R>& m, const R* Hf
 // E = (H + H^T + H^T H)/2, J - 1 from the invariants of H, C^-1 via F^-1.
 // Returns false when J <= 0. E is written to Eout (for the residual).
 template <int LAW, typename R>
-__device__ __forceinline__ bool state_from_H(const R* H, const MaterialK<R>& m, QState<R>& s,
-                                             R* E) {
+__device__ __forceinline__ bool state_from_H(const R* H, const MaterialK<R>& m,
+                                             const Fib<R>& fb, QState<R>& s, R* E) {
 #pragma unroll
   for (int i = 0; i < 9; ++i) s.F[i] = H[i];
   s.F[0] += R(1);
@@ -213,11 +227,11 @@ __device__ __forceinline__ bool state_from_H(const R* H, const MaterialK<R>& m, 
     const R I1 = R(3) + R(2) * (E[0] + E[4] + E[8]);
     s.c1 = R(0.5) * m.kappa * s.Jm * (s.Jm + R(2)) - m.mu / R(3) * s.Jp * I1;
     s.c2 = R(2) * m.mu / R(9) * s.Jp * I1 + m.kappa * J * J;
-    if constexpr (LAW == kFIBER) {
+    if constexpr (kIsFiber<LAW>) {
 #pragma unroll
       for (int f = 0; f < 2; ++f) {
-        const R* Hf = f == 0 ? m.H4 : m.H6;
-        const R* M = f == 0 ? m.M4 : m.M6;
+        const R* Hf = f == 0 ? fb.H4 : fb.H6;
+        const R* M = f == 0 ? fb.M4 : fb.M6;
         R Ei = R(0), mem = R(0);
 #pragma unroll
         for (int i = 0; i < 9; ++i) Ei += Hf[i] * E[i];
@@ -236,7 +250,7 @@ __device__ __forceinline__ bool state_from_H(const R* H, const MaterialK<R>& m, 
 // State from stored F^-1 and J - 1: F = J adj(F^-1).
 template <int LAW, typename R>
 __device__ __forceinline__ void state_from_finv(const R* Fi, R Jm, const MaterialK<R>& m,
-                                                QState<R>& s) {
+                                                const Fib<R>& fb, QState<R>& s) {
 #pragma unroll
   for (int i = 0; i < 9; ++i) s.Fi[i] = Fi[i];
   s.Jm = Jm;
@@ -254,7 +268,7 @@ __device__ __forceinline__ void state_from_finv(const R* Fi, R Jm, const Materia
     for (int i = 0; i < 9; ++i) I1 += s.F[i] * s.F[i];
     s.c1 = R(0.5) * m.kappa * Jm * (Jm + R(2)) - m.mu / R(3) * s.Jp * I1;
     s.c2 = R(2) * m.mu / R(9) * s.Jp * I1 + m.kappa * J * J;
-    if constexpr (LAW == kFIBER) {
+    if constexpr (kIsFiber<LAW>) {
       R C[9];
 #pragma unroll
       for (int i = 0; i < 3; ++i)
@@ -263,8 +277,8 @@ __device__ __forceinline__ void state_from_finv(const R* Fi, R Jm, const Materia
           C[3 * i + j] = s.F[i] * s.F[j] + s.F[3 + i] * s.F[3 + j] + s.F[6 + i] * s.F[6 + j];
 #pragma unroll
       for (int f = 0; f < 2; ++f) {
-        const R* Hf = f == 0 ? m.H4 : m.H6;
-        const R* M = f == 0 ? m.M4 : m.M6;
+        const R* Hf = f == 0 ? fb.H4 : fb.H6;
+        const R* M = f == 0 ? fb.M4 : fb.M6;
         R Ei = -(Hf[0] + Hf[4] + Hf[8]), mcm = R(0);
 #pragma unroll
         for (int i = 0; i < 9; ++i) Ei += Hf[i] * C[i];
@@ -284,7 +298,7 @@ __device__ __forceinline__ void state_from_finv(const R* Fi, R Jm, const Materia
 //   fibre adds sum_i c3 E_i F H_i
 template <int LAW, typename R>
 __device__ __forceinline__ void stress_P(const QState<R>& s, const R* E, const MaterialK<R>& m,
-                                         R* P) {
+                                         const Fib<R>& fb, R* P) {
   R Sv[9];
   if constexpr (LAW == kCNH) {
 #pragma unroll
@@ -309,10 +323,10 @@ __device__ __forceinline__ void stress_P(const QState<R>& s, const R* E, const M
 #pragma unroll
     for (int j = 0; j < 3; ++j)
       P[3 * i + j] = s.Fi[i] * Sv[j] + s.Fi[3 + i] * Sv[3 + j] + s.Fi[6 + i] * Sv[6 + j];
-  if constexpr (LAW == kFIBER) {
+  if constexpr (kIsFiber<LAW>) {
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
-      const R* Hf = f == 0 ? m.H4 : m.H6;
+      const R* Hf = f == 0 ? fb.H4 : fb.H6;
       const R c = s.c3[f] * s.Ei[f];
 #pragma unroll
       for (int i = 0; i < 3; ++i)
@@ -332,8 +346,8 @@ __device__ __forceinline__ void stress_P(const QState<R>& s, const R* E, const M
 //             + (c2 tr(F^-1 G) - 2mu/3 Jp F:G) F^-T
 //   fibre adds sum_i c3 [E_i G H_i + 2 (2 k2 E_i^2 + 1) ((F H_i):G) F H_i]
 template <int LAW, typename R>
-__device__ __forceinline__ void action(const QState<R>& s, const MaterialK<R>& m, const R* G,
-                                       R* Pd) {
+__device__ __forceinline__ void action(const QState<R>& s, const MaterialK<R>& m,
+                                       const Fib<R>& fb, const R* G, R* Pd) {
   // X = (F^-1 G)^T, Y = F^-T X = F^-T G^T F^-T, tr = tr(F^-1 G)
   R X[9];
 #pragma unroll
@@ -369,10 +383,10 @@ __device__ __forceinline__ void action(const QState<R>& s, const MaterialK<R>& m
       for (int j = 0; j < 3; ++j)
         Pd[3 * i + j] = a * G[3 * i + j] - s.c1 * Y[3 * i + j] - b * s.F[3 * i + j] +
                         c * s.Fi[3 * j + i];
-    if constexpr (LAW == kFIBER) {
+    if constexpr (kIsFiber<LAW>) {
 #pragma unroll
       for (int f = 0; f < 2; ++f) {
-        const R* Hf = f == 0 ? m.H4 : m.H6;
+        const R* Hf = f == 0 ? fb.H4 : fb.H6;
         R FH[9], GH[9];
 #pragma unroll
         for (int i = 0; i < 3; ++i)
@@ -776,6 +790,11 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
   }
 
   const MaterialK<R>& m = a.c->m;
+  Fib<R> fb{m.H4, m.H6, m.M4, m.M6};
+  if constexpr (LAW == kFIBERC) {
+    const R* f = a.fib + static_cast<int64_t>(valid ? e : e0) * kFibWords;
+    fb = Fib<R>{f, f + 9, f + 18, f + 21};
+  }
   if constexpr (KIND == 0 && MODE == HX_STORE_TANGENT) {
     // t = D g with the stored symmetric 9x9 tangent (45 planes, upper triangle row by row)
     const ST* qd = static_cast<const ST*>(a.qdata) + qblk;
@@ -815,7 +834,7 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
     if constexpr (MODE == HX_STORE_NONE) {
       R H[9], E[9];
       to_physical(g1, K, H);
-      state_from_H<LAW>(H, m, st, E);
+      state_from_H<LAW>(H, m, fb, st, E);
     } else {
       const ST* qd = static_cast<const ST*>(a.qdata) + qblk;
       R Fi[9], Jm;
@@ -828,19 +847,19 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
         for (int w = 0; w < 9; ++w) Fi[w] = R(w % 4 == 0);
         Jm = R(0);
       }
-      state_from_finv<LAW>(Fi, Jm, m, st);
+      state_from_finv<LAW>(Fi, Jm, m, fb, st);
     }
     R G[9], Pd[9];
     to_physical(g0, K, G);
-    action<LAW>(st, m, G, Pd);
+    action<LAW>(st, m, fb, G, Pd);
     to_reference(Pd, K, wdet, t);
   } else if constexpr (KIND == 1) {
     R K[9], H[9], E[9], P[9];
     const R wdet = valid ? qpoint_geometry(a, sv + le * 24, q, K) : R(0);
     to_physical(g0, K, H);
     QState<R> st;
-    state_from_H<LAW>(H, m, st, E);
-    stress_P<LAW>(st, E, m, P);
+    state_from_H<LAW>(H, m, fb, st, E);
+    stress_P<LAW>(st, E, m, fb, P);
     to_reference(P, K, wdet, t);
   } else {
     // linearisation update (always FP64 arithmetic)
@@ -848,7 +867,7 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
     const R wdet = valid ? qpoint_geometry(a, sv + le * 24, q, K) : R(0);
     to_physical(g0, K, H);
     QState<R> st;
-    const bool ok = state_from_H<LAW>(H, m, st, E);
+    const bool ok = state_from_H<LAW>(H, m, fb, st, E);
     int bad = 0;
     if (valid && !ok) bad |= kFlagInverted;
     ST* qw = static_cast<ST*>(a.qdata_w) + qblk;
@@ -874,7 +893,7 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
         for (int i = 0; i < 9; ++i) G[i] = R(0);
 #pragma unroll
         for (int J = 0; J < 3; ++J) G[3 * kk + J] = K[3 * bb + J];
-        action<LAW>(st, m, G, Pd);
+        action<LAW>(st, m, fb, G, Pd);
         to_reference(Pd, K, wdet, tc);
 #pragma unroll
         for (int r = 0; r < 9; ++r) Dm[9 * r + col] = tc[r];

@@ -105,6 +105,57 @@ def test_periodic_direction(device):
     op.close()
 
 
+def _random_frames(n, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        Q, R = np.linalg.qr(rng.standard_normal((3, 3)))
+        Q = Q * np.sign(np.diag(R))
+        if np.linalg.det(Q) < 0:
+            Q[:, 0] = -Q[:, 0]
+        out.append(Q)
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_cell_frames_tube(device, p):
+    """Fibre law with one local frame per cell (circumferential, axial, radial) on a ring."""
+    cells = (8, 2, 3)
+    tube = dict(r_in=1.0, wall=0.2, length=1.0, bend=0.3)
+    frames = workloads.tube_frames(*cells, length=1.0, bend=0.3)
+    op, pb = make_pair(cells, p, "fiber", faces=(4, 5), periodic=(True, False, False), tube=tube,
+                       frames=frames)
+    u, du = _inputs(op, pb)
+    X = pb.mesh.node_coords
+    z = X[:, 2]
+    u += 0.04 * z * (1.0 - z) * np.stack([X[:, 0], X[:, 1], np.zeros_like(z)])   # inflation: fibres in tension
+    u[:, pb.mesh.constrained] = 0.0
+    ud, dud, du32 = to_dev(u), to_dev(du), to_dev(du, "float32")
+    assert rel(to_host(op.residual(ud), op.num_nodes), pb.residual(u)) < TOL64
+    ref = pb.apply_tangent(u, du)
+    ref32 = pb.apply_tangent(u, du.astype(np.float32).astype(np.float64))
+    for mode in ["none", "finv_j", "tangent"]:
+        op.update_linearization(ud, mode=mode, precision="fp64")
+        assert rel(to_host(op.apply_tangent(dud), op.num_nodes), ref) < TOL64, mode
+        op.update_linearization(ud, mode=mode, precision="fp32")
+        y = to_host(op.apply_tangent(du32, precision="fp32"), op.num_nodes)
+        assert rel(y, ref32) < TOL32, (mode, rel(y, ref32))
+    op.close()
+
+
+def test_cell_frames_random_box(device):
+    """Random frames per cell at p = 4 (two cells per workgroup: frames differ inside a block)."""
+    op, pb = make_pair((3, 2, 2), 4, "fiber", faces=(0,), frames=_random_frames(12, 7))
+    u, du = _inputs(op, pb, scale=0.05)
+    ud, dud = to_dev(u), to_dev(du)
+    assert rel(to_host(op.residual(ud), op.num_nodes), pb.residual(u)) < TOL64
+    ref = pb.apply_tangent(u, du)
+    for mode in ["none", "finv_j", "tangent"]:
+        op.update_linearization(ud, mode=mode, precision="fp64")
+        assert rel(to_host(op.apply_tangent(dud), op.num_nodes), ref) < TOL64, mode
+    op.close()
+
+
 def test_fp32_newton_jpow_near_incompressible(device):
     """Algorithm 2 (3 Newton steps for J^-2/3) in its regime J in [0.95, 1.05]."""
     op, pb = make_pair((4, 2, 2), 3, "fiber", perturb=0.0, faces=(), lengths=(2.0, 1.0, 1.0),
@@ -172,6 +223,12 @@ def test_error_paths(device):
     with pytest.raises(hx.HxError) as ei:
         hx.Operator(1, 1, 1, workloads.box_vertices(1, 1, 1), 7)
     assert ei.value.name == "HX_E_UNSUPPORTED"
+    # cell frames must be orthonormal and right-handed
+    for bad in (2.0 * np.eye(3), np.diag([1.0, 1.0, -1.0])):
+        with pytest.raises(hx.HxError) as ei:
+            hx.Operator(1, 1, 1, workloads.box_vertices(1, 1, 1), 2, law="fiber", mu=1.0, kappa=10.0,
+                        frames=bad[None])
+        assert ei.value.name == "HX_E_ARG"
 
 
 def test_single_cell_all_degrees(device):

@@ -14,7 +14,7 @@ import torch
 
 import paper_2408_12479_amd as hx
 import workloads
-from oracle import fem, mesh as omesh
+from oracle import fem, fiber, mesh as omesh
 from tests.gpu_helpers import rel, to_dev, to_host
 from tests.helpers import make_material
 
@@ -22,20 +22,23 @@ pytestmark = pytest.mark.gpu
 
 
 def _levels(cells, degrees, law="cnh", faces=(0,), perturb=0.2, tube=None, periodic=(False, False, False),
-            **matkw):
+            frames=None, **matkw):
     nx, ny, nz = cells
     if tube is not None:
         V = workloads.tube_vertices(nx, ny, nz, **tube)
     else:
         V = workloads.box_vertices(nx, ny, nz, perturb=perturb, seed=2)
     mat = make_material(law, **matkw)
+    cell_fibers = None
+    if frames is not None:
+        cell_fibers = fiber.cell_structure_tensors(frames, np.deg2rad(45.0), *fiber.dispersion_coefficients(3.62, 34.3))
     ops, pbs = [], []
     for p in degrees:
         m = omesh.BoxMesh(nx, ny, nz, V, p, dirichlet_faces=faces, periodic=periodic)
-        pbs.append(fem.Problem(m, mat))
+        pbs.append(fem.Problem(m, mat, cell_fibers=cell_fibers))
         ops.append(hx.Operator(nx, ny, nz, V, p, law=law, mu=mat.mu, lam=mat.lam, kappa=mat.kappa, k1=mat.k1,
                                k2=mat.k2, H4=mat.H4, H6=mat.H6, M4=mat.M4, M6=mat.M6, dirichlet_faces=faces,
-                               periodic=periodic))
+                               periodic=periodic, frames=frames))
     return ops, pbs
 
 
@@ -165,10 +168,12 @@ def test_newton_solve_box(device, precision):
     mg.close()
 
 
-def test_newton_solve_pressurised_ring_mixed_matches_fp64(device):
+@pytest.mark.parametrize("law", ["inh", "fiber"])
+def test_newton_solve_pressurised_ring_mixed_matches_fp64(device, law):
     tube = dict(r_in=1.0, wall=0.2, length=1.0, bend=0.2)
-    ops, pbs = _levels((8, 2, 3), [2, 1], law="inh", faces=(4, 5), tube=tube, periodic=(True, False, False),
-                       mu=2.0, kappa=50.0)
+    frames = workloads.tube_frames(8, 2, 3, length=1.0, bend=0.2) if law == "fiber" else None
+    ops, pbs = _levels((8, 2, 3), [2, 1], law=law, faces=(4, 5), tube=tube, periodic=(True, False, False),
+                       frames=frames, mu=2.0, kappa=50.0)
     f = ops[0].surface_load(2, 0.05)
     sols = {}
     for precision in ["fp32", "fp64"]:

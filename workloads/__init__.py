@@ -174,6 +174,26 @@ def tube_vertices(n_theta, n_wall, n_axial, r_in=1.0, wall=0.2, length=10.0, ben
     return np.stack([X.ravel(), Y.ravel(), S.ravel()], axis=1)
 
 
+def tube_frames(n_theta, n_wall, n_axial, length=10.0, bend=1.0):
+    """Local fibre frames of the tube cells [cells, 3, 3] (rows E1, E2, E3, cells x fastest).
+
+    At each cell centre (angle and centreline parameter of the cell's middle): E2 is the unit
+    tangent of the centreline, E1 the circumferential direction of increasing angle made
+    orthogonal to E2, E3 = E1 x E2 (the outward radial direction for a straight tube).
+    """
+    th = -2.0 * np.pi * (np.arange(n_theta) + 0.5) / n_theta
+    s = length * (np.arange(n_axial) + 0.5) / n_axial
+    S, _, Th = np.meshgrid(s, np.arange(n_wall), th, indexing="ij")
+    S, Th = S.ravel(), Th.ravel()
+    t = np.stack([bend * np.pi / length * np.cos(np.pi * S / length), np.zeros_like(S), np.ones_like(S)], axis=1)
+    t /= np.linalg.norm(t, axis=1, keepdims=True)
+    e1 = np.stack([-np.sin(Th), np.cos(Th), np.zeros_like(Th)], axis=1)
+    e1 -= np.sum(e1 * t, axis=1, keepdims=True) * t
+    e1 /= np.linalg.norm(e1, axis=1, keepdims=True)
+    e3 = np.cross(e1, t)
+    return np.stack([e1, t, e3], axis=1)
+
+
 def random_direction(n_nodes, seed, mask=None):
     du = np.random.default_rng(seed).standard_normal((3, n_nodes))
     if mask is not None:
