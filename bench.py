@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cells", type=int, default=32)
+    ap.add_argument("--no-mg", action="store_true")
+    ap.add_argument("--no-newton", action="store_true")
+    ap.add_argument("--newton-cells", default="32,16,400")
     return ap.parse_args()
 
 
@@ -203,6 +206,11 @@ def main():
 
     if not args.no_fp32:
         extra["fiber_box_q3"] = fp32_study(hx, workloads, torch, dev, timer, args)
+    if not args.no_mg:
+        extra["tube_vcycle_p6321"] = mg_study(hx, workloads, torch, dev, timer)
+    if not args.no_newton:
+        cells = tuple(int(c) for c in args.newton_cells.split(","))
+        extra["tube_newton_q4"] = newton_study(hx, workloads, torch, dev, cells=cells)
 
     # roofline of the headline kernel
     ms = head["ms"]
@@ -270,6 +278,107 @@ def fp32_study(hx, workloads, torch, dev, timer, args):
             err = torch.linalg.norm(y.double() - yref).item() / nrm
             out[f"{prec}_{mode}"] = {"gdofs": op.num_dofs / ms / 1e6, "rel_err_vs_fp64": err}
     op.close()
+    return out
+
+
+TUBE = dict(r_in=1.0, wall=0.2, length=10.0, bend=1.0)
+TUBE_MAT = dict(law="fiber", mu=2.0, kappa=1e3, k1=1.0, k2=10.0)
+
+
+def tube_levels(hx, workloads, cells, degrees):
+    """Operators of the fibre-reinforced curved tube (periodic circumference, both ends clamped),
+    one per degree, with the circumferential/axial/radial frame of every cell."""
+    import math
+    V = workloads.tube_vertices(*cells, **TUBE)
+    frames = workloads.tube_frames(*cells, length=TUBE["length"], bend=TUBE["bend"])
+    H4, H6, M4, M6 = hx.fiber_structure(3.62, 34.3, math.radians(45.0))
+    return [hx.Operator(*cells, V, p, H4=H4, H6=H6, M4=M4, M6=M6, dirichlet_faces=(4, 5),
+                        periodic=(True, False, False), frames=frames, **TUBE_MAT) for p in degrees]
+
+
+def tube_inflation(op, amp=0.05):
+    """Radial displacement amp sin(pi s / L) (x - x_c(s)) that vanishes on the clamped ends."""
+    X = op.node_coords()
+    s = X[:, 2]
+    xc = TUBE["bend"] * np.sin(np.pi * s / TUBE["length"])
+    w = amp * np.sin(np.pi * s / TUBE["length"])
+    return np.stack([w * (X[:, 0] - xc), w * X[:, 1], np.zeros_like(s)])
+
+
+def mg_study(hx, workloads, torch, dev, timer, cells=(16, 8, 200), degrees=(6, 3, 2, 1), reps=20):
+    """FP32 p-multigrid V-cycle on the tube: graph-captured vs eager time per V-cycle, the storage
+    mode the autotuner picked per level, and the measured convergence factor of the stationary
+    iteration x <- x + M (b - K x) with the FP64 fine operator."""
+    ops = tube_levels(hx, workloads, cells, degrees)
+    u = tube_inflation(ops[0])
+    ud = torch.tensor(u.reshape(-1), dtype=torch.float64, device=dev)
+    n = ops[0].num_dofs
+    mask = np.tile(ops[0].constrained_mask(), 3)
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal(n)
+    b[mask] = 0.0
+    bd = torch.tensor(b, dtype=torch.float64, device=dev)
+    out = {"cells": list(cells), "degrees": list(degrees), "level_dofs": [op.num_dofs for op in ops]}
+    for use_graph in (True, False):
+        mg = hx.Multigrid(ops, precision="fp32", use_graph=use_graph, level_mode="auto")
+        t0 = time.perf_counter()
+        mg.update(ud)
+        t_upd = time.perf_counter() - t0
+        r32 = bd.float()
+        z = mg.vcycle(r32)
+        ms = timer.time(lambda: mg.vcycle(r32, z), reps)
+        key = "graph" if use_graph else "eager"
+        out[f"vcycle_ms_{key}"] = ms
+        if use_graph:
+            out["update_s"] = t_upd
+            out["level_modes"] = [mg.level_mode(l) for l in range(len(ops))]
+            out["lambda_max"] = [mg.lambda_max(l) for l in range(len(ops))]
+            ops[0].update_linearization(ud, mode="tangent", precision="fp64")
+            x = torch.zeros_like(bd)
+            r = bd.clone()
+            its = 8
+            for _ in range(its):
+                x += mg.vcycle(r.float()).double()
+                r = bd - ops[0].apply_tangent(x)
+            out["stationary_factor"] = (torch.linalg.norm(r).item() / np.linalg.norm(b)) ** (1.0 / its)
+        mg.close()
+        print(f"[bench] tube V-cycle ({key}): {ms:.2f} ms", file=sys.stderr, flush=True)
+    for op in ops:
+        op.close()
+    return out
+
+
+def newton_study(hx, workloads, torch, dev, cells=(32, 16, 400), degrees=(4, 2, 1), pressure=0.1, load_steps=5,
+                 rel_tol=1e-8, krylov_rel_tol=1e-3):
+    """Newton-Krylov solve of the pressurised tube: FP32 multigrid with FP64 outer CG (mixed) vs
+    the all-FP64 solve on the same GPU, each from u = 0 with the same load steps and tolerances."""
+    ops = tube_levels(hx, workloads, cells, degrees)
+    f = ops[0].surface_load(2, pressure)   # inner wall: lattice face -y
+    fd = torch.tensor(f.reshape(-1), dtype=torch.float64, device=dev)
+    out = {"cells": list(cells), "degrees": list(degrees), "dofs": ops[0].num_dofs, "pressure": pressure,
+           "load_steps": load_steps, "newton_rel_tol": rel_tol, "krylov_rel_tol": krylov_rel_tol}
+    sols = {}
+    for name, prec in (("mixed", "fp32"), ("fp64", "fp64")):
+        mg = hx.Multigrid(ops, precision=prec, level_mode="auto")
+        u = torch.zeros(ops[0].num_dofs, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = mg.newton_solve(u, fd, rel_tol=rel_tol, krylov_rel_tol=krylov_rel_tol, load_steps=load_steps,
+                              max_newton=30, max_krylov=1000, outer_mode="auto", check=False)
+        torch.cuda.synchronize()
+        rep["wall_s"] = time.perf_counter() - t0
+        rep["level_modes"] = [mg.level_mode(l) for l in range(len(ops))]
+        out[name] = rep
+        sols[name] = u
+        mg.close()
+        print(f"[bench] tube Newton ({name}): {rep['wall_s']:.1f} s, {rep['newton_iters']} Newton, "
+              f"{rep['krylov_iters']} CG, status {rep['status']}", file=sys.stderr, flush=True)
+    out["speedup_mixed_vs_fp64"] = out["fp64"]["wall_s"] / out["mixed"]["wall_s"]
+    out["rel_diff_mixed_vs_fp64"] = (torch.linalg.norm(sols["mixed"] - sols["fp64"]) /
+                                     torch.linalg.norm(sols["fp64"])).item()
+    out["max_displacement"] = sols["fp64"].abs().max().item()
+    for op in ops:
+        op.close()
     return out
 
 

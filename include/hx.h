@@ -72,7 +72,12 @@ typedef enum { HX_LAW_CNH = 0, HX_LAW_INH = 1, HX_LAW_FIBER = 2 } hx_law;
  *   TANGENT  the symmetric 9x9 tangent in reference coordinates, 45 words:
  *            D_(i a)(k b) = w_q detJ0 sum_{J,L} J0^-1_aJ A_iJkL J0^-1_bL, A = dP/dF,
  *            geometry and weight folded in; the apply is a 9x9 product per q-point. */
-typedef enum { HX_STORE_NONE = 0, HX_STORE_FINV_J = 1, HX_STORE_TANGENT = 2 } hx_storage;
+typedef enum {
+  HX_STORE_NONE = 0,
+  HX_STORE_FINV_J = 1,
+  HX_STORE_TANGENT = 2,
+  HX_STORE_AUTO = 255 /* only where a field says so: the mode is chosen by hx_autotune_storage */
+} hx_storage;
 
 /* Arithmetic of hx_apply_tangent and the type of its stored data.
  *   FP64             double vectors, double compute, double data
@@ -164,6 +169,16 @@ hx_status hx_update_linearization(hx_ctx ctx, const double* u, hx_storage mode,
 hx_status hx_apply_tangent(hx_ctx ctx, const void* du, void* dst, hx_precision prec,
                            void* stream);
 
+/* Autotuner of the storage strategy (Section 7.2: which strategy is fastest depends on the
+ * hardware, degree and law and has to be measured). For each of NONE, FINV_J and TANGENT:
+ * updates the slot of prec (HX_FP64 or HX_FP32) at u, applies once to warm up, then times `reps`
+ * applies (1..1000) of a fixed direction with HIP events on the stream. Leaves the slot
+ * linearised in the fastest mode, written to *best; ms_per_apply (HOST [3] or NULL) receives the
+ * mean time per apply of each mode in that order. Allocates two temporary device vectors and
+ * waits for the stream. Errors of the updates (HX_E_INVERTED, ...) are returned as they come. */
+hx_status hx_autotune_storage(hx_ctx ctx, const double* u, hx_precision prec, int32_t reps,
+                              hx_storage* best, double* ms_per_apply, void* stream);
+
 /* Bytes of per-q-point data held by a slot (0 before its first update). */
 int64_t hx_linearization_bytes(hx_ctx ctx, hx_precision prec);
 
@@ -186,16 +201,35 @@ typedef struct {
   int32_t smoother_degree; /* Chebyshev degree of the Jacobi smoother on all but the coarsest
                               level (default 4) */
   int32_t coarse_degree;   /* Chebyshev degree of the approximate coarse solve (default 30) */
-  double smoothing_range;  /* lambda_min = lambda_max / range (default 20) */
-  int32_t eig_iters;       /* power iterations for lambda_max of D^-1 A (default 20) */
+  double smoothing_range;  /* smoother interval [lambda_max / range, lambda_max] (default 20); the
+                              coarse Chebyshev solve extends it down to the smallest Ritz value */
+  int32_t eig_iters;       /* Lanczos (Jacobi-preconditioned CG) steps that estimate the extreme
+                              eigenvalues of D^-1 A (default 20) */
   double eig_safety;       /* the estimate is multiplied by this factor (default 1.2) */
   hx_precision precision;  /* HX_FP32: levels apply in FP32 with FP32 stored tangents (the
                               mixed-precision preconditioner); HX_FP64: everything in FP64 */
   int32_t use_graph;       /* 1: one V-cycle is captured into a HIP graph per update */
+  hx_storage level_mode;   /* storage mode of the level operators inside the V-cycle: NONE,
+                              FINV_J, TANGENT (default) or AUTO (hx_autotune_storage on each
+                              level at the first update; the choice is kept). The inverse
+                              diagonal always comes from a TANGENT update of the level. */
+  int32_t coarse_solver;   /* coarsest level: 0 = dense if it has at most 8192 DoFs, else
+                              Chebyshev (default); 1 = Chebyshev of coarse_degree; 2 = dense
+                              (HX_E_UNSUPPORTED above 8192 DoFs). Dense: the level operator is
+                              assembled by probing with 3 k_x k_y k_z coloured vectors, factored
+                              by Cholesky (rocSOLVER, FP64) at each update and applied as its
+                              explicit inverse. */
 } hx_mg_options;
 
-/* Builds a V-cycle over contexts on the same lattice with strictly decreasing degrees
- * (levels[0] finest). The contexts stay owned by the caller and must outlive the hierarchy.
+/* Fills *opt with the defaults listed above. */
+hx_status hx_mg_default_options(hx_mg_options* opt);
+
+/* Builds a V-cycle over contexts (levels[0] finest). Consecutive levels either share the
+ * lattice with a strictly lower degree (polynomial transfer), or both have degree 1 and the
+ * coarser lattice has half the cells in some directions and the same cells in the others
+ * (transfer in lattice reference space: the coarse trilinear basis at the fine nodes); Dirichlet
+ * faces and periodic directions must agree. The contexts stay owned by the caller and must
+ * outlive the hierarchy.
  * opt may be NULL (defaults). Levels store the TANGENT mode in the multigrid precision; with
  * HX_FP64 the finest level's FP64 slot is shared with the outer operator. */
 hx_status hx_mg_create(const hx_ctx* levels, int32_t n_levels, const hx_mg_options* opt,
@@ -213,6 +247,9 @@ hx_status hx_mg_update(hx_mg mg, const double* u, void* stream);
  * hierarchies and double for HX_FP64. */
 hx_status hx_mg_vcycle(hx_mg mg, const void* r, void* z, void* stream);
 int64_t hx_mg_vcycle_count(hx_mg mg);
+/* Storage mode the level operators of `level` use (the autotuner's choice with AUTO), or -1 for
+ * an invalid level or before the first update. */
+int32_t hx_mg_level_mode(hx_mg mg, int32_t level);
 double hx_mg_lambda_max(hx_mg mg, int32_t level);
 
 /* Transfers between level `level` (fine) and level + 1 (coarse), device vectors [3][n_nodes]:
@@ -235,12 +272,16 @@ typedef struct {
   double krylov_rel_tol;  /* inner flexible CG: ||b - K x|| <= rel * ||b|| */
   int32_t max_krylov;
   int32_t load_steps;     /* the external load is applied in this many equal increments */
-  hx_storage outer_mode;  /* storage mode of the FP64 outer operator (mixed precision only) */
+  hx_storage outer_mode;  /* storage mode of the FP64 outer operator with an FP32 hierarchy:
+                             NONE, FINV_J, TANGENT or AUTO (hx_autotune_storage at the first
+                             linearisation, kept for the solve). An FP64 hierarchy shares the
+                             finest level's data with the outer operator and ignores it. */
 } hx_newton_opts;
 
 typedef struct {
   int32_t newton_iters, krylov_iters, vcycles, load_steps_done;
   double initial_residual, final_residual, seconds;
+  int32_t outer_mode;     /* storage mode the outer FP64 operator used */
 } hx_newton_report;
 
 /* Solves r(u) = f_ext (Problem 2.1 with a dead load) by Newton's method with load stepping

@@ -19,14 +19,15 @@ Work proceeds over chunks of cells; arrays are the plain [cells, q-points, ...] 
 
 Also: the dead-load surface vector of a pressure on a boundary face, and the dense transfer
 matrices between two degrees on one lattice (prolongation = coarse basis at the fine nodes;
-interpolation of a fine field onto the coarse nodes).
+interpolation of a fine field onto the coarse nodes), and between two degree-1 lattices, one
+with half the cells in some directions (the same in lattice reference coordinates).
 
 Test infrastructure only. Pinned in tests/test_oracle_fem.py and tests/test_oracle_transfer.py
 (patch test, rigid rotation, translation invariance, residual = complex-step gradient of the
 energy, tangent = complex-step derivative of the residual, symmetry, linear elasticity at u = 0
 against an independent Voigt-notation stiffness; face resultant of a pressure on a planar face,
 zero resultant on a closed surface; exact reproduction of polynomials by the transfers and
-J P = I).
+J P = I; the Galerkin identity P^T K_fine P = K_coarse for nested lattices of an affine body).
 """
 import dataclasses
 
@@ -294,4 +295,61 @@ def interpolation_matrix(mesh_f, mesh_c):
             for j in range(nf):
                 for i in range(nf):
                     J[node, mesh_f.cell_nodes[e, i + nf * (j + nf * k)]] = vals[0][i] * vals[1][j] * vals[2][k]
+    return J
+
+
+def _lattice_factors(mesh_f, mesh_c):
+    if mesh_f.p != 1 or mesh_c.p != 1:
+        raise ValueError("lattice transfers act between degree-1 meshes")
+    fac = []
+    for nf, nc in zip((mesh_f.nx, mesh_f.ny, mesh_f.nz), (mesh_c.nx, mesh_c.ny, mesh_c.nz)):
+        if nf not in (nc, 2 * nc):
+            raise ValueError("each direction must keep or halve its cells")
+        fac.append(nf // nc)
+    return fac
+
+
+def _q1_row(mesh, pos):
+    """{node: weight} of the trilinear basis of ``mesh`` at lattice coordinates ``pos`` (cell units)."""
+    ncs = (mesh.nx, mesh.ny, mesh.nz)
+    cell, xi = [], []
+    for d in range(3):
+        c = min(int(np.floor(pos[d])), ncs[d] - 1)
+        cell.append(c)
+        xi.append(pos[d] - c)
+    e = cell[0] + mesh.nx * (cell[1] + mesh.ny * cell[2])
+    row = {}
+    for k in range(2):
+        for j in range(2):
+            for i in range(2):
+                w = (xi[0] if i else 1 - xi[0]) * (xi[1] if j else 1 - xi[1]) * (xi[2] if k else 1 - xi[2])
+                node = mesh.cell_nodes[e, i + 2 * (j + 2 * k)]
+                row[node] = row.get(node, 0.0) + w
+    return row
+
+
+def lattice_prolongation_matrix(mesh_f, mesh_c):
+    """Dense P [fine nodes, coarse nodes] between degree-1 meshes whose coarse lattice has half the
+    cells in some directions: the coarse trilinear basis evaluated at every fine node, the fine
+    node with lattice index I sitting at coarse lattice coordinate I / f (f = 1 or 2)."""
+    fac = _lattice_factors(mesh_f, mesh_c)
+    Nx, Ny, _ = mesh_f.ndims
+    P = np.zeros((mesh_f.n_nodes, mesh_c.n_nodes))
+    for node in range(mesh_f.n_nodes):
+        lat = (node % Nx, (node // Nx) % Ny, node // (Nx * Ny))
+        for cn, w in _q1_row(mesh_c, [lat[d] / fac[d] for d in range(3)]).items():
+            P[node, cn] += w
+    return P
+
+
+def lattice_interpolation_matrix(mesh_f, mesh_c):
+    """Dense J [coarse nodes, fine nodes]: the fine trilinear basis at every coarse node (coarse
+    lattice index I sits at fine lattice coordinate f I)."""
+    fac = _lattice_factors(mesh_f, mesh_c)
+    Nx, Ny, _ = mesh_c.ndims
+    J = np.zeros((mesh_c.n_nodes, mesh_f.n_nodes))
+    for node in range(mesh_c.n_nodes):
+        lat = (node % Nx, (node // Nx) % Ny, node // (Nx * Ny))
+        for fn, w in _q1_row(mesh_f, [lat[d] * fac[d] for d in range(3)]).items():
+            J[node, fn] += w
     return J

@@ -2,7 +2,7 @@
 
 Every operator evaluation runs in the HIP kernels of the library; torch provides device memory and
 streams. Importing the package loads the in-tree ``libhx.so`` and fails loudly if it is missing
-(build it with ``python -m paper_2408_12479_amd.build`` or ``__graft_entry__.build()``).
+(build it with ``python paper_2408_12479_amd/build.py`` or ``__graft_entry__.build()``).
 """
 import ctypes
 import os
@@ -17,7 +17,8 @@ HX_OK = 0
 STATUS = {0: "HX_OK", 1: "HX_E_ARG", 2: "HX_E_HIP", 3: "HX_E_NOMEM", 4: "HX_E_STATE", 5: "HX_E_INVERTED",
           6: "HX_E_NONFINITE", 7: "HX_E_NOT_CONVERGED", 8: "HX_E_UNSUPPORTED"}
 LAWS = {"cnh": 0, "inh": 1, "fiber": 2}
-MODES = {"none": 0, "finv_j": 1, "tangent": 2}
+MODES = {"none": 0, "finv_j": 1, "tangent": 2, "auto": 255}
+MODE_NAMES = {0: "none", 1: "finv_j", 2: "tangent", 255: "auto"}
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_bf16": 2, "fp32_fp16": 3}
 
 
@@ -48,7 +49,8 @@ class _Options(ctypes.Structure):
 class _MgOptions(ctypes.Structure):
     _fields_ = [("smoother_degree", ctypes.c_int32), ("coarse_degree", ctypes.c_int32),
                 ("smoothing_range", ctypes.c_double), ("eig_iters", ctypes.c_int32),
-                ("eig_safety", ctypes.c_double), ("precision", ctypes.c_int), ("use_graph", ctypes.c_int32)]
+                ("eig_safety", ctypes.c_double), ("precision", ctypes.c_int), ("use_graph", ctypes.c_int32),
+                ("level_mode", ctypes.c_int), ("coarse_solver", ctypes.c_int32)]
 
 
 class _NewtonOpts(ctypes.Structure):
@@ -61,12 +63,12 @@ class _NewtonReport(ctypes.Structure):
     _fields_ = [("newton_iters", ctypes.c_int32), ("krylov_iters", ctypes.c_int32),
                 ("vcycles", ctypes.c_int32), ("load_steps_done", ctypes.c_int32),
                 ("initial_residual", ctypes.c_double), ("final_residual", ctypes.c_double),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("outer_mode", ctypes.c_int32)]
 
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2408_12479_amd.build")
+        raise ImportError(f"{LIB_PATH} is not built; run python paper_2408_12479_amd/build.py")
     lib = ctypes.CDLL(LIB_PATH)
     vp, i64 = ctypes.c_void_p, ctypes.c_int64
     sig = {
@@ -82,6 +84,10 @@ def _load():
         "hx_update_linearization": (ctypes.c_int, [vp, vp, ctypes.c_int, ctypes.c_int, vp]),
         "hx_apply_tangent": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, vp]),
         "hx_linearization_bytes": (i64, [vp, ctypes.c_int]),
+        "hx_autotune_storage": (ctypes.c_int, [vp, vp, ctypes.c_int, ctypes.c_int32, ctypes.POINTER(ctypes.c_int),
+                                               ctypes.POINTER(ctypes.c_double), vp]),
+        "hx_mg_default_options": (ctypes.c_int, [ctypes.POINTER(_MgOptions)]),
+        "hx_mg_level_mode": (ctypes.c_int32, [vp, ctypes.c_int32]),
         "hx_fiber_structure": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double]
                                + [ctypes.POINTER(ctypes.c_double)] * 5),
         "hx_mg_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(_MgOptions),
@@ -223,6 +229,15 @@ class Operator:
     def linearization_bytes(self, precision="fp64"):
         return int(lib.hx_linearization_bytes(self.ctx, PRECISIONS[precision]))
 
+    def autotune_storage(self, u, precision="fp64", reps=10, stream=None):
+        """Runs the library's storage-mode autotuner at u: (best mode, {mode: ms per apply})."""
+        import torch
+        best = ctypes.c_int()
+        ms = np.zeros(3)
+        _check(lib.hx_autotune_storage(self.ctx, self._vec(u, torch.float64, "u"), PRECISIONS[precision], int(reps),
+                                       ctypes.byref(best), _dptr(ms), _stream_handle(stream)), self.ctx)
+        return MODE_NAMES[best.value], {"none": ms[0], "finv_j": ms[1], "tangent": ms[2]}
+
     def surface_load(self, face, pressure):
         """Dead-load pressure vector on a boundary face, host array (3, n_nodes)."""
         out = np.zeros(3 * self.num_nodes)
@@ -239,11 +254,14 @@ class Multigrid:
     """p-multigrid V-cycle over operators on the same lattice with decreasing degrees."""
 
     def __init__(self, levels, smoother_degree=4, coarse_degree=30, smoothing_range=20.0, eig_iters=20,
-                 eig_safety=1.2, precision="fp32", use_graph=True):
+                 eig_safety=1.2, precision="fp32", use_graph=True, level_mode="tangent", coarse_solver="auto"):
+        """levels: Operators, finest first (see hx_mg_create for the allowed level pairs).
+        coarse_solver: "auto" (dense up to 8192 DoFs), "chebyshev" or "dense"."""
         self.levels = list(levels)
         arr = (ctypes.c_void_p * len(self.levels))(*[op.ctx.value for op in self.levels])
         o = _MgOptions(int(smoother_degree), int(coarse_degree), float(smoothing_range), int(eig_iters),
-                       float(eig_safety), PRECISIONS[precision], int(bool(use_graph)))
+                       float(eig_safety), PRECISIONS[precision], int(bool(use_graph)), MODES[level_mode],
+                       {"auto": 0, "chebyshev": 1, "dense": 2}[coarse_solver])
         mg = ctypes.c_void_p()
         _check(lib.hx_mg_create(arr, len(self.levels), ctypes.byref(o), ctypes.byref(mg)))
         self.mg = mg
@@ -277,6 +295,10 @@ class Multigrid:
     def vcycle_count(self):
         return int(lib.hx_mg_vcycle_count(self.mg))
 
+    def level_mode(self, level):
+        m = int(lib.hx_mg_level_mode(self.mg, int(level)))
+        return MODE_NAMES.get(m)
+
     def lambda_max(self, level):
         return float(lib.hx_mg_lambda_max(self.mg, int(level)))
 
@@ -309,6 +331,7 @@ class Multigrid:
         st = lib.hx_newton_solve(self.mg, self.levels[0]._vec(u, torch.float64, "u"), f, ctypes.byref(o),
                                  ctypes.byref(rep), _stream_handle(stream))
         out = {k: getattr(rep, k) for k, _ in _NewtonReport._fields_}
+        out["outer_mode"] = MODE_NAMES.get(out["outer_mode"], out["outer_mode"])
         out["status"] = STATUS.get(st, st)
         if check:
             _check_mg(st, self.mg)

@@ -62,7 +62,7 @@ def build(jobs=None, verbose=False):
     objs = [os.path.join(BUILD, f"hx_p{p}.o") for p in DEGREES] + [os.path.join(BUILD, "hx_api.o"),
                                                                    os.path.join(BUILD, "hx_solver.o")]
     tmp = LIB + ".tmp"
-    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs)
+    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + ["-lrocsolver", "-lrocblas"])
     os.replace(tmp, LIB)
     if verbose:
         print(f"[build] linked {LIB}", flush=True)

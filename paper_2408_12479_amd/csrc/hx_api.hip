@@ -278,6 +278,13 @@ __global__ void init_output_kernel(R* __restrict__ out, const R* __restrict__ du
 
 __global__ void clear_flag(int* f) { *f = 0; }
 
+// A fixed non-trivial direction for timing runs: x_i = 1 + (i mod 7) / 8.
+template <typename T>
+__global__ void fill_timing_direction(T* __restrict__ x, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = T(1) + T(i % 7) * T(0.125);
+}
+
 int grid_for(int64_t n) {
   const int64_t b = (n + 255) / 256;
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(b, 8192)));
@@ -609,18 +616,18 @@ hx_status hx_update_linearization(hx_ctx ctx, const double* u, hx_storage mode, 
   const size_t need = static_cast<size_t>(mode_words(mode)) * padded_cells * Q * store_bytes(st);
   hipError_t e = hipStreamSynchronize(s);  // the slot's buffers may still be in use
   if (e != hipSuccess) return hip_fail(ctx, e, "hx_update_linearization: sync");
-  if (sl.qbytes != need || (need && !sl.qdata)) {
+  if (need > sl.qcap) {
     if (sl.qdata) (void)hipFree(sl.qdata);
     sl.qdata = nullptr;
-    sl.qbytes = 0;
-    if (need) {
-      if ((e = hipMalloc(&sl.qdata, need)) != hipSuccess) {
-        sl.valid = false;
-        return hip_fail(ctx, e, "hx_update_linearization: q-point data");
-      }
+    sl.qcap = 0;
+    if ((e = hipMalloc(&sl.qdata, need)) != hipSuccess) {
+      sl.valid = false;
+      sl.qbytes = 0;
+      return hip_fail(ctx, e, "hx_update_linearization: q-point data");
     }
-    sl.qbytes = need;
+    sl.qcap = need;
   }
+  sl.qbytes = need;
   if (st == kStoreF16 && !sl.cscale) {
     if ((e = hipMalloc(&sl.cscale, L.n_cells * sizeof(float))) != hipSuccess) {
       sl.valid = false;
@@ -689,6 +696,67 @@ hx_status hx_apply_tangent(hx_ctx ctx, const void* du, void* dst, hx_precision p
   e = dispatch(ctx->p, op, h, s, &ok);
   if (!ok) return fail(ctx, HX_E_UNSUPPORTED, "hx_apply_tangent: combination not built");
   if (e != hipSuccess) return hip_fail(ctx, e, "hx_apply_tangent: launch");
+  return HX_OK;
+}
+
+hx_status hx_autotune_storage(hx_ctx ctx, const double* u, hx_precision prec, int32_t reps,
+                              hx_storage* best, double* ms_per_apply, void* stream) {
+  if (!ctx || !u || !best) return fail(ctx, HX_E_ARG, "hx_autotune_storage: NULL argument");
+  if (prec != HX_FP64 && prec != HX_FP32)
+    return fail(ctx, HX_E_ARG, "hx_autotune_storage: precision must be HX_FP64 or HX_FP32");
+  if (reps < 1 || reps > 1000) return fail(ctx, HX_E_ARG, "hx_autotune_storage: reps out of [1, 1000]");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t n = 3 * ctx->L.n_nodes;
+  const size_t vb = n * (prec == HX_FP64 ? sizeof(double) : sizeof(float));
+  void* du = nullptr;
+  void* dst = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMalloc(&du, vb);
+  if (e == hipSuccess) e = hipMalloc(&dst, vb);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  auto cleanup = [&]() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (du) (void)hipFree(du);
+    if (dst) (void)hipFree(dst);
+  };
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_fail(ctx, e, "hx_autotune_storage: allocation");
+  }
+  if (prec == HX_FP64)
+    fill_timing_direction<double><<<grid_for(n), 256, 0, s>>>(static_cast<double*>(du), n);
+  else
+    fill_timing_direction<float><<<grid_for(n), 256, 0, s>>>(static_cast<float*>(du), n);
+  const hx_storage modes[3] = {HX_STORE_NONE, HX_STORE_FINV_J, HX_STORE_TANGENT};
+  double t[3] = {0.0, 0.0, 0.0};
+  int arg = 2;
+  for (int k = 0; k < 3; ++k) {
+    hx_status st = hx_update_linearization(ctx, u, modes[k], prec, stream);
+    if (st == HX_OK) st = hx_apply_tangent(ctx, du, dst, prec, stream);  // warm-up
+    if (st != HX_OK) {
+      cleanup();
+      return st;
+    }
+    e = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && st == HX_OK; ++r) st = hx_apply_tangent(ctx, du, dst, prec, stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (st != HX_OK || e != hipSuccess) {
+      cleanup();
+      return st != HX_OK ? st : hip_fail(ctx, e, "hx_autotune_storage: timing");
+    }
+    t[k] = ms / reps;
+    if (t[k] < t[arg] || k == 0) arg = k;
+  }
+  cleanup();
+  if (ms_per_apply)
+    for (int k = 0; k < 3; ++k) ms_per_apply[k] = t[k];
+  *best = modes[arg];
+  if (arg != 2) return hx_update_linearization(ctx, u, modes[arg], prec, stream);
   return HX_OK;
 }
 

@@ -14,7 +14,8 @@ struct Slot {
   hx_storage mode = HX_STORE_NONE;
   int store = kStoreF64;
   void* qdata = nullptr;
-  size_t qbytes = 0;
+  size_t qbytes = 0;   // bytes of the current mode's data
+  size_t qcap = 0;     // bytes allocated (kept across mode switches)
   float* cscale = nullptr;
   void* uk = nullptr;  // linearisation point (recompute mode): double or float
 };

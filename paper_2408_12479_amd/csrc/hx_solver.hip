@@ -4,12 +4,14 @@
 // polynomial embedding of the coarse space into the fine space (prolongation) and its transpose
 // (restriction); the linearisation point is moved down by interpolation at the coarse nodes.
 // Smoothing is Chebyshev-accelerated Jacobi with the inverse diagonal of the level operator
-// (computed matrix-free from the stored tangent) and a power-iteration estimate of the largest
-// eigenvalue; the coarsest level is solved approximately by a higher-degree Chebyshev iteration,
+// (computed matrix-free from the stored tangent) and Lanczos estimates of the extreme
+// eigenvalues; the coarsest level is solved approximately by a higher-degree Chebyshev iteration,
 // which keeps the V-cycle a fixed linear operator. The V-cycle runs in FP32 or FP64 and is
 // captured once per linearisation into a HIP graph. The outer Krylov solver is a flexible
 // preconditioned CG in FP64 on the finest FP64 operator.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
 
 #include <chrono>
 #include <cmath>
@@ -129,6 +131,73 @@ __global__ void k_hash_vector(T* x, Lattice L) {
     const T v = static_cast<T>(h & 0xffffff) / static_cast<T>(0x1000000) - T(0.5);
     x[i] = node_constrained(L, i % L.n_nodes) ? T(0) : v;
   }
+}
+
+// ---------------------------------------------------------------- dense coarse solve
+// Probe vector of colour class (cx, cy, cz) and component cc: 1 on the nodes whose lattice index
+// is congruent to the class modulo the colour counts (kx, ky, kz), 0 elsewhere.
+template <typename T>
+__global__ void k_probe(T* x, Lattice L, int kx, int ky, int kz, int cx, int cy, int cz, int cc) {
+  HX_GRID_LOOP(i, 3 * L.n_nodes) {
+    const int64_t node = i % L.n_nodes;
+    const int c = static_cast<int>(i / L.n_nodes);
+    const int I = static_cast<int>(node % L.Nx);
+    const int J = static_cast<int>((node / L.Nx) % L.Ny);
+    const int K = static_cast<int>(node / (static_cast<int64_t>(L.Nx) * L.Ny));
+    x[i] = (c == cc && I % kx == cx && J % ky == cy && K % kz == cz) ? T(1) : T(0);
+  }
+}
+
+// index in {I-1, I, I+1} (wrapped if periodic, skipped if outside) congruent to col mod k; -1 if none
+__device__ __forceinline__ int probe_hit(int I, int N, bool periodic, int k, int col) {
+  for (int d = -1; d <= 1; ++d) {
+    int J = I + d;
+    if (periodic) {
+      J = J < 0 ? J + N : (J >= N ? J - N : J);
+    } else if (J < 0 || J >= N) {
+      continue;
+    }
+    if (J % k == col) return J;
+  }
+  return -1;
+}
+
+// y = A x for a probe x: row i of A has its only entry of this colour class in the column of the
+// neighbour node of that class, so A[i][col(i)] = y[i]. A is column-major n x n (FP64).
+template <typename T>
+__global__ void k_probe_extract(const T* __restrict__ y, double* __restrict__ A, Lattice L, int kx, int ky,
+                                int kz, int cx, int cy, int cz, int cc) {
+  const int64_t n = 3 * L.n_nodes;
+  HX_GRID_LOOP(i, n) {
+    const int64_t node = i % L.n_nodes;
+    const int I = static_cast<int>(node % L.Nx);
+    const int J = static_cast<int>((node / L.Nx) % L.Ny);
+    const int K = static_cast<int>(node / (static_cast<int64_t>(L.Nx) * L.Ny));
+    const int a = probe_hit(I, L.Nx, L.Nx == L.nx, kx, cx);
+    const int b = probe_hit(J, L.Ny, L.Ny == L.ny, ky, cy);
+    const int c = probe_hit(K, L.Nz, L.Nz == L.nz, kz, cz);
+    if (a < 0 || b < 0 || c < 0) continue;
+    const int64_t col = cc * L.n_nodes + a + static_cast<int64_t>(L.Nx) * (b + static_cast<int64_t>(L.Ny) * c);
+    A[col * n + i] = static_cast<double>(y[i]);
+  }
+}
+
+__global__ void k_identity(double* B, int64_t n) {
+  HX_GRID_LOOP(i, n * n) B[i] = (i / n == i % n) ? 1.0 : 0.0;
+}
+
+// x = M b with the dense symmetric n x n matrix M (column j = row j): one wavefront per row.
+template <typename T>
+__global__ void __launch_bounds__(256) k_dense_mv(const T* __restrict__ M, const T* __restrict__ b,
+                                                  T* __restrict__ x, int64_t n) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  if (row >= n) return;
+  const T* m = M + row * n;
+  T acc = T(0);
+  for (int64_t j = lane; j < n; j += 64) acc += m[j] * b[j];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) x[row] = acc;
 }
 
 // ---------------------------------------------------------------- transfers between degrees
@@ -281,9 +350,136 @@ hipError_t transfer_nc(int nc, int kind, const void* in, void* out, const Lattic
   return hipErrorInvalidValue;
 }
 
+// ---------------------------------------------------------------- transfers between lattices
+// Two degree-1 lattices where the coarse one has half the cells in some directions (factor 2)
+// and the same cells in the others (factor 1). The coarse cell covers 2 fine cells per halved
+// direction; the coarse Q1 basis, evaluated at the fine node in the coarse cell's reference
+// coordinates, is 1 at coincident nodes and 1/2 at midpoints. The fine geometry is not required
+// to be the coarse geometry refined (curved bodies): the transfer lives in reference space.
+
+// coarse neighbours of fine node index I along one direction: a (weight wa), b (weight 1 - wa)
+__device__ __forceinline__ void h_up(int I, int fac, int Nc, bool periodic, int& a, int& b, bool& two) {
+  if (fac == 1 || (I & 1) == 0) {
+    a = fac == 1 ? I : I >> 1;
+    b = a;
+    two = false;
+    return;
+  }
+  a = (I - 1) >> 1;
+  b = a + 1;
+  if (periodic && b >= Nc) b -= Nc;
+  two = true;
+}
+
+template <typename T>
+__global__ void k_h_prolong_add(const T* __restrict__ xc, T* __restrict__ xf, Lattice Lf, Lattice Lc,
+                                int fx, int fy, int fz, int periodic) {
+  HX_GRID_LOOP(node, Lf.n_nodes) {
+    const int I = static_cast<int>(node % Lf.Nx);
+    const int J = static_cast<int>((node / Lf.Nx) % Lf.Ny);
+    const int K = static_cast<int>(node / (static_cast<int64_t>(Lf.Nx) * Lf.Ny));
+    int ia[2], ja[2], ka[2];
+    bool ti, tj, tk;
+    h_up(I, fx, Lc.Nx, periodic & 1, ia[0], ia[1], ti);
+    h_up(J, fy, Lc.Ny, periodic & 2, ja[0], ja[1], tj);
+    h_up(K, fz, Lc.Nz, periodic & 4, ka[0], ka[1], tk);
+    const T wi = ti ? T(0.5) : T(1), wj = tj ? T(0.5) : T(1), wk = tk ? T(0.5) : T(1);
+    T v[3] = {T(0), T(0), T(0)};
+    for (int c2 = 0; c2 < (tk ? 2 : 1); ++c2)
+      for (int b2 = 0; b2 < (tj ? 2 : 1); ++b2)
+        for (int a2 = 0; a2 < (ti ? 2 : 1); ++a2) {
+          const int64_t cn = ia[a2] + static_cast<int64_t>(Lc.Nx) * (ja[b2] + static_cast<int64_t>(Lc.Ny) * ka[c2]);
+          const T w = wi * wj * wk;
+          for (int c = 0; c < 3; ++c) v[c] += w * xc[c * Lc.n_nodes + cn];
+        }
+    for (int c = 0; c < 3; ++c) xf[c * Lf.n_nodes + node] += v[c];
+  }
+}
+
+// fine indices feeding coarse index Ic along one direction: f[0..cnt), weights w
+__device__ __forceinline__ int h_down(int Ic, int fac, int Nf, bool periodic, int* f, float* w) {
+  if (fac == 1) {
+    f[0] = Ic;
+    w[0] = 1.0f;
+    return 1;
+  }
+  int cnt = 0;
+  for (int d = -1; d <= 1; ++d) {
+    int I = 2 * Ic + d;
+    if (periodic) {
+      I = I < 0 ? I + Nf : (I >= Nf ? I - Nf : I);
+    } else if (I < 0 || I >= Nf) {
+      continue;
+    }
+    f[cnt] = I;
+    w[cnt] = d == 0 ? 1.0f : 0.5f;
+    ++cnt;
+  }
+  return cnt;
+}
+
+// rc += P^T rf, gathered per coarse node (no atomics); constrained coarse rows untouched
+template <typename T>
+__global__ void k_h_restrict_add(const T* __restrict__ rf, T* __restrict__ rc, Lattice Lf, Lattice Lc,
+                                 int fx, int fy, int fz, int periodic) {
+  HX_GRID_LOOP(node, Lc.n_nodes) {
+    if (node_constrained(Lc, node)) continue;
+    const int I = static_cast<int>(node % Lc.Nx);
+    const int J = static_cast<int>((node / Lc.Nx) % Lc.Ny);
+    const int K = static_cast<int>(node / (static_cast<int64_t>(Lc.Nx) * Lc.Ny));
+    int fi[3], fj[3], fk[3];
+    float wi[3], wj[3], wk[3];
+    const int ni = h_down(I, fx, Lf.Nx, periodic & 1, fi, wi);
+    const int nj = h_down(J, fy, Lf.Ny, periodic & 2, fj, wj);
+    const int nk = h_down(K, fz, Lf.Nz, periodic & 4, fk, wk);
+    T v[3] = {T(0), T(0), T(0)};
+    for (int c2 = 0; c2 < nk; ++c2)
+      for (int b2 = 0; b2 < nj; ++b2)
+        for (int a2 = 0; a2 < ni; ++a2) {
+          const int64_t fn = fi[a2] + static_cast<int64_t>(Lf.Nx) * (fj[b2] + static_cast<int64_t>(Lf.Ny) * fk[c2]);
+          const T w = static_cast<T>(wi[a2] * wj[b2] * wk[c2]);
+          for (int c = 0; c < 3; ++c) v[c] += w * rf[c * Lf.n_nodes + fn];
+        }
+    for (int c = 0; c < 3; ++c) rc[c * Lc.n_nodes + node] += v[c];
+  }
+}
+
+// uc = uf at the coarse nodes (every coarse node is a fine node)
+__global__ void k_h_inject(const double* __restrict__ uf, double* __restrict__ uc, Lattice Lf, Lattice Lc,
+                           int fx, int fy, int fz) {
+  HX_GRID_LOOP(node, Lc.n_nodes) {
+    const int64_t I = node % Lc.Nx;
+    const int64_t J = (node / Lc.Nx) % Lc.Ny;
+    const int64_t K = node / (static_cast<int64_t>(Lc.Nx) * Lc.Ny);
+    const int64_t fn = fx * I + Lf.Nx * (fy * J + Lf.Ny * (fz * K));
+    for (int c = 0; c < 3; ++c) uc[c * Lc.n_nodes + node] = uf[c * Lf.n_nodes + fn];
+  }
+}
+
+// coarsening factor per direction between two degree-1 lattices (1 or 2), 0 if not related
+int h_factor(int nf, int nc) { return nf == nc ? 1 : (nf == 2 * nc ? 2 : 0); }
+
+template <typename T>
+hipError_t h_transfer(int kind, const void* in, void* out, const Lattice& Lf, const Lattice& Lc, int periodic,
+                      hipStream_t s) {
+  const int fx = h_factor(Lf.nx, Lc.nx), fy = h_factor(Lf.ny, Lc.ny), fz = h_factor(Lf.nz, Lc.nz);
+  if (!fx || !fy || !fz) return hipErrorInvalidValue;
+  if (kind == 0)
+    k_h_prolong_add<T><<<grid_for(Lf.n_nodes), 256, 0, s>>>(static_cast<const T*>(in), static_cast<T*>(out), Lf, Lc,
+                                                            fx, fy, fz, periodic);
+  else if (kind == 1)
+    k_h_restrict_add<T><<<grid_for(Lc.n_nodes), 256, 0, s>>>(static_cast<const T*>(in), static_cast<T*>(out), Lf, Lc,
+                                                              fx, fy, fz, periodic);
+  else
+    k_h_inject<<<grid_for(Lc.n_nodes), 256, 0, s>>>(static_cast<const double*>(in), static_cast<double*>(out), Lf, Lc,
+                                                    fx, fy, fz);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t transfer(int kind, const void* in, void* out, const Lattice& Lf, const Lattice& Lc,
                     int periodic, hipStream_t s) {
+  if (Lf.p == 1 && Lc.p == 1) return h_transfer<T>(kind, in, out, Lf, Lc, periodic, s);
   const int nf = Lf.p + 1, nc = Lc.p + 1;
   switch (nf) {
     case 3: return transfer_nc<T, 3>(nc, kind, in, out, Lf, Lc, periodic, s);
@@ -330,7 +526,9 @@ struct hx_mg_s {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   // per level: b, x, t (operator output), d (Chebyshev direction), dinv; u (FP64 linearisation)
   std::vector<std::unique_ptr<DevBuf[]>> buf;
-  std::vector<double> lmax;
+  std::vector<double> lmax;   // Chebyshev upper bound: largest Ritz value times the safety factor
+  std::vector<double> lmin;   // smallest Ritz value
+  std::vector<int> mode;  // storage mode of each level's operator (-1 before the first update)
   DevBuf dots;  // 3 doubles
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -339,11 +537,19 @@ struct hx_mg_s {
   std::string err;
   // Newton / Krylov work vectors (FP64, finest level)
   DevBuf r, x, p, q, z, zold, f;
+  // dense coarse solve: the coarsest operator is assembled by probing, factored by Cholesky and
+  // kept as its explicit inverse (hierarchy precision)
+  bool dense = false;
+  rocblas_handle blas = nullptr;
+  DevBuf cA, cB, cinv, cinfo;
 };
 
 namespace {
 
 enum { B_B = 0, B_X, B_T, B_D, B_DINV, B_U, B_COUNT };
+
+// largest coarsest level (DoFs) that the dense coarse solve accepts
+constexpr int64_t kDenseCoarseMax = 8192;
 
 hx_status mg_fail(hx_mg mg, hx_status s, const std::string& m) {
   if (mg) mg->err = m;
@@ -363,7 +569,8 @@ hipError_t level_apply(hx_mg mg, int l, const T* x, T* y) {
 }
 
 // Chebyshev-Jacobi on level l: x <- approximately A^-1 b, degree `deg`, starting from x (zero_init:
-// from 0). Eigenvalue interval [lmax / range, lmax].
+// from 0). Eigenvalue interval [lmax / range, lmax] for smoothing; the coarse solve widens it down
+// to the smallest Ritz value (modes below the interval are still damped, never amplified).
 template <typename T>
 hipError_t chebyshev(hx_mg mg, int l, int deg, bool zero_init) {
   const hx_ctx c = mg->lv[l];
@@ -374,7 +581,9 @@ hipError_t chebyshev(hx_mg mg, int l, int deg, bool zero_init) {
   T* t = B[B_T].as<T>();
   T* d = B[B_D].as<T>();
   const T* dinv = B[B_DINV].as<T>();
-  const double lmax = mg->lmax[l], lmin = lmax / mg->opt.smoothing_range;
+  const bool coarse = l == static_cast<int>(mg->lv.size()) - 1;
+  const double lmax = mg->lmax[l];
+  const double lmin = coarse ? std::min(lmax / mg->opt.smoothing_range, mg->lmin[l]) : lmax / mg->opt.smoothing_range;
   const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
   const double sigma = theta / delta;
   double rho_old = 1.0 / sigma;
@@ -399,7 +608,15 @@ template <typename T>
 hipError_t vcycle_level(hx_mg mg, int l) {
   const int L = static_cast<int>(mg->lv.size());
   hipError_t e;
-  if (l == L - 1) return chebyshev<T>(mg, l, mg->opt.coarse_degree, true);
+  if (l == L - 1) {
+    if (!mg->dense) return chebyshev<T>(mg, l, mg->opt.coarse_degree, true);
+    const int64_t n = 3 * mg->lv[l]->L.n_nodes;
+    DevBuf* B = mg->buf[l].get();
+    const int64_t blocks = (n * 64 + 255) / 256;
+    k_dense_mv<T><<<static_cast<unsigned>(blocks), 256, 0, mg->stream>>>(mg->cinv.as<T>(), B[B_B].as<T>(),
+                                                                         B[B_X].as<T>(), n);
+    return hipGetLastError();
+  }
   if ((e = chebyshev<T>(mg, l, mg->opt.smoother_degree, true)) != hipSuccess) return e;
   const hx_ctx cf = mg->lv[l], cc = mg->lv[l + 1];
   DevBuf* Bf = mg->buf[l].get();
@@ -433,32 +650,132 @@ hipError_t dots(hx_mg mg, int64_t n, int npairs, const T* a0, const T* b0, const
   return read_dots(mg, npairs, host);
 }
 
-// largest eigenvalue of D^-1 A on level l by power iteration
+// Number of eigenvalues below x of the symmetric tridiagonal matrix (diagonal a, off-diagonal b),
+// by the Sturm sequence of its leading principal minors.
+int sturm_count(const std::vector<double>& a, const std::vector<double>& b, double x) {
+  int c = 0;
+  double q = a[0] - x;
+  if (q < 0.0) ++c;
+  for (size_t i = 1; i < a.size(); ++i) {
+    const double qp = q != 0.0 ? q : 1e-300;
+    q = a[i] - x - b[i - 1] * b[i - 1] / qp;
+    if (q < 0.0) ++c;
+  }
+  return c;
+}
+
+// k-th smallest eigenvalue (k = 0 .. m-1) of the tridiagonal matrix by bisection inside the
+// Gershgorin interval.
+double tridiag_eig(const std::vector<double>& a, const std::vector<double>& b, int k) {
+  double lo = 1e300, hi = -1e300;
+  for (size_t i = 0; i < a.size(); ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < a.size() ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(std::fabs(lo), std::fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (sturm_count(a, b, mid) > k) hi = mid; else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// Extreme eigenvalues of D^-1 A on level l: Lanczos through eig_iters steps of Jacobi-
+// preconditioned CG from a fixed pseudo-random start (zero on constrained rows). The Ritz values
+// of the CG tridiagonal matrix, T_kk = 1/alpha_k + beta_(k-1)/alpha_(k-1),
+// T_k,k+1 = sqrt(beta_k)/alpha_k, bound the spectrum from inside; the largest converges fast.
 template <typename T>
-hipError_t estimate_lmax(hx_mg mg, int l, double* out) {
+hipError_t estimate_spectrum(hx_mg mg, int l, double* lmax, double* lmin) {
   const hx_ctx c = mg->lv[l];
   const int64_t n = 3 * c->L.n_nodes;
   DevBuf* B = mg->buf[l].get();
-  T* v = B[B_X].as<T>();
-  T* w = B[B_T].as<T>();
+  T* r = B[B_B].as<T>();
+  T* z = B[B_X].as<T>();
+  T* q = B[B_T].as<T>();
+  T* p = B[B_D].as<T>();
   const T* dinv = B[B_DINV].as<T>();
-  k_hash_vector<T><<<grid_for(n), 256, 0, mg->stream>>>(v, c->L);
-  double h[3], lam = 0.0;
-  hipError_t e = dots<T>(mg, n, 1, v, v, nullptr, nullptr, nullptr, nullptr, h);
+  k_hash_vector<T><<<grid_for(n), 256, 0, mg->stream>>>(r, c->L);
+  k_cheb_first<T><<<grid_for(n), 256, 0, mg->stream>>>(z, z, r, nullptr, dinv, T(1), 1, n);
+  k_convert<T, T><<<grid_for(n), 256, 0, mg->stream>>>(z, p, n);
+  double h[3];
+  hipError_t e = dots<T>(mg, n, 1, r, z, nullptr, nullptr, nullptr, nullptr, h);
   if (e != hipSuccess) return e;
-  double nv = std::sqrt(h[0]);
-  for (int it = 0; it < mg->opt.eig_iters; ++it) {
-    if ((e = level_apply<T>(mg, l, v, w)) != hipSuccess) return e;
-    // w = dinv * w (the constrained identity rows keep eigenvalue 1)
-    k_cheb_first<T><<<grid_for(n), 256, 0, mg->stream>>>(w, B[B_D].as<T>(), w, nullptr, dinv, T(1), 1, n);
-    if ((e = dots<T>(mg, n, 1, w, w, nullptr, nullptr, nullptr, nullptr, h)) != hipSuccess) return e;
-    const double nw = std::sqrt(h[0]);
-    lam = nw / nv;
-    k_axpby<T><<<grid_for(n), 256, 0, mg->stream>>>(v, static_cast<T>(1.0 / nw), w, T(0), n);
-    nv = 1.0;
+  double rz = h[0];
+  std::vector<double> alpha, beta;
+  for (int it = 0; it < mg->opt.eig_iters && rz > 0.0; ++it) {
+    if ((e = level_apply<T>(mg, l, p, q)) != hipSuccess) return e;
+    if ((e = dots<T>(mg, n, 1, p, q, nullptr, nullptr, nullptr, nullptr, h)) != hipSuccess) return e;
+    if (!(h[0] > 0.0)) break;
+    const double a = rz / h[0];
+    k_axpby<T><<<grid_for(n), 256, 0, mg->stream>>>(r, static_cast<T>(-a), q, T(1), n);
+    k_cheb_first<T><<<grid_for(n), 256, 0, mg->stream>>>(z, z, r, nullptr, dinv, T(1), 1, n);
+    if ((e = dots<T>(mg, n, 1, r, z, nullptr, nullptr, nullptr, nullptr, h)) != hipSuccess) return e;
+    const double bta = h[0] / rz;
+    alpha.push_back(a);
+    beta.push_back(bta);
+    rz = h[0];
+    k_axpby<T><<<grid_for(n), 256, 0, mg->stream>>>(p, T(1), z, static_cast<T>(bta), n);
   }
-  *out = lam * mg->opt.eig_safety;
+  if (alpha.empty()) return hipErrorInvalidValue;
+  const size_t m = alpha.size();
+  std::vector<double> da(m), ob(m > 1 ? m - 1 : 0);
+  for (size_t k = 0; k < m; ++k) {
+    da[k] = 1.0 / alpha[k] + (k > 0 ? beta[k - 1] / alpha[k - 1] : 0.0);
+    if (k + 1 < m) ob[k] = std::sqrt(beta[k]) / alpha[k];
+  }
+  *lmax = tridiag_eig(da, ob, static_cast<int>(m) - 1);
+  *lmin = tridiag_eig(da, ob, 0);
   return hipGetLastError();
+}
+
+// smallest colour count >= 3 along a lattice direction that keeps probe columns apart: any k
+// >= 3 for an open direction (at most N), a divisor of N for a periodic one (so the wrap keeps
+// same-coloured nodes 3 or more indices apart)
+int probe_colours(int N, bool periodic) {
+  if (!periodic) return std::min(3, N);
+  for (int k = 3; k <= N; ++k)
+    if (N % k == 0) return k;
+  return N;
+}
+
+// Assembles the coarsest operator by probing (3 * kx * ky * kz applies), factors it by Cholesky
+// (rocSOLVER, FP64) and stores its inverse in the hierarchy precision.
+template <typename T>
+hx_status dense_coarse_update(hx_mg mg) {
+  const int l = static_cast<int>(mg->lv.size()) - 1;
+  const Lattice& L = mg->lv[l]->L;
+  const int64_t n = 3 * L.n_nodes;
+  DevBuf* B = mg->buf[l].get();
+  T* x = B[B_X].as<T>();
+  T* y = B[B_T].as<T>();
+  double* A = mg->cA.as<double>();
+  const int kx = probe_colours(L.Nx, L.Nx == L.nx), ky = probe_colours(L.Ny, L.Ny == L.ny),
+            kz = probe_colours(L.Nz, L.Nz == L.nz);
+  k_fill<double><<<grid_for(n * n), 256, 0, mg->stream>>>(A, 0.0, n * n);
+  for (int cc = 0; cc < 3; ++cc)
+    for (int cz = 0; cz < kz; ++cz)
+      for (int cy = 0; cy < ky; ++cy)
+        for (int cx = 0; cx < kx; ++cx) {
+          k_probe<T><<<grid_for(n), 256, 0, mg->stream>>>(x, L, kx, ky, kz, cx, cy, cz, cc);
+          if (level_apply<T>(mg, l, x, y) != hipSuccess) return HX_E_HIP;
+          k_probe_extract<T><<<grid_for(n), 256, 0, mg->stream>>>(y, A, L, kx, ky, kz, cx, cy, cz, cc);
+        }
+  k_identity<<<grid_for(n * n), 256, 0, mg->stream>>>(mg->cB.as<double>(), n);
+  if (hipGetLastError() != hipSuccess) return HX_E_HIP;
+  const rocblas_int nn = static_cast<rocblas_int>(n);
+  rocblas_int* info = mg->cinfo.as<rocblas_int>();
+  if (rocblas_set_stream(mg->blas, mg->stream) != rocblas_status_success ||
+      rocsolver_dpotrf(mg->blas, rocblas_fill_lower, nn, A, nn, info) != rocblas_status_success)
+    return HX_E_HIP;
+  rocblas_int h_info = 0;
+  if (hipMemcpyAsync(&h_info, info, sizeof(h_info), hipMemcpyDeviceToHost, mg->stream) != hipSuccess ||
+      hipStreamSynchronize(mg->stream) != hipSuccess)
+    return HX_E_HIP;
+  if (h_info != 0) return HX_E_NONFINITE;  // not positive definite
+  if (rocsolver_dpotrs(mg->blas, rocblas_fill_lower, nn, nn, A, nn, mg->cB.as<double>(), nn) != rocblas_status_success)
+    return HX_E_HIP;
+  k_convert<double, T><<<grid_for(n * n), 256, 0, mg->stream>>>(mg->cB.as<double>(), mg->cinv.as<T>(), n * n);
+  return hipGetLastError() == hipSuccess ? HX_OK : HX_E_HIP;
 }
 
 template <typename T>
@@ -495,31 +812,43 @@ hx_status hx_mg_create(const hx_ctx* levels, int32_t n_levels, const hx_mg_optio
     if (l > 0) {
       const Lattice& a = levels[l - 1]->L;
       const Lattice& b = levels[l]->L;
-      if (a.nx != b.nx || a.ny != b.ny || a.nz != b.nz || b.p >= a.p || a.dir_faces != b.dir_faces)
-        return HX_E_ARG;
+      const int pa = (a.Nx == a.nx * a.p ? 1 : 0) | (a.Ny == a.ny * a.p ? 2 : 0) | (a.Nz == a.nz * a.p ? 4 : 0);
+      const int pb = (b.Nx == b.nx * b.p ? 1 : 0) | (b.Ny == b.ny * b.p ? 2 : 0) | (b.Nz == b.nz * b.p ? 4 : 0);
+      if (a.dir_faces != b.dir_faces || pa != pb) return HX_E_ARG;
+      const bool same = a.nx == b.nx && a.ny == b.ny && a.nz == b.nz;
+      if (same) {
+        if (b.p >= a.p) return HX_E_ARG;  // degree transfer
+      } else {
+        // lattice transfer: degree 1 on both, every direction kept or halved
+        if (a.p != 1 || b.p != 1 || !h_factor(a.nx, b.nx) || !h_factor(a.ny, b.ny) || !h_factor(a.nz, b.nz))
+          return HX_E_ARG;
+      }
     }
   }
   hx_mg_s* mg = new (std::nothrow) hx_mg_s();
   if (!mg) return HX_E_NOMEM;
   mg->lv.assign(levels, levels + n_levels);
   hx_mg_options o{};
-  o.smoother_degree = 4;
-  o.coarse_degree = 30;
-  o.smoothing_range = 20.0;
-  o.eig_iters = 20;
-  o.eig_safety = 1.2;
-  o.precision = HX_FP32;
-  o.use_graph = 1;
+  hx_mg_default_options(&o);
   if (opt) {
     o = *opt;
+    const bool mode_ok = o.level_mode == HX_STORE_NONE || o.level_mode == HX_STORE_FINV_J ||
+                         o.level_mode == HX_STORE_TANGENT || o.level_mode == HX_STORE_AUTO;
     if (o.smoother_degree < 1 || o.coarse_degree < 1 || o.eig_iters < 1 || !(o.smoothing_range > 1.0) ||
-        !(o.eig_safety >= 1.0) || (o.precision != HX_FP32 && o.precision != HX_FP64)) {
+        !(o.eig_safety >= 1.0) || (o.precision != HX_FP32 && o.precision != HX_FP64) || !mode_ok ||
+        o.coarse_solver < 0 || o.coarse_solver > 2) {
       delete mg;
       return HX_E_ARG;
     }
   }
   mg->opt = o;
   mg->fp32 = o.precision == HX_FP32;
+  const int64_t n_coarse = 3 * levels[n_levels - 1]->L.n_nodes;
+  if (o.coarse_solver == 2 && n_coarse > kDenseCoarseMax) {
+    delete mg;
+    return HX_E_UNSUPPORTED;
+  }
+  mg->dense = o.coarse_solver == 2 || (o.coarse_solver == 0 && n_coarse <= kDenseCoarseMax);
   // periodic flags: recovered from the lattice (periodic direction has N = n p)
   const Lattice& L0 = levels[0]->L;
   mg->periodic = (L0.Nx == L0.nx * L0.p ? 1 : 0) | (L0.Ny == L0.ny * L0.p ? 2 : 0) | (L0.Nz == L0.nz * L0.p ? 4 : 0);
@@ -534,13 +863,43 @@ hx_status hx_mg_create(const hx_ctx* levels, int32_t n_levels, const hx_mg_optio
       e = mg->buf[l][k].alloc(b);
     }
   }
+  if (e == hipSuccess && mg->dense) {
+    const size_t nn = static_cast<size_t>(n_coarse) * n_coarse;
+    e = mg->cA.alloc(nn * sizeof(double));
+    if (e == hipSuccess) e = mg->cB.alloc(nn * sizeof(double));
+    if (e == hipSuccess) e = mg->cinv.alloc(nn * (mg->fp32 ? sizeof(float) : sizeof(double)));
+    if (e == hipSuccess) e = mg->cinfo.alloc(sizeof(rocblas_int));
+    if (e == hipSuccess && rocblas_create_handle(&mg->blas) != rocblas_status_success) e = hipErrorUnknown;
+  }
   mg->lmax.assign(n_levels, 1.0);
+  mg->lmin.assign(n_levels, 1.0);
+  mg->mode.assign(n_levels, -1);
   if (e != hipSuccess) {
     hx_mg_destroy(mg);
     return e == hipErrorOutOfMemory ? HX_E_NOMEM : HX_E_HIP;
   }
   *out = mg;
   return HX_OK;
+}
+
+hx_status hx_mg_default_options(hx_mg_options* o) {
+  if (!o) return HX_E_ARG;
+  *o = hx_mg_options{};
+  o->smoother_degree = 4;
+  o->coarse_degree = 30;
+  o->smoothing_range = 20.0;
+  o->eig_iters = 20;
+  o->eig_safety = 1.2;
+  o->precision = HX_FP32;
+  o->use_graph = 1;
+  o->level_mode = HX_STORE_TANGENT;
+  o->coarse_solver = 0;
+  return HX_OK;
+}
+
+int32_t hx_mg_level_mode(hx_mg mg, int32_t level) {
+  if (!mg || level < 0 || level >= static_cast<int32_t>(mg->mode.size())) return -1;
+  return mg->mode[level];
 }
 
 hx_status hx_mg_destroy(hx_mg mg) {
@@ -550,6 +909,7 @@ hx_status hx_mg_destroy(hx_mg mg) {
   if (mg->graph) (void)hipGraphDestroy(mg->graph);
   if (mg->ev_in) (void)hipEventDestroy(mg->ev_in);
   if (mg->ev_out) (void)hipEventDestroy(mg->ev_out);
+  if (mg->blas) (void)rocblas_destroy_handle(mg->blas);
   if (mg->stream) (void)hipStreamDestroy(mg->stream);
   delete mg;
   return HX_OK;
@@ -577,11 +937,32 @@ hx_status hx_mg_update(hx_mg mg, const double* u, void* stream) {
     if (st != HX_OK) return mg_fail(mg, st, std::string("hx_mg_update: level update: ") + hx_last_error(mg->lv[l]));
     e = mg->fp32 ? level_diagonal<float>(mg, l) : level_diagonal<double>(mg, l);
     if (e != hipSuccess) return mg_fail(mg, HX_E_HIP, "hx_mg_update: diagonal");
-    double lm = 1.0;
-    e = mg->fp32 ? estimate_lmax<float>(mg, l, &lm) : estimate_lmax<double>(mg, l, &lm);
+    // the level operator's own storage mode (the diagonal above needed the tangent)
+    hx_status sm = HX_OK;
+    if (mg->mode[l] < 0 && mg->opt.level_mode == HX_STORE_AUTO) {
+      hx_storage best = HX_STORE_TANGENT;
+      sm = hx_autotune_storage(mg->lv[l], mg->buf[l][B_U].as<double>(), mg_prec(mg), 5, &best, nullptr, mg->stream);
+      if (sm == HX_OK) mg->mode[l] = best;
+    } else {
+      if (mg->mode[l] < 0) mg->mode[l] = mg->opt.level_mode;
+      if (mg->mode[l] != HX_STORE_TANGENT)
+        sm = hx_update_linearization(mg->lv[l], mg->buf[l][B_U].as<double>(), static_cast<hx_storage>(mg->mode[l]),
+                                     mg_prec(mg), mg->stream);
+    }
+    if (sm != HX_OK) return mg_fail(mg, sm, std::string("hx_mg_update: level mode: ") + hx_last_error(mg->lv[l]));
+    double lm = 1.0, ln = 1.0;
+    e = mg->fp32 ? estimate_spectrum<float>(mg, l, &lm, &ln) : estimate_spectrum<double>(mg, l, &lm, &ln);
     if (e != hipSuccess) return mg_fail(mg, HX_E_HIP, "hx_mg_update: eigenvalue estimate");
-    if (!(lm > 0.0) || !std::isfinite(lm)) return mg_fail(mg, HX_E_NONFINITE, "hx_mg_update: eigenvalue estimate");
-    mg->lmax[l] = lm;
+    if (!(lm > 0.0) || !std::isfinite(lm) || !(ln > 0.0))
+      return mg_fail(mg, HX_E_NONFINITE, "hx_mg_update: eigenvalue estimate");
+    mg->lmax[l] = lm * mg->opt.eig_safety;
+    mg->lmin[l] = ln;
+  }
+  if (mg->dense) {
+    const hx_status sd = mg->fp32 ? dense_coarse_update<float>(mg) : dense_coarse_update<double>(mg);
+    if (sd != HX_OK)
+      return mg_fail(mg, sd, sd == HX_E_NONFINITE ? "hx_mg_update: coarse matrix not positive definite"
+                                                  : "hx_mg_update: dense coarse factorisation");
   }
   // capture one V-cycle (internal buffers only) into a graph
   if (mg->exec) {
@@ -723,6 +1104,10 @@ hx_status hx_newton_solve(hx_mg mg, double* u, const double* f_ext, const hx_new
     return hipGetLastError() == hipSuccess ? HX_OK : HX_E_HIP;
   };
   hx_status status = HX_OK;
+  const bool mode_ok = opt->outer_mode == HX_STORE_NONE || opt->outer_mode == HX_STORE_FINV_J ||
+                       opt->outer_mode == HX_STORE_TANGENT || opt->outer_mode == HX_STORE_AUTO;
+  if (!mode_ok) return mg_fail(mg, HX_E_ARG, "hx_newton_solve: unknown outer_mode");
+  int outer = opt->outer_mode == HX_STORE_AUTO ? -1 : opt->outer_mode;
   for (int step = 1; step <= opt->load_steps && status == HX_OK; ++step) {
     const double scale = static_cast<double>(step) / opt->load_steps;
     if ((status = residual(scale)) != HX_OK) break;
@@ -735,7 +1120,13 @@ hx_status hx_newton_solve(hx_mg mg, double* u, const double* f_ext, const hx_new
     while (!converged && it < opt->max_newton) {
       // linearisation of the outer FP64 operator and of every multigrid level
       if (mg->fp32) {
-        status = hx_update_linearization(fine, u, opt->outer_mode, HX_FP64, mg->stream);
+        if (outer < 0) {
+          hx_storage best = HX_STORE_TANGENT;
+          status = hx_autotune_storage(fine, u, HX_FP64, 5, &best, nullptr, mg->stream);
+          outer = best;
+        } else {
+          status = hx_update_linearization(fine, u, static_cast<hx_storage>(outer), HX_FP64, mg->stream);
+        }
         if (status != HX_OK) break;
       }
       if ((status = hx_mg_update(mg, u, mg->stream)) != HX_OK) break;
@@ -789,6 +1180,7 @@ hx_status hx_newton_solve(hx_mg mg, double* u, const double* f_ext, const hx_new
   }
   (void)hipStreamSynchronize(mg->stream);
   R.vcycles = mg->vcycles - vc0;
+  R.outer_mode = mg->fp32 ? outer : mg->mode[0];
   R.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (rep) *rep = R;
   (void)hipEventRecord(mg->ev_out, mg->stream);

@@ -188,3 +188,140 @@ def test_newton_solve_pressurised_ring_mixed_matches_fp64(device, law):
     for s in sols.values():
         assert np.linalg.norm(pbs[0].residual(s) - fo) < 1e-8 * np.linalg.norm(fo)
     assert rel(sols["fp32"], sols["fp64"]) < 1e-6
+
+
+def test_autotune_and_level_modes(device):
+    ops, pbs = _levels((3, 2, 2), [3, 1], law="fiber", faces=(0,))
+    u = _smooth_u(pbs[0])
+    ud = to_dev(u)
+    best, ms = ops[0].autotune_storage(ud, "fp64", reps=3)
+    assert best in ("none", "finv_j", "tangent") and all(v > 0.0 for v in ms.values())
+    assert ms[best] == min(ms.values())
+    # the context is left linearised in the chosen mode
+    rng = np.random.default_rng(12)
+    du = rng.standard_normal((3, ops[0].num_nodes))
+    assert rel(to_host(ops[0].apply_tangent(to_dev(du)), ops[0].num_nodes), pbs[0].apply_tangent(u, du)) < 1e-12
+    # level operators stored as F^-1, J give the same V-cycle as stored tangents (FP64)
+    w = rng.standard_normal((3, ops[0].num_nodes))
+    w[:, pbs[0].mesh.constrained] = 0.0
+    z = {}
+    for mode in ["tangent", "finv_j", "auto"]:
+        mg = hx.Multigrid(ops, precision="fp64", level_mode=mode)
+        mg.update(ud)
+        if mode != "auto":
+            assert mg.level_mode(0) == mode and mg.level_mode(1) == mode
+        else:
+            assert all(mg.level_mode(l) in ("none", "finv_j", "tangent") for l in range(2))
+        z[mode] = to_host(mg.vcycle(to_dev(w)), ops[0].num_nodes)
+        mg.close()
+    assert rel(z["finv_j"], z["tangent"]) < 1e-10
+    assert rel(z["auto"], z["tangent"]) < 1e-10
+
+
+def test_newton_outer_mode_auto(device):
+    ops, pbs = _levels((3, 2, 2), [2, 1], faces=(0,), mu=1.0, lam=10.0)
+    f = -ops[0].surface_load(1, 0.05)
+    mg = hx.Multigrid(ops, precision="fp32", level_mode="auto")
+    u = torch.zeros(ops[0].num_dofs, dtype=torch.float64, device="cuda")
+    rep = mg.newton_solve(u, to_dev(f), rel_tol=1e-9, krylov_rel_tol=1e-4, load_steps=1, outer_mode="auto")
+    assert rep["status"] == "HX_OK" and rep["outer_mode"] in ("none", "finv_j", "tangent")
+    fo = f.copy()
+    fo[:, pbs[0].mesh.constrained] = 0.0
+    assert np.linalg.norm(pbs[0].residual(to_host(u, ops[0].num_nodes)) - fo) < 1e-8 * np.linalg.norm(fo)
+    mg.close()
+
+
+def _operator(cells, V, p, law="cnh", faces=(0,), periodic=(False, False, False), frames=None, **matkw):
+    mat = make_material(law, **matkw)
+    m = omesh.BoxMesh(*cells, V, p, dirichlet_faces=faces, periodic=periodic)
+    cell_fibers = None
+    if frames is not None:
+        cell_fibers = fiber.cell_structure_tensors(frames, np.deg2rad(45.0), *fiber.dispersion_coefficients(3.62, 34.3))
+    op = hx.Operator(*cells, V, p, law=law, mu=mat.mu, lam=mat.lam, kappa=mat.kappa, k1=mat.k1, k2=mat.k2,
+                     H4=mat.H4, H6=mat.H6, M4=mat.M4, M6=mat.M6, dirichlet_faces=faces, periodic=periodic,
+                     frames=frames)
+    return op, fem.Problem(m, mat, cell_fibers=cell_fibers)
+
+
+def test_lattice_transfers_match_oracle(device):
+    rng = np.random.default_rng(21)
+    cases = [
+        ((4, 2, 4), (2, 1, 2), workloads.box_vertices(4, 2, 4, perturb=0.2, seed=2), workloads.box_vertices(2, 1, 2),
+         (0, 3), (False, False, False)),
+        ((8, 2, 4), (4, 2, 2), workloads.tube_vertices(8, 2, 4, length=1.0, bend=0.2),
+         workloads.tube_vertices(4, 2, 2, length=1.0, bend=0.2), (4, 5), (True, False, False)),
+    ]
+    for nf, nc, Vf, Vc, faces, per in cases:
+        opf, pbf = _operator(nf, Vf, 1, faces=faces, periodic=per)
+        opc, pbc = _operator(nc, Vc, 1, faces=faces, periodic=per)
+        mg = hx.Multigrid([opf, opc], precision="fp64")
+        P = fem.lattice_prolongation_matrix(pbf.mesh, pbc.mesh)
+        J = fem.lattice_interpolation_matrix(pbf.mesh, pbc.mesh)
+        n_f, n_c = opf.num_nodes, opc.num_nodes
+        xc, yf = rng.standard_normal((3, n_c)), rng.standard_normal((3, n_f))
+        out = torch.zeros(3 * n_f, dtype=torch.float64, device="cuda")
+        mg.transfer(0, 0, to_dev(xc), out)
+        assert rel(to_host(out, n_f), (P @ xc.T).T) < 1e-15
+        out = torch.zeros(3 * n_c, dtype=torch.float64, device="cuda")
+        mg.transfer(0, 1, to_dev(yf), out)
+        ref = (P.T @ yf.T).T
+        ref[:, pbc.mesh.constrained] = 0.0
+        assert rel(to_host(out, n_c), ref) < 1e-15
+        out = torch.zeros(3 * n_c, dtype=torch.float64, device="cuda")
+        mg.transfer(0, 2, to_dev(yf), out)
+        assert rel(to_host(out, n_c), (J @ yf.T).T) < 1e-15
+        mg.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_dense_coarse_solve_is_exact(device, precision):
+    # a one-level hierarchy is its coarse solve: z = K~^-1 r
+    V = workloads.tube_vertices(4, 2, 3, length=1.0, bend=0.2)
+    op, pb = _operator((4, 2, 3), V, 1, law="fiber", faces=(4,), periodic=(True, False, False),
+                       frames=workloads.tube_frames(4, 2, 3, length=1.0, bend=0.2))
+    u = _smooth_u(pb, scale=0.01)
+    u[:, pb.mesh.constrained] = 0.0
+    mg = hx.Multigrid([op], precision=precision, coarse_solver="dense")
+    mg.update(to_dev(u))
+    K = pb.tangent_matrix(u)
+    rng = np.random.default_rng(8)
+    r = rng.standard_normal((3, op.num_nodes))
+    r[:, pb.mesh.constrained] = 0.0
+    z = to_host(mg.vcycle(to_dev(r, "float32" if precision == "fp32" else "float64")), op.num_nodes)
+    ref = np.linalg.solve(K, r.ravel()).reshape(3, -1)
+    assert rel(z, ref) < (5e-4 if precision == "fp32" else 1e-10), rel(z, ref)
+    mg.close()
+
+
+def test_hp_hierarchy_vcycle_on_ring(device):
+    # degree levels 2 -> 1 on 8x2x4, then lattice levels 8x2x4 -> 4x2x2, dense coarse solve
+    tube = dict(length=1.0, bend=0.2)
+    V1 = workloads.tube_vertices(8, 2, 4, **tube)
+    V2 = workloads.tube_vertices(4, 2, 2, **tube)
+    kw = dict(law="inh", faces=(4, 5), periodic=(True, False, False), mu=2.0, kappa=50.0)
+    op0, pb0 = _operator((8, 2, 4), V1, 2, **kw)
+    op1, _ = _operator((8, 2, 4), V1, 1, **kw)
+    op2, _ = _operator((4, 2, 2), V2, 1, **kw)
+    mg = hx.Multigrid([op0, op1, op2], precision="fp64")
+    u = _smooth_u(pb0, scale=0.01)
+    u[:, pb0.mesh.constrained] = 0.0
+    mg.update(to_dev(u))
+    n = op0.num_nodes
+    rng = np.random.default_rng(9)
+    mask = pb0.mesh.constrained
+    w1, w2 = rng.standard_normal((2, 3, n))
+    w1[:, mask] = 0.0
+    w2[:, mask] = 0.0
+    z1 = to_host(mg.vcycle(to_dev(w1)), n)
+    z2 = to_host(mg.vcycle(to_dev(w2)), n)
+    a, b = np.vdot(w2, z1), np.vdot(w1, z2)
+    assert abs(a - b) < 1e-10 * (abs(a) + abs(b))
+    K = pb0.tangent_matrix(u)
+    bvec = rng.standard_normal(3 * n)
+    bvec[np.tile(mask, 3)] = 0.0
+    x = np.zeros(3 * n)
+    for _ in range(6):
+        x = x + to_host(mg.vcycle(to_dev((bvec - K @ x).reshape(3, n))), n).ravel()
+    factor = (np.linalg.norm(bvec - K @ x) / np.linalg.norm(bvec)) ** (1.0 / 6.0)
+    assert factor < 0.9, factor   # convergent stationary iteration (Chebyshev(4) smoothing)
+    mg.close()
