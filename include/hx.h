@@ -276,6 +276,7 @@ typedef struct {
                              NONE, FINV_J, TANGENT or AUTO (hx_autotune_storage at the first
                              linearisation, kept for the solve). An FP64 hierarchy shares the
                              finest level's data with the outer operator and ignores it. */
+  int32_t verbose;        /* 1: one progress line per Newton iteration on stderr */
 } hx_newton_opts;
 
 typedef struct {

@@ -56,7 +56,8 @@ class _MgOptions(ctypes.Structure):
 class _NewtonOpts(ctypes.Structure):
     _fields_ = [("newton_rel_tol", ctypes.c_double), ("newton_abs_tol", ctypes.c_double),
                 ("max_newton", ctypes.c_int32), ("krylov_rel_tol", ctypes.c_double),
-                ("max_krylov", ctypes.c_int32), ("load_steps", ctypes.c_int32), ("outer_mode", ctypes.c_int)]
+                ("max_krylov", ctypes.c_int32), ("load_steps", ctypes.c_int32), ("outer_mode", ctypes.c_int),
+                ("verbose", ctypes.c_int32)]
 
 
 class _NewtonReport(ctypes.Structure):
@@ -322,10 +323,10 @@ class Multigrid:
         return out
 
     def newton_solve(self, u, f_ext=None, rel_tol=1e-8, abs_tol=0.0, max_newton=20, krylov_rel_tol=1e-3,
-                     max_krylov=500, load_steps=1, outer_mode="tangent", stream=None, check=True):
+                     max_krylov=500, load_steps=1, outer_mode="tangent", stream=None, check=True, verbose=False):
         import torch
         o = _NewtonOpts(float(rel_tol), float(abs_tol), int(max_newton), float(krylov_rel_tol), int(max_krylov),
-                        int(load_steps), MODES[outer_mode])
+                        int(load_steps), MODES[outer_mode], int(bool(verbose)))
         rep = _NewtonReport()
         f = None if f_ext is None else self.levels[0]._vec(f_ext, torch.float64, "f_ext")
         st = lib.hx_newton_solve(self.mg, self.levels[0]._vec(u, torch.float64, "u"), f, ctypes.byref(o),

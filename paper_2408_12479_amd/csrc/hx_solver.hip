@@ -15,6 +15,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -1170,6 +1171,12 @@ hx_status hx_newton_solve(hx_mg mg, double* u, const double* f_ext, const hx_new
       rn = std::sqrt(h[0]);
       if (!std::isfinite(rn)) { status = HX_E_NONFINITE; break; }
       converged = rn <= std::max(opt->newton_abs_tol, opt->newton_rel_tol * r0);
+      if (opt->verbose) {
+        std::fprintf(stderr, "[hx_newton] load step %d/%d  Newton %d  CG %d  |r|/|r0| %.3e  %.2f s\n", step,
+                     opt->load_steps, it, k, rn / r0,
+                     std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+        std::fflush(stderr);
+      }
     }
     R.newton_iters += it;
     R.final_residual = rn;
