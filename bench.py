@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cells", type=int, default=32)
     ap.add_argument("--no-mg", action="store_true")
+    ap.add_argument("--no-stability", action="store_true")
     ap.add_argument("--no-newton", action="store_true")
     ap.add_argument("--newton-cells", default="32,16,400")
     return ap.parse_args()
@@ -123,16 +124,20 @@ def cpu_baseline(p, cells, budget_s=15.0):
 
 
 def measured_traffic(p, mode):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they match this source."""
-    path = os.path.join(ROOT, "profiles", f"apply_{mode}_p{p}_cube32_pmc.json")
+    """HBM bytes per apply from the committed rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE,
+    scaled by the plain copy kernel's reading), if they were taken on this kernel source."""
+    path = os.path.join(ROOT, "profiles", "apply_hbm_traffic_cube32.txt")
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path))
     src = os.path.join(ROOT, "paper_2408_12479_amd", "csrc", "hx_kernels.hpp")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if rec.get("kernel_src_sha256") != sha:
-        return None
-    return rec.get("hbm_bytes_per_launch")
+    for line in open(path):
+        if not line.startswith("traffic "):
+            continue
+        kv = dict(tok.split("=", 1) for tok in line.split()[1:])
+        if kv.get("p") == str(p) and kv.get("mode") == mode and kv.get("kernel_src_sha256") == sha:
+            return float(kv["hbm_bytes_per_apply"])
+    return None
 
 
 def main():
@@ -206,6 +211,8 @@ def main():
 
     if not args.no_fp32:
         extra["fiber_box_q3"] = fp32_study(hx, workloads, torch, dev, timer, args)
+    if not args.no_stability:
+        extra["forward_stability"] = stability_study(hx, workloads, torch)
     if not args.no_mg:
         extra["tube_vcycle_p6321"] = mg_study(hx, workloads, torch, dev, timer)
     if not args.no_newton:
@@ -278,6 +285,48 @@ def fp32_study(hx, workloads, torch, dev, timer, args):
             err = torch.linalg.norm(y.double() - yref).item() / nrm
             out[f"{prec}_{mode}"] = {"gdofs": op.num_dofs / ms / 1e6, "rel_err_vs_fp64": err}
     op.close()
+    return out
+
+
+def stability_study(hx, workloads, torch, n_scales=200, n_samples=1000):
+    """Forward-stability study (Section 7.1): for 200 strain scales from 1e-8 to 1e2 and 1000
+    samples each, the largest relative difference (Frobenius, per sample) between the FP32 and the
+    FP64 evaluation of P and of P' by the same forms: stable (the operator kernels' functions,
+    also with Algorithm 2 for J^-2/3) and standard."""
+    import math
+    H4, H6, M4, M6 = hx.fiber_structure(3.62, 34.3, math.radians(45.0))
+    materials = {"cnh": dict(mu=1.0, lam=10.0), "inh": dict(mu=2.0, kappa=50.0),
+                 "fiber": dict(mu=2.0, kappa=50.0, k1=1.0, k2=10.0, H4=H4, H6=H6, M4=M4, M6=M6)}
+    scales = np.logspace(-8, 2, n_scales)
+    out = {"scales": scales[::20].tolist() + [float(scales[-1])], "n_samples": n_samples,
+           "materials": {k: {a: b for a, b in v.items() if a[0] not in "HM"} for k, v in materials.items()}}
+    for law in ["cnh", "inh", "fiber"]:
+        kw = materials[law]
+        Hs, Gs = zip(*[workloads.stability_samples(sc, n_samples, seed=100 + i) for i, sc in enumerate(scales)])
+        H = torch.tensor(np.concatenate(Hs), dtype=torch.float64, device="cuda")
+        G = torch.tensor(np.concatenate(Gs), dtype=torch.float64, device="cuda")
+        res = {}
+        for form, jpow in [("stable", 0), ("stable", 3), ("standard", 0)]:
+            P64, dP64 = hx.qpoint_eval(H, G, law, form=form, precision="fp64", **kw)
+            P32, dP32 = hx.qpoint_eval(H, G, law, form=form, precision="fp32", jpow_newton_iters=jpow, **kw)
+
+            def rel(a, b):
+                # per scale: largest relative difference over the samples; None where the FP32
+                # evaluation overflowed (exp of the fibre law beyond the FP32 range)
+                e = torch.linalg.norm((a - b).reshape(-1, 9), dim=1) / torch.linalg.norm(b.reshape(-1, 9), dim=1)
+                e = e.reshape(n_scales, n_samples).max(dim=1).values.cpu().numpy()
+                return [float(x) if np.isfinite(x) else None for x in e]
+            key = form + ("_alg2" if jpow else "")
+            eP, edP = rel(P32, P64), rel(dP32, dP64)
+            fin = [i for i, sc in enumerate(scales) if sc <= 0.1]
+            res[key] = {"P": eP[::20] + [eP[-1]], "dP": edP[::20] + [edP[-1]],
+                        "P_max_scale_le_0.1": max(eP[i] for i in fin), "dP_max_scale_le_0.1": max(edP[i] for i in fin),
+                        "fp32_overflow_from_scale": next((float(sc) for sc, e in zip(scales, eP) if e is None), None)}
+        out[law] = res
+        print(f"[bench] stability {law}: FP32 vs FP64 up to strain 0.1: stable P/dP "
+              f"{res['stable']['P_max_scale_le_0.1']:.1e}/{res['stable']['dP_max_scale_le_0.1']:.1e}, standard "
+              f"{res['standard']['P_max_scale_le_0.1']:.1e}/{res['standard']['dP_max_scale_le_0.1']:.1e}",
+              file=sys.stderr, flush=True)
     return out
 
 

@@ -298,6 +298,24 @@ hx_status hx_newton_solve(hx_mg mg, double* u, const double* f_ext, const hx_new
  * (Section 2, Neumann term of the residual). f: HOST array [3][n_nodes], overwritten. */
 hx_status hx_surface_load(hx_ctx ctx, int32_t face, double pressure, double* f);
 
+/* ------------------------------------------------------------------------------------------
+ * Forward-stability study of the q-point functions (Section 7.1).
+ * ------------------------------------------------------------------------------------------ */
+/* For n displacement gradients H and directions G (device FP64 arrays [n][9], row-major 3x3),
+ * evaluates the first Piola-Kirchhoff stress P(I + H) and its directional derivative
+ * P'(H)[G] = G S + F D_u S[G] of the law in *mat (uniform fibre tensors), in the arithmetic of
+ * prec (HX_FP64, or HX_FP32 with H and G rounded to FP32 first):
+ *   form 0: the stable forms of Section 4, i.e. the functions the operator kernels evaluate (J - 1
+ *           from the invariants of H, E = (H + H^T + H^T H)/2, C^-1 via F^-1, log1p);
+ *   form 1: the standard forms of Section 3 (C = F^T F, J = det F, C^-1 by inverting C, ln J and
+ *           J^-2/3 from J, E = (C - I)/2).
+ * jpow_iters: FP32 J^-2/3 by Algorithm 2 with this many steps (0: cube root), as in hx_options;
+ * FP32 exp is the hardware base-2 exponential in both forms. P, dP: device FP64 [n][9].
+ * Asynchronous on the stream; HX_E_ARG for invalid arguments. */
+hx_status hx_qpoint_eval(const hx_material* mat, int32_t form, hx_precision prec, int32_t jpow_iters,
+                         int64_t n, const double* H, const double* G, double* P, double* dP,
+                         void* stream);
+
 const char* hx_last_error(hx_ctx ctx);
 const char* hx_status_string(hx_status s);
 

@@ -17,8 +17,9 @@ rounding order (Sections 2 and 6 of the paper: the same integrals, evaluated by 
   with p+1 points per direction, Lagrange elements on Gauss-Lobatto nodes.
 
 Modules: ``basis`` (1D rules), ``mesh`` (structured hex lattices), ``material`` (energies,
-stresses, tangent moduli), ``fem`` (geometry, residual, tangent, energy), ``fiber`` (fibre
-structure tensors).
+stresses, tangent moduli), ``fem`` (geometry, residual, tangent, energy, transfers), ``fiber``
+(fibre structure tensors), ``stability`` (80-digit stress and directional derivative for the
+forward-stability study).
 
 Parity status per function is listed in each module header. Every function here is pinned by a
 ``-m "not gpu"`` test in ``tests/test_oracle_*.py`` against something other than itself
@@ -26,4 +27,4 @@ Parity status per function is listed in each module header. Every function here 
 tests, the worked example of the fibre-parameter table).
 """
 
-from . import basis, fiber, material, mesh, fem  # noqa: F401
+from . import basis, fiber, material, mesh, fem, stability  # noqa: F401

@@ -104,6 +104,8 @@ def _load():
         "hx_newton_solve": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(_NewtonOpts),
                                            ctypes.POINTER(_NewtonReport), vp]),
         "hx_surface_load": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
+        "hx_qpoint_eval": (ctypes.c_int, [ctypes.POINTER(_Material), ctypes.c_int32, ctypes.c_int, ctypes.c_int32,
+                                          i64, vp, vp, vp, vp, vp]),
         "hx_last_error": (ctypes.c_char_p, [vp]),
         "hx_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     }
@@ -135,6 +137,34 @@ def fiber_structure(a, b, phi, E=None):
     return H4.reshape(3, 3), H6.reshape(3, 3), M4, M6
 
 
+def _material(law, mu=1.0, lam=0.0, kappa=0.0, k1=0.0, k2=0.0, H4=None, H6=None, M4=None, M6=None):
+    mat = _Material()
+    mat.law = LAWS[law]
+    mat.mu, mat.lam, mat.kappa, mat.k1, mat.k2 = mu, lam, kappa, k1, k2
+    for name, val, n in (("H4", H4, 9), ("H6", H6, 9), ("M4", M4, 3), ("M6", M6, 3)):
+        arr = np.zeros(n) if val is None else np.asarray(val, dtype=np.float64).ravel()
+        getattr(mat, name)[:] = arr.tolist()
+    return mat
+
+
+def qpoint_eval(H, G, law, form="stable", precision="fp64", jpow_newton_iters=0, stream=None, **mat):
+    """P(I + H) and P'(H)[G] for batches H, G (CUDA FP64 tensors [n, 3, 3]) through
+    hx_qpoint_eval: returns (P, dP) as CUDA FP64 tensors [n, 3, 3]."""
+    import torch
+    for t in (H, G):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+            raise TypeError("H and G must be contiguous CUDA float64 tensors")
+    if H.shape != G.shape or H.shape[-2:] != (3, 3):
+        raise ValueError("H and G must have shape [n, 3, 3]")
+    n = H.shape[0]
+    P, dP = torch.empty_like(H), torch.empty_like(H)
+    m = _material(law, **mat)
+    _check(lib.hx_qpoint_eval(ctypes.byref(m), {"stable": 0, "standard": 1}[form], PRECISIONS[precision],
+                              int(jpow_newton_iters), n, ctypes.c_void_p(H.data_ptr()), ctypes.c_void_p(G.data_ptr()),
+                              ctypes.c_void_p(P.data_ptr()), ctypes.c_void_p(dP.data_ptr()), _stream_handle(stream)))
+    return P, dP
+
+
 def _stream_handle(stream):
     import torch
     s = torch.cuda.current_stream() if stream is None else stream
@@ -160,12 +190,7 @@ class Operator:
         mesh = _Mesh(int(nx), int(ny), int(nz),
                      int(sum(1 << d for d in range(3) if periodic[d])), _dptr(V),
                      int(sum(1 << f for f in dirichlet_faces)), None if fr is None else _dptr(fr))
-        mat = _Material()
-        mat.law = LAWS[law]
-        mat.mu, mat.lam, mat.kappa, mat.k1, mat.k2 = mu, lam, kappa, k1, k2
-        for name, val, n in (("H4", H4, 9), ("H6", H6, 9), ("M4", M4, 3), ("M6", M6, 3)):
-            arr = np.zeros(n) if val is None else np.asarray(val, dtype=np.float64).ravel()
-            getattr(mat, name)[:] = arr.tolist()
+        mat = _material(law, mu, lam, kappa, k1, k2, H4, H6, M4, M6)
         opt = _Options()
         opt.jpow_newton_iters = int(jpow_newton_iters)
         ctx = ctypes.c_void_p()

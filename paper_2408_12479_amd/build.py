@@ -50,6 +50,8 @@ def build(jobs=None, verbose=False):
                    "-o", os.path.join(BUILD, "hx_api.o")], "api"))
     units.append(([hipcc] + FLAGS + ["-c", os.path.join(CSRC, "hx_solver.hip"),
                    "-o", os.path.join(BUILD, "hx_solver.o")], "solver"))
+    units.append(([hipcc] + FLAGS + ["-c", os.path.join(CSRC, "hx_stability.hip"),
+                   "-o", os.path.join(BUILD, "hx_stability.o")], "stability"))
     jobs = jobs or min(len(units), max(1, os.cpu_count() or 1), 16)
     with cf.ThreadPoolExecutor(jobs) as ex:
         futs = {ex.submit(_run, cmd): name for cmd, name in units}
@@ -59,8 +61,8 @@ def build(jobs=None, verbose=False):
                 print(f"[build] {futs[f]} done", flush=True)
                 if out.strip():
                     print(out)
-    objs = [os.path.join(BUILD, f"hx_p{p}.o") for p in DEGREES] + [os.path.join(BUILD, "hx_api.o"),
-                                                                   os.path.join(BUILD, "hx_solver.o")]
+    objs = [os.path.join(BUILD, f"hx_p{p}.o") for p in DEGREES] + [
+        os.path.join(BUILD, n) for n in ("hx_api.o", "hx_solver.o", "hx_stability.o")]
     tmp = LIB + ".tmp"
     _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + ["-lrocsolver", "-lrocblas"])
     os.replace(tmp, LIB)

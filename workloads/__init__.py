@@ -194,6 +194,23 @@ def tube_frames(n_theta, n_wall, n_axial, length=10.0, bend=1.0):
     return np.stack([e1, t, e3], axis=1)
 
 
+def stability_samples(scale, n, seed):
+    """Displacement gradients for the forward-stability study: every entry uniform in
+    [scale/10, scale] with a random sign (the band below scale/10 left out so the sample has the
+    intended order of magnitude); samples with det(I + H) <= 0 are drawn again. Also a direction
+    G with entries uniform in [-1, 1]. Returns (H [n, 3, 3], G [n, 3, 3])."""
+    rng = np.random.default_rng(seed)
+    out = np.zeros((0, 3, 3))
+    while len(out) < n:
+        mag = rng.uniform(scale / 10.0, scale, size=(2 * n, 3, 3))
+        sign = np.where(rng.random((2 * n, 3, 3)) < 0.5, -1.0, 1.0)
+        H = mag * sign
+        ok = np.linalg.det(np.eye(3) + H) > 0.0
+        out = np.concatenate([out, H[ok]])
+    G = rng.uniform(-1.0, 1.0, size=(n, 3, 3))
+    return out[:n], G
+
+
 def random_direction(n_nodes, seed, mask=None):
     du = np.random.default_rng(seed).standard_normal((3, n_nodes))
     if mask is not None:
