@@ -36,6 +36,12 @@ __device__ __forceinline__ float load_val(const bf16_t* p) {
 }
 __device__ __forceinline__ float load_val(const _Float16* p) { return static_cast<float>(*p); }
 
+// stored word as held in a register before conversion
+__device__ __forceinline__ double as_val(double v) { return v; }
+__device__ __forceinline__ float as_val(float v) { return v; }
+__device__ __forceinline__ float as_val(bf16_t v) { return __uint_as_float(static_cast<uint32_t>(v.v) << 16); }
+__device__ __forceinline__ float as_val(_Float16 v) { return static_cast<float>(v); }
+
 __device__ __forceinline__ void store_val(double* p, double v) { *p = v; }
 __device__ __forceinline__ void store_val(float* p, double v) { *p = static_cast<float>(v); }
 __device__ __forceinline__ void store_val(bf16_t* p, double v) {
@@ -771,6 +777,18 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
   const int64_t qblk = static_cast<int64_t>(blockIdx.x) * W * EBQ;
   const int qi = threadIdx.x;
 
+  // stored q-point data of this thread (apply), requested before the sum factorisation so that
+  // its HBM latency overlaps the gather and the forward sweeps
+  constexpr int WA = KIND == 0 ? W : 0;
+  ST qv[WA > 0 ? WA : 1];
+  if constexpr (WA > 0) {
+    if (valid) {
+      const ST* qd = static_cast<const ST*>(a.qdata) + qblk;
+#pragma unroll
+      for (int w = 0; w < WA; ++w) qv[w] = qd[w * EBQ + qi];
+    }
+  }
+
   constexpr bool kGeom = !(KIND == 0 && MODE == HX_STORE_TANGENT);
   if constexpr (kGeom) load_vertices<N, EB>(a, sv, e0, c0);
   if constexpr (KIND == 2 && S == kStoreF16) {
@@ -797,11 +815,10 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
   }
   if constexpr (KIND == 0 && MODE == HX_STORE_TANGENT) {
     // t = D g with the stored symmetric 9x9 tangent (45 planes, upper triangle row by row)
-    const ST* qd = static_cast<const ST*>(a.qdata) + qblk;
     R Dv[45];
     if (valid) {
 #pragma unroll
-      for (int w = 0; w < 45; ++w) Dv[w] = static_cast<R>(load_val(qd + w * EBQ + qi));
+      for (int w = 0; w < 45; ++w) Dv[w] = static_cast<R>(as_val(qv[w]));
     } else {
 #pragma unroll
       for (int w = 0; w < 45; ++w) Dv[w] = R(0);
@@ -836,12 +853,11 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
       to_physical(g1, K, H);
       state_from_H<LAW>(H, m, fb, st, E);
     } else {
-      const ST* qd = static_cast<const ST*>(a.qdata) + qblk;
       R Fi[9], Jm;
       if (valid) {
 #pragma unroll
-        for (int w = 0; w < 9; ++w) Fi[w] = static_cast<R>(load_val(qd + w * EBQ + qi));
-        Jm = static_cast<R>(load_val(qd + 9 * EBQ + qi));
+        for (int w = 0; w < 9; ++w) Fi[w] = static_cast<R>(as_val(qv[w]));
+        Jm = static_cast<R>(as_val(qv[9]));
       } else {
 #pragma unroll
         for (int w = 0; w < 9; ++w) Fi[w] = R(w % 4 == 0);
