@@ -33,8 +33,8 @@ FP32_PEAK_TFLOPS = 157.3
 # Algorithmic work per q-point (FP64 flops, cNH) of each storage mode's q-point routine, and
 # stored words per q-point; sum factorisation adds 12 n^4 fused multiply-adds per field and cell
 # (6 sweeps forward, 6 backward), 6 n^4 for the linearisation point in recompute mode.
-QPOINT_FLOPS = {"tangent": 162, "finv_j": 400, "none": 597}
-QPOINT_WORDS = {"tangent": 45, "finv_j": 10, "none": 0}
+QPOINT_FLOPS = {"tangent": 162, "finv_j": 400, "none": 597, "spatial": 214}
+QPOINT_WORDS = {"tangent": 45, "finv_j": 10, "none": 0, "spatial": 17}
 
 
 def parse():
@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--p", type=int, default=4)
-    ap.add_argument("--mode", default="auto", choices=["auto", "none", "finv_j", "tangent"])
+    ap.add_argument("--mode", default="auto", choices=["auto", "none", "finv_j", "tangent", "spatial"])
     ap.add_argument("--degrees", default="2,3,4,6")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
@@ -157,7 +157,7 @@ def main():
     degrees = [int(x) for x in args.degrees.split(",")]
     if args.p not in degrees:
         degrees.append(args.p)
-    modes = ["none", "finv_j", "tangent"]
+    modes = ["none", "finv_j", "tangent", "spatial"]
     sweep = {}
     extra = {}
     head = None
@@ -269,7 +269,7 @@ def fp32_study(hx, workloads, torch, dev, timer, args):
     du32 = dud.float()
     ref = {}
     out = {"dofs": op.num_dofs}
-    for mode in ["none", "finv_j", "tangent"]:
+    for mode in ["none", "finv_j", "tangent", "spatial"]:
         op.update_linearization(ud, mode=mode, precision="fp64")
         y = op.apply_tangent(dud)
         ms = timer.time(lambda: op.apply_tangent(dud, y), 10)
@@ -277,7 +277,8 @@ def fp32_study(hx, workloads, torch, dev, timer, args):
         out[f"fp64_{mode}"] = {"gdofs": op.num_dofs / ms / 1e6}
     yref = ref["tangent"]
     nrm = torch.linalg.norm(yref).item()
-    for mode, precs in [("none", ["fp32"]), ("finv_j", ["fp32"]), ("tangent", ["fp32", "fp32_bf16", "fp32_fp16"])]:
+    for mode, precs in [("none", ["fp32"]), ("finv_j", ["fp32"]), ("spatial", ["fp32"]),
+                        ("tangent", ["fp32", "fp32_bf16", "fp32_fp16"])]:
         for prec in precs:
             op.update_linearization(ud, mode=mode, precision=prec)
             y = op.apply_tangent(du32, precision=prec)

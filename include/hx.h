@@ -76,6 +76,12 @@ typedef enum {
   HX_STORE_NONE = 0,
   HX_STORE_FINV_J = 1,
   HX_STORE_TANGENT = 2,
+  HX_STORE_SPATIAL = 3, /* integration over the spatial configuration (Section 2, spatial residual
+                           and its linearisation; Section 5, spatial forms): the inverse Jacobian of
+                           the deformed map X + u_k, w det J0, the Kirchhoff stress tau and the law's
+                           data for J c : (.)^S (cNH 2(mu - 2 lambda ln J); iNH c1, c2 and
+                           (2 mu / 3) J^-2/3 b; fibre per family F H_i F^T and 2 c3 (2 k2 E_i^2 + 1)):
+                           17 / 24 / 38 words for cNH / iNH / fibre; FP64 or FP32 data */
   HX_STORE_AUTO = 255 /* only where a field says so: the mode is chosen by hx_autotune_storage */
 } hx_storage;
 
@@ -170,10 +176,10 @@ hx_status hx_apply_tangent(hx_ctx ctx, const void* du, void* dst, hx_precision p
                            void* stream);
 
 /* Autotuner of the storage strategy (Section 7.2: which strategy is fastest depends on the
- * hardware, degree and law and has to be measured). For each of NONE, FINV_J and TANGENT:
+ * hardware, degree and law and has to be measured). For each of NONE, FINV_J, TANGENT and SPATIAL:
  * updates the slot of prec (HX_FP64 or HX_FP32) at u, applies once to warm up, then times `reps`
  * applies (1..1000) of a fixed direction with HIP events on the stream. Leaves the slot
- * linearised in the fastest mode, written to *best; ms_per_apply (HOST [3] or NULL) receives the
+ * linearised in the fastest mode, written to *best; ms_per_apply (HOST [4] or NULL) receives the
  * mean time per apply of each mode in that order. Allocates two temporary device vectors and
  * waits for the stream. Errors of the updates (HX_E_INVERTED, ...) are returned as they come. */
 hx_status hx_autotune_storage(hx_ctx ctx, const double* u, hx_precision prec, int32_t reps,
@@ -210,7 +216,7 @@ typedef struct {
                               mixed-precision preconditioner); HX_FP64: everything in FP64 */
   int32_t use_graph;       /* 1: one V-cycle is captured into a HIP graph per update */
   hx_storage level_mode;   /* storage mode of the level operators inside the V-cycle: NONE,
-                              FINV_J, TANGENT (default) or AUTO (hx_autotune_storage on each
+                              FINV_J, TANGENT (default), SPATIAL or AUTO (hx_autotune_storage on each
                               level at the first update; the choice is kept). The inverse
                               diagonal always comes from a TANGENT update of the level. */
   int32_t coarse_solver;   /* coarsest level: 0 = dense if it has at most 8192 DoFs, else
@@ -273,7 +279,7 @@ typedef struct {
   int32_t max_krylov;
   int32_t load_steps;     /* the external load is applied in this many equal increments */
   hx_storage outer_mode;  /* storage mode of the FP64 outer operator with an FP32 hierarchy:
-                             NONE, FINV_J, TANGENT or AUTO (hx_autotune_storage at the first
+                             NONE, FINV_J, TANGENT, SPATIAL or AUTO (hx_autotune_storage at the first
                              linearisation, kept for the solve). An FP64 hierarchy shares the
                              finest level's data with the outer operator and ignores it. */
   int32_t verbose;        /* 1: one progress line per Newton iteration on stderr */

@@ -145,6 +145,17 @@ def first_pk(F, mat):
     return np.einsum("...ia,...aj->...ij", F, second_pk(F, mat))
 
 
+def kirchhoff_stress(F, mat):
+    """tau = F S F^T (Section 2, spatial residual)."""
+    return np.einsum("...ia,...ab,...jb->...ij", F, second_pk(F, mat), F)
+
+
+def spatial_moduli(F, mat):
+    """J c_ijkl = F_iA F_jB CC_ABCD F_kC F_lD: the push-forward of the material moduli (Section 2,
+    spatial linearisation), taken from CC by its definition rather than from printed forms."""
+    return np.einsum("...ia,...jb,...abcd,...kc,...ld->...ijkl", F, F, moduli(F, mat), F, F)
+
+
 def first_elasticity(F, mat):
     """A_iJkL = delta_ik S_JL + F_iA CC_AJCL F_kC  (= dP_iJ / dF_kL)."""
     S = second_pk(F, mat)

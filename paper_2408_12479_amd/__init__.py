@@ -17,8 +17,8 @@ HX_OK = 0
 STATUS = {0: "HX_OK", 1: "HX_E_ARG", 2: "HX_E_HIP", 3: "HX_E_NOMEM", 4: "HX_E_STATE", 5: "HX_E_INVERTED",
           6: "HX_E_NONFINITE", 7: "HX_E_NOT_CONVERGED", 8: "HX_E_UNSUPPORTED"}
 LAWS = {"cnh": 0, "inh": 1, "fiber": 2}
-MODES = {"none": 0, "finv_j": 1, "tangent": 2, "auto": 255}
-MODE_NAMES = {0: "none", 1: "finv_j", 2: "tangent", 255: "auto"}
+MODES = {"none": 0, "finv_j": 1, "tangent": 2, "spatial": 3, "auto": 255}
+MODE_NAMES = {0: "none", 1: "finv_j", 2: "tangent", 3: "spatial", 255: "auto"}
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_bf16": 2, "fp32_fp16": 3}
 
 
@@ -259,10 +259,10 @@ class Operator:
         """Runs the library's storage-mode autotuner at u: (best mode, {mode: ms per apply})."""
         import torch
         best = ctypes.c_int()
-        ms = np.zeros(3)
+        ms = np.zeros(4)
         _check(lib.hx_autotune_storage(self.ctx, self._vec(u, torch.float64, "u"), PRECISIONS[precision], int(reps),
                                        ctypes.byref(best), _dptr(ms), _stream_handle(stream)), self.ctx)
-        return MODE_NAMES[best.value], {"none": ms[0], "finv_j": ms[1], "tangent": ms[2]}
+        return MODE_NAMES[best.value], {"none": ms[0], "finv_j": ms[1], "tangent": ms[2], "spatial": ms[3]}
 
     def surface_load(self, face, pressure):
         """Dead-load pressure vector on a boundary face, host array (3, n_nodes)."""

@@ -600,7 +600,7 @@ hx_status hx_residual(hx_ctx ctx, const double* u, double* r, void* stream) {
 hx_status hx_update_linearization(hx_ctx ctx, const double* u, hx_storage mode, hx_precision prec,
                                   void* stream) {
   if (!ctx || !u) return fail(ctx, HX_E_ARG, "hx_update_linearization: NULL argument");
-  if (mode != HX_STORE_NONE && mode != HX_STORE_FINV_J && mode != HX_STORE_TANGENT)
+  if (mode != HX_STORE_NONE && mode != HX_STORE_FINV_J && mode != HX_STORE_TANGENT && mode != HX_STORE_SPATIAL)
     return fail(ctx, HX_E_ARG, "hx_update_linearization: unknown storage mode");
   const int st = store_of(prec);
   if (st < 0) return fail(ctx, HX_E_ARG, "hx_update_linearization: unknown precision");
@@ -613,7 +613,7 @@ hx_status hx_update_linearization(hx_ctx ctx, const double* u, hx_storage mode, 
   // whole workgroup blocks of cells (the last one may be partly unused)
   const int64_t eb = cells_per_block(ctx->p);
   const int64_t padded_cells = (L.n_cells + eb - 1) / eb * eb;
-  const size_t need = static_cast<size_t>(mode_words(mode)) * padded_cells * Q * store_bytes(st);
+  const size_t need = static_cast<size_t>(mode_words(mode, ctx->base.mat.law)) * padded_cells * Q * store_bytes(st);
   hipError_t e = hipStreamSynchronize(s);  // the slot's buffers may still be in use
   if (e != hipSuccess) return hip_fail(ctx, e, "hx_update_linearization: sync");
   if (need > sl.qcap) {
@@ -729,10 +729,10 @@ hx_status hx_autotune_storage(hx_ctx ctx, const double* u, hx_precision prec, in
     fill_timing_direction<double><<<grid_for(n), 256, 0, s>>>(static_cast<double*>(du), n);
   else
     fill_timing_direction<float><<<grid_for(n), 256, 0, s>>>(static_cast<float*>(du), n);
-  const hx_storage modes[3] = {HX_STORE_NONE, HX_STORE_FINV_J, HX_STORE_TANGENT};
-  double t[3] = {0.0, 0.0, 0.0};
-  int arg = 2;
-  for (int k = 0; k < 3; ++k) {
+  const hx_storage modes[4] = {HX_STORE_NONE, HX_STORE_FINV_J, HX_STORE_TANGENT, HX_STORE_SPATIAL};
+  double t[4] = {0.0, 0.0, 0.0, 0.0};
+  int arg = 3;
+  for (int k = 0; k < 4; ++k) {
     hx_status st = hx_update_linearization(ctx, u, modes[k], prec, stream);
     if (st == HX_OK) st = hx_apply_tangent(ctx, du, dst, prec, stream);  // warm-up
     if (st != HX_OK) {
@@ -754,9 +754,9 @@ hx_status hx_autotune_storage(hx_ctx ctx, const double* u, hx_precision prec, in
   }
   cleanup();
   if (ms_per_apply)
-    for (int k = 0; k < 3; ++k) ms_per_apply[k] = t[k];
+    for (int k = 0; k < 4; ++k) ms_per_apply[k] = t[k];
   *best = modes[arg];
-  if (arg != 2) return hx_update_linearization(ctx, u, modes[arg], prec, stream);
+  if (arg != 3) return hx_update_linearization(ctx, u, modes[arg], prec, stream);
   return HX_OK;
 }
 

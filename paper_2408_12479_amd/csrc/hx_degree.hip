@@ -102,6 +102,10 @@ hipError_t by_law(const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok) 
         if (op.store == kStoreF64) return launch<double, 2, HX_STORE_FINV_J, LAW, kStoreF64>(h, s);
         if (op.store == kStoreF32) return launch<double, 2, HX_STORE_FINV_J, LAW, kStoreF32>(h, s);
       }
+      if (op.mode == HX_STORE_SPATIAL) {
+        if (op.store == kStoreF64) return launch<double, 2, HX_STORE_SPATIAL, LAW, kStoreF64>(h, s);
+        if (op.store == kStoreF32) return launch<double, 2, HX_STORE_SPATIAL, LAW, kStoreF32>(h, s);
+      }
       if (op.mode == HX_STORE_TANGENT) {
         switch (op.store) {
           case kStoreF64: return launch<double, 2, HX_STORE_TANGENT, LAW, kStoreF64>(h, s);
@@ -124,6 +128,14 @@ hipError_t by_law(const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok) 
           return launch<double, 0, HX_STORE_FINV_J, LAW, kStoreF64>(h, s);
         if (op.fp32 && op.store == kStoreF32)
           return launch<float, 0, HX_STORE_FINV_J, LAW, kStoreF32>(h, s);
+      }
+      if (op.mode == HX_STORE_SPATIAL) {
+        // the stored words carry the frames: one apply kernel per law family
+        constexpr int AL = LAW == kFIBERC ? kFIBER : LAW;
+        if (!op.fp32 && op.store == kStoreF64)
+          return launch<double, 0, HX_STORE_SPATIAL, AL, kStoreF64>(h, s);
+        if (op.fp32 && op.store == kStoreF32)
+          return launch<float, 0, HX_STORE_SPATIAL, AL, kStoreF32>(h, s);
       }
       break;
   }

@@ -108,9 +108,18 @@ struct HostArgs {
   const float* fib32;
 };
 
+// Words per q-point of the spatial storage mode: J_t^-1 (9), w det J0 (1), tau (6) and the law's
+// data (cNH 1; iNH 2 + 6; fibre iNH + 2 x 7).
+constexpr int spatial_words(int law) { return law == 0 ? 17 : (law == 1 ? 24 : 38); }
+
 // Words per q-point of each storage mode.
-inline int mode_words(hx_storage m) {
-  return m == HX_STORE_TANGENT ? 45 : (m == HX_STORE_FINV_J ? 10 : 0);
+inline int mode_words(hx_storage m, hx_law law) {
+  switch (m) {
+    case HX_STORE_TANGENT: return 45;
+    case HX_STORE_FINV_J: return 10;
+    case HX_STORE_SPATIAL: return spatial_words(law);
+    default: return 0;
+  }
 }
 
 // One per degree, defined in hx_degree.hip compiled with HX_DEGREE = p.

@@ -140,8 +140,7 @@ __device__ __forceinline__ void to_reference(const R* P, const R* K, R w, R* t) 
 // Trilinear geometry at reference point (s, t, r): K = J0^-1, returns det J0.
 // X[3*v + c] is coordinate c of vertex v = a + 2b + 4c'.
 template <typename R>
-__device__ __forceinline__ R trilinear_geometry(const R* X, R s, R t, R r, R* K) {
-  R J[9];
+__device__ __forceinline__ void trilinear_jacobian(const R* X, R s, R t, R r, R* J) {
   const R s1 = R(1) - s, t1 = R(1) - t, r1 = R(1) - r;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -152,6 +151,13 @@ __device__ __forceinline__ R trilinear_geometry(const R* X, R s, R t, R r, R* K)
     J[3 * c + 2] = s1 * t1 * (X[12 + c] - X[c]) + s * t1 * (X[15 + c] - X[3 + c]) +
                    s1 * t * (X[18 + c] - X[6 + c]) + s * t * (X[21 + c] - X[9 + c]);
   }
+}
+
+// J0 = dX/dxi of the trilinear map at (s, t, r); K = J0^-1, returns det J0
+template <typename R>
+__device__ __forceinline__ R trilinear_geometry(const R* X, R s, R t, R r, R* K) {
+  R J[9];
+  trilinear_jacobian(X, s, t, r, J);
   R A[9];
   adj3(J, A);
   const R det = J[0] * A[0] + J[1] * A[3] + J[2] * A[6];
@@ -732,6 +738,189 @@ __device__ __forceinline__ R qpoint_geometry(const KernelArgs<N, R>& a, const R*
   return det * (pick<N>(Tab1D<N, R>::w, qx) * pick<N>(Tab1D<N, R>::w, qy) * pick<N>(Tab1D<N, R>::w, qz));
 }
 
+template <int N, typename R>
+__device__ __forceinline__ void qpoint_jacobian(const R* X, int q, R* J0) {
+  const int qx = q % N, qy = (q / N) % N, qz = q / (N * N);
+  trilinear_jacobian(X, pick<N>(Tab1D<N, R>::x, qx), pick<N>(Tab1D<N, R>::x, qy), pick<N>(Tab1D<N, R>::x, qz), J0);
+}
+
+// ------------------------------------------------------------------------------------------
+// Spatial configuration (Section 2, spatial residual and its linearisation; Section 5 spatial
+// forms). Stored words per q-point: J_t^-1 (9, row-major, J_t = dx/dxi of the deformed map
+// x = X + u_k), w det J0 (1), the Kirchhoff stress tau (6: xx yy zz xy xz yz), then
+//   cNH   a2 = 2 (mu - 2 lambda ln J)                       J c:e = a2 e + 2 lambda tr(e) I
+//   iNH   c1, c2, beta_b = (2 mu / 3) J^-2/3 b (6)        J c:e = -[beta_b tr(e) + (beta_b:e) I]
+//                                                                 - 2 c1 e + c2 tr(e) I
+//   fibre iNH, then per family h_i = F H_i F^T (6), d_i = 2 c3 (2 k2 E_i^2 + 1):
+//                                                         J c:e += sum_i d_i (h_i:e) h_i
+// The b-term is the push-forward of the symmetrised iNH second derivative (b, not C).
+// The apply: e = sym(grad du), grad du = (d du/dxi) J_t^-1,
+//   t = w det J0 [ (grad du) tau + J c:e ] J_t^-T.
+// ------------------------------------------------------------------------------------------
+template <int LAW>
+constexpr int kSpatialWords = spatial_words(LAW == kCNH ? 0 : (LAW == kINH ? 1 : 2));
+
+template <typename R>
+__device__ __forceinline__ void sym_to_full(const R* v, R* A) {
+  A[0] = v[0];
+  A[4] = v[1];
+  A[8] = v[2];
+  A[1] = A[3] = v[3];
+  A[2] = A[6] = v[4];
+  A[5] = A[7] = v[5];
+}
+
+template <typename R>
+__device__ __forceinline__ void full_to_sym(const R* A, R* v) {
+  v[0] = A[0];
+  v[1] = A[4];
+  v[2] = A[8];
+  v[3] = R(0.5) * (A[1] + A[3]);
+  v[4] = R(0.5) * (A[2] + A[6]);
+  v[5] = R(0.5) * (A[5] + A[7]);
+}
+
+// Spatial data at a q-point (update): H = Grad u, F, state, J0 and the reference gradient g of u.
+template <int LAW, typename R>
+__device__ __forceinline__ void spatial_words_at(const R* H, const QState<R>& st, const MaterialK<R>& m,
+                                                 const Fib<R>& fb, const R* J0, const R* g, R wdet, R* out) {
+  R Jt[9], A[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Jt[i] = J0[i] + g[i];
+  adj3(Jt, A);
+  const R inv = R(1) / (Jt[0] * A[0] + Jt[1] * A[3] + Jt[2] * A[6]);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) out[i] = A[i] * inv;
+  out[9] = wdet;
+  // b~ = (H + H^T + H H^T) / 2 (stable Green-Euler strain)
+  R bt[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      bt[3 * i + j] = R(0.5) * (H[3 * i + j] + H[3 * j + i] + H[3 * i] * H[3 * j] + H[3 * i + 1] * H[3 * j + 1] +
+                                H[3 * i + 2] * H[3 * j + 2]);
+  R tau[9];
+  if constexpr (LAW == kCNH) {
+    // tau = 2 mu b~ + 2 lambda ln J I
+    const R d = R(2) * m.lam * st.lnJ;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) tau[i] = R(2) * m.mu * bt[i];
+    tau[0] += d;
+    tau[4] += d;
+    tau[8] += d;
+    out[16] = R(2) * (m.mu - R(2) * m.lam * st.lnJ);
+  } else {
+    // tau = kappa/2 (J - 1)(J + 1) I + 2 mu J^-2/3 (b~ - tr(b~)/3 I)
+    const R tr3 = (bt[0] + bt[4] + bt[8]) / R(3);
+    const R a = R(2) * m.mu * st.Jp;
+    const R d = R(0.5) * m.kappa * st.Jm * (st.Jm + R(2)) - a * tr3;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) tau[i] = a * bt[i];
+    tau[0] += d;
+    tau[4] += d;
+    tau[8] += d;
+    out[16] = st.c1;
+    out[17] = st.c2;
+    R bb[9];
+    const R beta = R(2) / R(3) * m.mu * st.Jp;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) bb[i] = beta * R(2) * bt[i];
+    bb[0] += beta;
+    bb[4] += beta;
+    bb[8] += beta;
+    full_to_sym(bb, out + 18);
+    if constexpr (kIsFiber<LAW>) {
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        const R* Hf = f == 0 ? fb.H4 : fb.H6;
+        R FH[9], h[9];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j)
+            FH[3 * i + j] = st.F[3 * i] * Hf[j] + st.F[3 * i + 1] * Hf[3 + j] + st.F[3 * i + 2] * Hf[6 + j];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j)
+            h[3 * i + j] = FH[3 * i] * st.F[3 * j] + FH[3 * i + 1] * st.F[3 * j + 1] + FH[3 * i + 2] * st.F[3 * j + 2];
+        const R ce = st.c3[f] * st.Ei[f];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) tau[i] += ce * h[i];
+        full_to_sym(h, out + 24 + 7 * f);
+        out[30 + 7 * f] = R(2) * st.c3[f] * st.dfac[f];
+      }
+    }
+  }
+  full_to_sym(tau, out + 10);
+}
+
+// Spatial apply at a q-point: reference gradient g of du -> test coefficients t.
+template <int LAW, typename R>
+__device__ __forceinline__ void spatial_action(const R* d, const MaterialK<R>& m, const R* g, R* t) {
+  const R* Kt = d;
+  R gd[9];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) gd[3 * c + j] = g[3 * c] * Kt[j] + g[3 * c + 1] * Kt[3 + j] + g[3 * c + 2] * Kt[6 + j];
+  R tau[9];
+  sym_to_full(d + 10, tau);
+  R e[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) e[3 * i + j] = R(0.5) * (gd[3 * i + j] + gd[3 * j + i]);
+  const R tr = gd[0] + gd[4] + gd[8];
+  R sg[9];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) sg[3 * c + j] = gd[3 * c] * tau[j] + gd[3 * c + 1] * tau[3 + j] + gd[3 * c + 2] * tau[6 + j];
+  if constexpr (LAW == kCNH) {
+    const R a2 = d[16];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) sg[i] += a2 * e[i];
+    const R l = R(2) * m.lam * tr;
+    sg[0] += l;
+    sg[4] += l;
+    sg[8] += l;
+  } else {
+    const R c1 = d[16], c2 = d[17];
+    R bb[9];
+    sym_to_full(d + 18, bb);
+    R be = R(0);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) be += bb[i] * e[i];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) sg[i] += -bb[i] * tr - R(2) * c1 * e[i];
+    const R diag = c2 * tr - be;
+    sg[0] += diag;
+    sg[4] += diag;
+    sg[8] += diag;
+    if constexpr (kIsFiber<LAW>) {
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        R h[9];
+        sym_to_full(d + 24 + 7 * f, h);
+        R he = R(0);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) he += h[i] * e[i];
+        const R cf = d[30 + 7 * f] * he;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) sg[i] += cf * h[i];
+      }
+    }
+  }
+  const R w = d[9];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int dd = 0; dd < 3; ++dd)
+      t[3 * c + dd] = w * (sg[3 * c] * Kt[3 * dd] + sg[3 * c + 1] * Kt[3 * dd + 1] + sg[3 * c + 2] * Kt[3 * dd + 2]);
+}
+
 template <int N, int EB, typename R>
 __device__ __forceinline__ void load_vertices(const KernelArgs<N, R>& a, R* sv, int e0,
                                               const CellPos& c0) {
@@ -772,7 +961,9 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
   const CellPos c0 = cell_pos(a.L, e0);
   // stored data: block-interleaved planes [block][word][EB * Q]; the plane base is uniform
   // across the workgroup and the lane offset is the thread index
-  constexpr int W = MODE == HX_STORE_TANGENT ? 45 : (MODE == HX_STORE_FINV_J ? 10 : 0);
+  constexpr int W = MODE == HX_STORE_TANGENT
+                        ? 45
+                        : (MODE == HX_STORE_FINV_J ? 10 : (MODE == HX_STORE_SPATIAL ? kSpatialWords<LAW> : 0));
   constexpr int EBQ = EB * Q;
   const int64_t qblk = static_cast<int64_t>(blockIdx.x) * W * EBQ;
   const int qi = threadIdx.x;
@@ -789,7 +980,7 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
     }
   }
 
-  constexpr bool kGeom = !(KIND == 0 && MODE == HX_STORE_TANGENT);
+  constexpr bool kGeom = !(KIND == 0 && (MODE == HX_STORE_TANGENT || MODE == HX_STORE_SPATIAL));
   if constexpr (kGeom) load_vertices<N, EB>(a, sv, e0, c0);
   if constexpr (KIND == 2 && S == kStoreF16) {
     if (q == 0) sred[le] = 0.0f;
@@ -844,6 +1035,11 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
         for (int i = 0; i < 9; ++i) t[i] *= inv;
       }
     }
+  } else if constexpr (KIND == 0 && MODE == HX_STORE_SPATIAL) {
+    R d[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) d[w] = valid ? static_cast<R>(as_val(qv[w])) : R(0);
+    spatial_action<LAW>(d, m, g0, t);
   } else if constexpr (KIND == 0) {
     R K[9];
     const R wdet = valid ? qpoint_geometry(a, sv + le * 24, q, K) : R(0);
@@ -943,6 +1139,18 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
       if (valid) {
 #pragma unroll
         for (int i = 0; i < 45; ++i) store_val(qw + i * EBQ + qi, Dsym[i] * scale);
+      }
+    } else if constexpr (MODE == HX_STORE_SPATIAL) {
+      R J0[9], dw[W];
+      qpoint_jacobian<N>(sv + le * 24, q, J0);
+      spatial_words_at<LAW>(H, st, m, fb, J0, g0, wdet, dw);
+      R chk = R(0);
+#pragma unroll
+      for (int w = 0; w < W; ++w) chk += dw[w];
+      if (valid && !isfinite(chk)) bad |= kFlagNonFinite;
+      if (valid) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) store_val(qw + w * EBQ + qi, dw[w]);
       }
     } else {
       R chk = st.Jm;

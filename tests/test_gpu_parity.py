@@ -52,7 +52,7 @@ def test_config1_small_cube(device):
     ud, dud = to_dev(u), to_dev(du)
     r = to_host(op.residual(ud), op.num_nodes)
     assert rel(r, r_ref) < TOL64
-    for mode in ["none", "finv_j", "tangent"]:
+    for mode in ["none", "finv_j", "tangent", "spatial"]:
         op.update_linearization(ud, mode=mode, precision="fp64")
         y = to_host(op.apply_tangent(dud, precision="fp64"), op.num_nodes)
         assert rel(y, Kdu_ref) < TOL64, mode
@@ -69,7 +69,7 @@ def test_fp64_all_modes(device, p, law):
     r = to_host(op.residual(ud), op.num_nodes)
     assert rel(r, pb.residual(u)) < TOL64
     Kdu_ref = pb.apply_tangent(u, du)
-    for mode in ["none", "finv_j", "tangent"]:
+    for mode in ["none", "finv_j", "tangent", "spatial"]:
         op.update_linearization(ud, mode=mode, precision="fp64")
         y = to_host(op.apply_tangent(dud, precision="fp64"), op.num_nodes)
         assert rel(y, Kdu_ref) < TOL64, mode
@@ -84,7 +84,7 @@ def test_fp32_and_16bit_data(device, p, law):
     ud, du32 = to_dev(u), to_dev(du, "float32")
     Kdu_ref = pb.apply_tangent(u, du.astype(np.float32).astype(np.float64))
     bounds = {"fp32": TOL32, "fp32_bf16": 2e-2, "fp32_fp16": 3e-3}
-    for mode, precs in [("none", ["fp32"]), ("finv_j", ["fp32"]),
+    for mode, precs in [("none", ["fp32"]), ("finv_j", ["fp32"]), ("spatial", ["fp32"]),
                         ("tangent", ["fp32", "fp32_bf16", "fp32_fp16"])]:
         for prec in precs:
             op.update_linearization(ud, mode=mode, precision=prec)
@@ -100,8 +100,9 @@ def test_periodic_direction(device):
     u, du = _inputs(op, pb)
     ud, dud = to_dev(u), to_dev(du)
     assert rel(to_host(op.residual(ud), op.num_nodes), pb.residual(u)) < TOL64
-    op.update_linearization(ud, mode="tangent")
-    assert rel(to_host(op.apply_tangent(dud), op.num_nodes), pb.apply_tangent(u, du)) < TOL64
+    for mode in ["tangent", "spatial"]:
+        op.update_linearization(ud, mode=mode)
+        assert rel(to_host(op.apply_tangent(dud), op.num_nodes), pb.apply_tangent(u, du)) < TOL64, mode
     op.close()
 
 
@@ -134,7 +135,7 @@ def test_cell_frames_tube(device, p):
     assert rel(to_host(op.residual(ud), op.num_nodes), pb.residual(u)) < TOL64
     ref = pb.apply_tangent(u, du)
     ref32 = pb.apply_tangent(u, du.astype(np.float32).astype(np.float64))
-    for mode in ["none", "finv_j", "tangent"]:
+    for mode in ["none", "finv_j", "tangent", "spatial"]:
         op.update_linearization(ud, mode=mode, precision="fp64")
         assert rel(to_host(op.apply_tangent(dud), op.num_nodes), ref) < TOL64, mode
         op.update_linearization(ud, mode=mode, precision="fp32")
@@ -150,7 +151,7 @@ def test_cell_frames_random_box(device):
     ud, dud = to_dev(u), to_dev(du)
     assert rel(to_host(op.residual(ud), op.num_nodes), pb.residual(u)) < TOL64
     ref = pb.apply_tangent(u, du)
-    for mode in ["none", "finv_j", "tangent"]:
+    for mode in ["none", "finv_j", "tangent", "spatial"]:
         op.update_linearization(ud, mode=mode, precision="fp64")
         assert rel(to_host(op.apply_tangent(dud), op.num_nodes), ref) < TOL64, mode
     op.close()

@@ -195,7 +195,7 @@ def test_autotune_and_level_modes(device):
     u = _smooth_u(pbs[0])
     ud = to_dev(u)
     best, ms = ops[0].autotune_storage(ud, "fp64", reps=3)
-    assert best in ("none", "finv_j", "tangent") and all(v > 0.0 for v in ms.values())
+    assert best in ("none", "finv_j", "tangent", "spatial") and all(v > 0.0 for v in ms.values())
     assert ms[best] == min(ms.values())
     # the context is left linearised in the chosen mode
     rng = np.random.default_rng(12)
@@ -205,16 +205,17 @@ def test_autotune_and_level_modes(device):
     w = rng.standard_normal((3, ops[0].num_nodes))
     w[:, pbs[0].mesh.constrained] = 0.0
     z = {}
-    for mode in ["tangent", "finv_j", "auto"]:
+    for mode in ["tangent", "finv_j", "spatial", "auto"]:
         mg = hx.Multigrid(ops, precision="fp64", level_mode=mode)
         mg.update(ud)
         if mode != "auto":
             assert mg.level_mode(0) == mode and mg.level_mode(1) == mode
         else:
-            assert all(mg.level_mode(l) in ("none", "finv_j", "tangent") for l in range(2))
+            assert all(mg.level_mode(l) in ("none", "finv_j", "tangent", "spatial") for l in range(2))
         z[mode] = to_host(mg.vcycle(to_dev(w)), ops[0].num_nodes)
         mg.close()
     assert rel(z["finv_j"], z["tangent"]) < 1e-10
+    assert rel(z["spatial"], z["tangent"]) < 1e-10
     assert rel(z["auto"], z["tangent"]) < 1e-10
 
 
@@ -224,7 +225,7 @@ def test_newton_outer_mode_auto(device):
     mg = hx.Multigrid(ops, precision="fp32", level_mode="auto")
     u = torch.zeros(ops[0].num_dofs, dtype=torch.float64, device="cuda")
     rep = mg.newton_solve(u, to_dev(f), rel_tol=1e-9, krylov_rel_tol=1e-4, load_steps=1, outer_mode="auto")
-    assert rep["status"] == "HX_OK" and rep["outer_mode"] in ("none", "finv_j", "tangent")
+    assert rep["status"] == "HX_OK" and rep["outer_mode"] in ("none", "finv_j", "tangent", "spatial")
     fo = f.copy()
     fo[:, pbs[0].mesh.constrained] = 0.0
     assert np.linalg.norm(pbs[0].residual(to_host(u, ops[0].num_nodes)) - fo) < 1e-8 * np.linalg.norm(fo)

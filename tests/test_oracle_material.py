@@ -106,3 +106,46 @@ def test_objectivity(name):
         S1 = material.second_pk(F[None], mat)[0]
         S2 = material.second_pk((Q @ F)[None], mat)[0]
         assert np.max(np.abs(S1 - S2)) < 1e-12 * np.max(np.abs(S1))
+
+
+@pytest.mark.parametrize("law", ["cnh", "inh", "fiber"])
+def test_spatial_linearisation_is_material_one(law):
+    # (grad du) tau + J c : sym(grad du) = (A : Grad du) F^T with grad du = Grad du F^-1, and
+    # tau = P F^T: the spatial integrand equals the material one (Section 2 derivation)
+    from tests.helpers import make_material
+    mat = make_material(law)
+    rng = np.random.default_rng(17)
+    F = np.eye(3)[None] + 0.2 * rng.uniform(-1, 1, size=(6, 3, 3))
+    G = rng.standard_normal((6, 3, 3))
+    tau = material.kirchhoff_stress(F, mat)
+    np.testing.assert_allclose(tau, np.einsum("nij,nkj->nik", material.first_pk(F, mat), F), atol=1e-12)
+    c = material.spatial_moduli(F, mat)
+    g = np.einsum("nij,njk->nik", G, np.linalg.inv(F))
+    eps = 0.5 * (g + np.swapaxes(g, 1, 2))
+    lhs = np.einsum("nik,nkj->nij", g, tau) + np.einsum("nijkl,nkl->nij", c, eps)
+    A = material.first_elasticity(F, mat)
+    rhs = np.einsum("niJ,nkJ->nik", np.einsum("niJkL,nkL->niJ", A, G), F)
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-11, atol=1e-11 * np.abs(rhs).max())
+
+
+def test_spatial_inh_push_forward_uses_b():
+    # the iNH volumetric-deviatoric cross term of J c is -2mu/3 J^-2/3 [b tr(e) + (b:e) I] (the
+    # push-forward of the symmetrised second derivative), not a term with C
+    from tests.helpers import make_material
+    mat = make_material("inh")
+    rng = np.random.default_rng(3)
+    F = np.eye(3) + 0.3 * rng.uniform(-1, 1, size=(3, 3))
+    J = np.linalg.det(F)
+    b = F @ F.T
+    C = F.T @ F
+    Jp = J ** (-2.0 / 3.0)
+    I1 = np.trace(b)
+    c1 = 0.5 * mat.kappa * (J * J - 1) - mat.mu / 3 * Jp * I1
+    c2 = 2 * mat.mu / 9 * Jp * I1 + mat.kappa * J * J
+    e = rng.standard_normal((3, 3))
+    e = 0.5 * (e + e.T)
+    ref = np.einsum("ijkl,kl->ij", material.spatial_moduli(F[None], mat)[0], e)
+    ours = -2 * mat.mu / 3 * Jp * (b * np.trace(e) + np.sum(b * e) * np.eye(3)) - 2 * c1 * e + c2 * np.trace(e) * np.eye(3)
+    np.testing.assert_allclose(ours, ref, atol=1e-10 * np.abs(ref).max())
+    printed = -4 * mat.mu / 3 * Jp * np.trace(e) * C - 2 * c1 * e + c2 * np.trace(e) * np.eye(3)
+    assert np.abs(printed - ref).max() > 1e-3 * np.abs(ref).max()
