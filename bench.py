@@ -33,8 +33,8 @@ FP32_PEAK_TFLOPS = 157.3
 # Algorithmic work per q-point (FP64 flops, cNH) of each storage mode's q-point routine, and
 # stored words per q-point; sum factorisation adds 12 n^4 fused multiply-adds per field and cell
 # (6 sweeps forward, 6 backward), 6 n^4 for the linearisation point in recompute mode.
-QPOINT_FLOPS = {"tangent": 162, "finv_j": 400, "none": 597, "spatial": 214}
-QPOINT_WORDS = {"tangent": 45, "finv_j": 10, "none": 0, "spatial": 17}
+QPOINT_FLOPS = {"tangent": 162, "finv_j": 400, "none": 597, "spatial": 205}
+QPOINT_WORDS = {"tangent": 45, "finv_j": 10, "none": 0, "spatial": 16}
 
 
 def parse():

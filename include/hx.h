@@ -78,10 +78,11 @@ typedef enum {
   HX_STORE_TANGENT = 2,
   HX_STORE_SPATIAL = 3, /* integration over the spatial configuration (Section 2, spatial residual
                            and its linearisation; Section 5, spatial forms): the inverse Jacobian of
-                           the deformed map X + u_k, w det J0, the Kirchhoff stress tau and the law's
-                           data for J c : (.)^S (cNH 2(mu - 2 lambda ln J); iNH c1, c2 and
-                           (2 mu / 3) J^-2/3 b; fibre per family F H_i F^T and 2 c3 (2 k2 E_i^2 + 1)):
-                           17 / 24 / 38 words for cNH / iNH / fibre; FP64 or FP32 data */
+                           the deformed map X + u_k scaled by sqrt(w det J0), the Kirchhoff stress
+                           tau and the law's data for J c : (.)^S (cNH 2(mu - 2 lambda ln J); iNH c1,
+                           c2 and (2 mu / 3) J^-2/3 b; fibre per family F H_i F^T and
+                           2 c3 (2 k2 E_i^2 + 1)): 16 / 23 / 37 words for cNH / iNH / fibre;
+                           FP64 or FP32 data */
   HX_STORE_AUTO = 255 /* only where a field says so: the mode is chosen by hx_autotune_storage */
 } hx_storage;
 

@@ -3,10 +3,12 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "hx.h"
@@ -254,25 +256,67 @@ __global__ void copy_convert(const double* __restrict__ src, T* __restrict__ dst
     dst[i] = static_cast<T>(src[i]);
 }
 
+// Output initialisation of the apply and the residual: zero fill with 16-byte stores when the
+// output is 16-byte aligned (the element kernels store interior nodes and add into shared ones),
+// then du copied into the rows of the constrained faces (apply only), one thread per face node.
 template <typename R>
-__global__ void init_output_kernel(R* __restrict__ out, const R* __restrict__ du, Lattice L,
-                                   int copy_constrained) {
+__global__ void zero_fill_kernel(R* __restrict__ out, int64_t n) {
+  constexpr int V = 16 / sizeof(R);
+  using Vec = typename std::conditional<sizeof(R) == 8, double2, float4>::type;
+  const int64_t nv = n / V;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  Vec z;
+  std::memset(&z, 0, sizeof(z));
+  Vec* o = reinterpret_cast<Vec*>(out);
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < nv; i += stride) o[i] = z;
+  for (int64_t i = nv * V + blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n; i += stride)
+    out[i] = R(0);
+}
+
+template <typename R>
+__global__ void zero_fill_scalar_kernel(R* __restrict__ out, int64_t n) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n; i += stride) out[i] = R(0);
+}
+
+// face f (0..5 = -x,+x,-y,+y,-z,+z) node count and the node of face-local index k
+__device__ __host__ __forceinline__ int64_t face_nodes(const Lattice& L, int f) {
+  const int d = f >> 1;
+  return d == 0 ? static_cast<int64_t>(L.Ny) * L.Nz : (d == 1 ? static_cast<int64_t>(L.Nx) * L.Nz
+                                                             : static_cast<int64_t>(L.Nx) * L.Ny);
+}
+
+template <typename R>
+__global__ void copy_constrained_kernel(R* __restrict__ out, const R* __restrict__ du, Lattice L) {
   const int64_t n = L.n_nodes;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < 3 * n;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    R v = R(0);
-    if (copy_constrained && L.dir_faces) {
-      const int64_t node = i % n;
-      const int I = static_cast<int>(node % L.Nx);
-      const int J = static_cast<int>((node / L.Nx) % L.Ny);
-      const int K = static_cast<int>(node / (static_cast<int64_t>(L.Nx) * L.Ny));
-      const uint32_t f = L.dir_faces;
-      const bool cons = ((f & 1u) && I == 0) || ((f & 2u) && I == L.Nx - 1) ||
-                        ((f & 4u) && J == 0) || ((f & 8u) && J == L.Ny - 1) ||
-                        ((f & 16u) && K == 0) || ((f & 32u) && K == L.Nz - 1);
-      if (cons) v = du[i];
+  int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  for (int f = 0; f < 6; ++f) {
+    const int64_t m = face_nodes(L, f);
+    if (!((L.dir_faces >> f) & 1u)) continue;
+    if (k >= m) {
+      k -= m;
+      continue;
     }
-    out[i] = v;
+    const int d = f >> 1;
+    const int side = f & 1;
+    int I, J, K;
+    if (d == 0) {
+      I = side ? L.Nx - 1 : 0;
+      J = static_cast<int>(k % L.Ny);
+      K = static_cast<int>(k / L.Ny);
+    } else if (d == 1) {
+      J = side ? L.Ny - 1 : 0;
+      I = static_cast<int>(k % L.Nx);
+      K = static_cast<int>(k / L.Nx);
+    } else {
+      K = side ? L.Nz - 1 : 0;
+      I = static_cast<int>(k % L.Nx);
+      J = static_cast<int>(k / L.Nx);
+    }
+    const int64_t node = I + static_cast<int64_t>(L.Nx) * (J + static_cast<int64_t>(L.Ny) * K);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[c * n + node] = du[c * n + node];
+    return;
   }
 }
 
@@ -288,6 +332,23 @@ __global__ void fill_timing_direction(T* __restrict__ x, int64_t n) {
 int grid_for(int64_t n) {
   const int64_t b = (n + 255) / 256;
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(b, 8192)));
+}
+
+// dst = 0, then dst = du on the constrained rows (if du is given)
+template <typename R>
+hipError_t init_output(R* dst, const R* du, const Lattice& L, hipStream_t s) {
+  const int64_t n = 3 * L.n_nodes;
+  if ((reinterpret_cast<uintptr_t>(dst) & 15u) == 0)
+    zero_fill_kernel<R><<<grid_for((n + 1) / 2), 256, 0, s>>>(dst, n);
+  else
+    zero_fill_scalar_kernel<R><<<grid_for(n), 256, 0, s>>>(dst, n);
+  if (du && L.dir_faces) {
+    int64_t m = 0;
+    for (int f = 0; f < 6; ++f)
+      if ((L.dir_faces >> f) & 1u) m += face_nodes(L, f);
+    copy_constrained_kernel<R><<<static_cast<unsigned>((m + 255) / 256), 256, 0, s>>>(dst, du, L);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -583,8 +644,7 @@ hx_status hx_residual(hx_ctx ctx, const double* u, double* r, void* stream) {
   if (static_cast<const void*>(u) == static_cast<const void*>(r)) return fail(ctx, HX_E_ARG, "hx_residual: u and r alias");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t n = 3 * ctx->L.n_nodes;
-  init_output_kernel<double><<<grid_for(n), 256, 0, s>>>(r, nullptr, ctx->L, 0);
-  hipError_t e = hipGetLastError();
+  hipError_t e = init_output<double>(r, nullptr, ctx->L, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "hx_residual: init");
   HostArgs h = args_for(ctx);
   h.in0 = u;
@@ -679,11 +739,8 @@ hx_status hx_apply_tangent(hx_ctx ctx, const void* du, void* dst, hx_precision p
   if (!sl.valid) return fail(ctx, HX_E_STATE, "hx_apply_tangent: no linearisation stored for this precision");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t n = 3 * ctx->L.n_nodes;
-  if (fp32)
-    init_output_kernel<float><<<grid_for(n), 256, 0, s>>>(static_cast<float*>(dst), static_cast<const float*>(du), ctx->L, 1);
-  else
-    init_output_kernel<double><<<grid_for(n), 256, 0, s>>>(static_cast<double*>(dst), static_cast<const double*>(du), ctx->L, 1);
-  hipError_t e = hipGetLastError();
+  hipError_t e = fp32 ? init_output<float>(static_cast<float*>(dst), static_cast<const float*>(du), ctx->L, s)
+                      : init_output<double>(static_cast<double*>(dst), static_cast<const double*>(du), ctx->L, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "hx_apply_tangent: init");
   HostArgs h = args_for(ctx);
   h.in0 = du;

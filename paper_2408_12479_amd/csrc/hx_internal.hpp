@@ -108,9 +108,9 @@ struct HostArgs {
   const float* fib32;
 };
 
-// Words per q-point of the spatial storage mode: J_t^-1 (9), w det J0 (1), tau (6) and the law's
+// Words per q-point of the spatial storage mode: sqrt(w det J0) J_t^-1 (9), tau (6) and the law's
 // data (cNH 1; iNH 2 + 6; fibre iNH + 2 x 7).
-constexpr int spatial_words(int law) { return law == 0 ? 17 : (law == 1 ? 24 : 38); }
+constexpr int spatial_words(int law) { return law == 0 ? 16 : (law == 1 ? 23 : 37); }
 
 // Words per q-point of each storage mode.
 inline int mode_words(hx_storage m, hx_law law) {

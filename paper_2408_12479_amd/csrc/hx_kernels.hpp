@@ -746,16 +746,17 @@ __device__ __forceinline__ void qpoint_jacobian(const R* X, int q, R* J0) {
 
 // ------------------------------------------------------------------------------------------
 // Spatial configuration (Section 2, spatial residual and its linearisation; Section 5 spatial
-// forms). Stored words per q-point: J_t^-1 (9, row-major, J_t = dx/dxi of the deformed map
-// x = X + u_k), w det J0 (1), the Kirchhoff stress tau (6: xx yy zz xy xz yz), then
+// forms). Stored words per q-point: K = sqrt(w det J0) J_t^-1 (9, row-major, J_t = dx/dxi of the
+// deformed map x = X + u_k), the Kirchhoff stress tau (6: xx yy zz xy xz yz), then
 //   cNH   a2 = 2 (mu - 2 lambda ln J)                       J c:e = a2 e + 2 lambda tr(e) I
 //   iNH   c1, c2, beta_b = (2 mu / 3) J^-2/3 b (6)        J c:e = -[beta_b tr(e) + (beta_b:e) I]
 //                                                                 - 2 c1 e + c2 tr(e) I
 //   fibre iNH, then per family h_i = F H_i F^T (6), d_i = 2 c3 (2 k2 E_i^2 + 1):
 //                                                         J c:e += sum_i d_i (h_i:e) h_i
 // The b-term is the push-forward of the symmetrised iNH second derivative (b, not C).
-// The apply: e = sym(grad du), grad du = (d du/dxi) J_t^-1,
-//   t = w det J0 [ (grad du) tau + J c:e ] J_t^-T.
+// The apply: with g' = (d du/dxi) K = sqrt(w det J0) grad du and e' = sym(g'), everything is
+// linear in g', so t = [ g' tau + J c:e' ] K^T = w det J0 [ (grad du) tau + J c:e ] J_t^-T: the
+// weight rides on the stored inverse Jacobian and costs no word.
 // ------------------------------------------------------------------------------------------
 template <int LAW>
 constexpr int kSpatialWords = spatial_words(LAW == kCNH ? 0 : (LAW == kINH ? 1 : 2));
@@ -788,10 +789,9 @@ __device__ __forceinline__ void spatial_words_at(const R* H, const QState<R>& st
 #pragma unroll
   for (int i = 0; i < 9; ++i) Jt[i] = J0[i] + g[i];
   adj3(Jt, A);
-  const R inv = R(1) / (Jt[0] * A[0] + Jt[1] * A[3] + Jt[2] * A[6]);
+  const R inv = sqrt(wdet) / (Jt[0] * A[0] + Jt[1] * A[3] + Jt[2] * A[6]);
 #pragma unroll
   for (int i = 0; i < 9; ++i) out[i] = A[i] * inv;
-  out[9] = wdet;
   // b~ = (H + H^T + H H^T) / 2 (stable Green-Euler strain)
   R bt[9];
 #pragma unroll
@@ -809,7 +809,7 @@ __device__ __forceinline__ void spatial_words_at(const R* H, const QState<R>& st
     tau[0] += d;
     tau[4] += d;
     tau[8] += d;
-    out[16] = R(2) * (m.mu - R(2) * m.lam * st.lnJ);
+    out[15] = R(2) * (m.mu - R(2) * m.lam * st.lnJ);
   } else {
     // tau = kappa/2 (J - 1)(J + 1) I + 2 mu J^-2/3 (b~ - tr(b~)/3 I)
     const R tr3 = (bt[0] + bt[4] + bt[8]) / R(3);
@@ -820,8 +820,8 @@ __device__ __forceinline__ void spatial_words_at(const R* H, const QState<R>& st
     tau[0] += d;
     tau[4] += d;
     tau[8] += d;
-    out[16] = st.c1;
-    out[17] = st.c2;
+    out[15] = st.c1;
+    out[16] = st.c2;
     R bb[9];
     const R beta = R(2) / R(3) * m.mu * st.Jp;
 #pragma unroll
@@ -829,7 +829,7 @@ __device__ __forceinline__ void spatial_words_at(const R* H, const QState<R>& st
     bb[0] += beta;
     bb[4] += beta;
     bb[8] += beta;
-    full_to_sym(bb, out + 18);
+    full_to_sym(bb, out + 17);
     if constexpr (kIsFiber<LAW>) {
 #pragma unroll
       for (int f = 0; f < 2; ++f) {
@@ -848,12 +848,12 @@ __device__ __forceinline__ void spatial_words_at(const R* H, const QState<R>& st
         const R ce = st.c3[f] * st.Ei[f];
 #pragma unroll
         for (int i = 0; i < 9; ++i) tau[i] += ce * h[i];
-        full_to_sym(h, out + 24 + 7 * f);
-        out[30 + 7 * f] = R(2) * st.c3[f] * st.dfac[f];
+        full_to_sym(h, out + 23 + 7 * f);
+        out[29 + 7 * f] = R(2) * st.c3[f] * st.dfac[f];
       }
     }
   }
-  full_to_sym(tau, out + 10);
+  full_to_sym(tau, out + 9);
 }
 
 // Spatial apply at a q-point: reference gradient g of du -> test coefficients t.
@@ -866,7 +866,7 @@ __device__ __forceinline__ void spatial_action(const R* d, const MaterialK<R>& m
 #pragma unroll
     for (int j = 0; j < 3; ++j) gd[3 * c + j] = g[3 * c] * Kt[j] + g[3 * c + 1] * Kt[3 + j] + g[3 * c + 2] * Kt[6 + j];
   R tau[9];
-  sym_to_full(d + 10, tau);
+  sym_to_full(d + 9, tau);
   R e[9];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -879,7 +879,7 @@ __device__ __forceinline__ void spatial_action(const R* d, const MaterialK<R>& m
 #pragma unroll
     for (int j = 0; j < 3; ++j) sg[3 * c + j] = gd[3 * c] * tau[j] + gd[3 * c + 1] * tau[3 + j] + gd[3 * c + 2] * tau[6 + j];
   if constexpr (LAW == kCNH) {
-    const R a2 = d[16];
+    const R a2 = d[15];
 #pragma unroll
     for (int i = 0; i < 9; ++i) sg[i] += a2 * e[i];
     const R l = R(2) * m.lam * tr;
@@ -887,9 +887,9 @@ __device__ __forceinline__ void spatial_action(const R* d, const MaterialK<R>& m
     sg[4] += l;
     sg[8] += l;
   } else {
-    const R c1 = d[16], c2 = d[17];
+    const R c1 = d[15], c2 = d[16];
     R bb[9];
-    sym_to_full(d + 18, bb);
+    sym_to_full(d + 17, bb);
     R be = R(0);
 #pragma unroll
     for (int i = 0; i < 9; ++i) be += bb[i] * e[i];
@@ -903,22 +903,21 @@ __device__ __forceinline__ void spatial_action(const R* d, const MaterialK<R>& m
 #pragma unroll
       for (int f = 0; f < 2; ++f) {
         R h[9];
-        sym_to_full(d + 24 + 7 * f, h);
+        sym_to_full(d + 23 + 7 * f, h);
         R he = R(0);
 #pragma unroll
         for (int i = 0; i < 9; ++i) he += h[i] * e[i];
-        const R cf = d[30 + 7 * f] * he;
+        const R cf = d[29 + 7 * f] * he;
 #pragma unroll
         for (int i = 0; i < 9; ++i) sg[i] += cf * h[i];
       }
     }
   }
-  const R w = d[9];
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int dd = 0; dd < 3; ++dd)
-      t[3 * c + dd] = w * (sg[3 * c] * Kt[3 * dd] + sg[3 * c + 1] * Kt[3 * dd + 1] + sg[3 * c + 2] * Kt[3 * dd + 2]);
+      t[3 * c + dd] = sg[3 * c] * Kt[3 * dd] + sg[3 * c + 1] * Kt[3 * dd + 1] + sg[3 * c + 2] * Kt[3 * dd + 2];
 }
 
 template <int N, int EB, typename R>
