@@ -511,13 +511,12 @@ __device__ __forceinline__ void pencil_jobs(Fn&& fn) {
   }
 }
 
-// LDS per cell: 12 fields of N^3 values (values at Gauss points and the three derivatives of the
-// three components; the backward pass reuses the first nine).
-constexpr int kBuffers = 12;
+// LDS per cell: 9 fields of N^3 values. Forward: values (then d/dx in place) in c, d/dz in
+// 3 + c, d/dy in 6 + c; backward: the nine test coefficients.
+constexpr int kBuffers = 9;
 
 // Forward pass for one 3-component vector V: writes the 9 reference derivatives at this
-// thread's q-point into g[c*3 + d]. Buffers per component c: c (values, then unused),
-// 3 + c (d/dx), 6 + c (d/dz), 9 + c (d/dy).
+// thread's q-point into g[c*3 + d].
 template <int N, int EB, bool MASK, typename R>
 __device__ __forceinline__ void forward_vector(const KernelArgs<N, R>& a, R* sb, const R* V,
                                                int e0, const CellPos& c0, int le_me, int q_me,
@@ -568,11 +567,11 @@ __device__ __forceinline__ void forward_vector(const KernelArgs<N, R>& a, R* sb,
     for (int m = 0; m < N; ++m) buf[pidx<N, 1>(i, k, m)] = out[m];
   });
   __syncthreads();
-  // F3: interpolate along z (values at Gauss points) and differentiate along z
+  // F3: interpolate along z (values at Gauss points, in place) and differentiate along z
   pencil_jobs<N, EB, 3>([&](int le, int c, int i, int j) __attribute__((always_inline)) {
     R in[N], v[N], d[N];
     R* buf = sb + le * CB + c * Q;
-    R* bz = sb + le * CB + (6 + c) * Q;
+    R* bz = sb + le * CB + (3 + c) * Q;
 #pragma unroll
     for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 2>(i, j, m)];
     apply1d<N, false>(Tab1D<N, R>::B, in, v);
@@ -584,35 +583,36 @@ __device__ __forceinline__ void forward_vector(const KernelArgs<N, R>& a, R* sb,
     }
   });
   __syncthreads();
-  // F4: differentiate along x (into 3 + c) and along y (into 9 + c) in one phase
-  pencil_jobs<N, EB, 6>([&](int le, int set, int a1, int b1) __attribute__((always_inline)) {
-    const int c = set >> 1;
+  // F4: differentiate along y (into 6 + c)
+  pencil_jobs<N, EB, 3>([&](int le, int c, int a1, int b1) __attribute__((always_inline)) {
     R in[N], d[N];
     const R* buf = sb + le * CB + c * Q;
-    if ((set & 1) == 0) {
-      R* bx = sb + le * CB + (3 + c) * Q;
+    R* by = sb + le * CB + (6 + c) * Q;
 #pragma unroll
-      for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 0>(a1, b1, m)];
-      apply1d<N, false>(Tab1D<N, R>::D, in, d);
+    for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 1>(a1, b1, m)];
+    apply1d<N, false>(Tab1D<N, R>::D, in, d);
 #pragma unroll
-      for (int m = 0; m < N; ++m) bx[pidx<N, 0>(a1, b1, m)] = d[m];
-    } else {
-      R* by = sb + le * CB + (9 + c) * Q;
-#pragma unroll
-      for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 1>(a1, b1, m)];
-      apply1d<N, false>(Tab1D<N, R>::D, in, d);
-#pragma unroll
-      for (int m = 0; m < N; ++m) by[pidx<N, 1>(a1, b1, m)] = d[m];
-    }
+    for (int m = 0; m < N; ++m) by[pidx<N, 1>(a1, b1, m)] = d[m];
   });
   __syncthreads();
-  // F5: this thread's q-point
+  // F5: differentiate along x, in place
+  pencil_jobs<N, EB, 3>([&](int le, int c, int a1, int b1) __attribute__((always_inline)) {
+    R in[N], d[N];
+    R* buf = sb + le * CB + c * Q;
+#pragma unroll
+    for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 0>(a1, b1, m)];
+    apply1d<N, false>(Tab1D<N, R>::D, in, d);
+#pragma unroll
+    for (int m = 0; m < N; ++m) buf[pidx<N, 0>(a1, b1, m)] = d[m];
+  });
+  __syncthreads();
+  // F6: this thread's q-point
   const R* cb = sb + le_me * CB;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    g[3 * c + 0] = cb[(3 + c) * Q + q_me];
-    g[3 * c + 1] = cb[(9 + c) * Q + q_me];
-    g[3 * c + 2] = cb[(6 + c) * Q + q_me];
+    g[3 * c + 0] = cb[c * Q + q_me];
+    g[3 * c + 1] = cb[(6 + c) * Q + q_me];
+    g[3 * c + 2] = cb[(3 + c) * Q + q_me];
   }
 }
 
@@ -940,10 +940,11 @@ __device__ __forceinline__ void load_vertices(const KernelArgs<N, R>& a, R* sv, 
   }
 }
 
-// Kernel: ops = residual, apply (three storage modes) and update (three storage modes).
+// Kernel: ops = residual, apply (four storage modes) and update (four storage modes).
 //   KIND 0 apply, 1 residual, 2 update; MODE = hx_storage; S = StoreType; LAW
-// The apply and residual kernels are held to at most 128 VGPRs (4 waves per SIMD); the update
-// runs once per Newton step and may use the whole register file.
+// The apply and residual kernels are held to at most 128 VGPRs (4 waves per SIMD; forcing 8
+// waves spills and is slower); the update runs once per Newton step and may use the whole
+// register file.
 template <int N, int EB, typename R, int KIND, int MODE, int LAW, int S>
 __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
     element_kernel(KernelArgs<N, R> a) {
