@@ -53,6 +53,7 @@ def parse():
     ap.add_argument("--no-stability", action="store_true")
     ap.add_argument("--no-newton", action="store_true")
     ap.add_argument("--newton-cells", default="32,16,400")
+    ap.add_argument("--newton-bf16", action="store_true", help="also solve with BF16-stored multigrid levels")
     return ap.parse_args()
 
 
@@ -217,7 +218,7 @@ def main():
         extra["tube_vcycle_p6321"] = mg_study(hx, workloads, torch, dev, timer)
     if not args.no_newton:
         cells = tuple(int(c) for c in args.newton_cells.split(","))
-        extra["tube_newton_q4"] = newton_study(hx, workloads, torch, dev, cells=cells)
+        extra["tube_newton_q4"] = newton_study(hx, workloads, torch, dev, cells=cells, bf16=args.newton_bf16)
 
     # roofline of the headline kernel
     ms = head["ms"]
@@ -391,20 +392,21 @@ def mg_study(hx, workloads, torch, dev, timer, cells=(16, 8, 200), degrees=(6, 3
     b[mask] = 0.0
     bd = torch.tensor(b, dtype=torch.float64, device=dev)
     out = {"cells": list(cells), "levels": [[op.p, op.num_cells, op.num_dofs] for op in ops]}
-    for use_graph in (True, False):
-        mg = hx.Multigrid(ops, precision="fp32", use_graph=use_graph, level_mode="auto")
+    for use_graph, prec in ((True, "fp32"), (False, "fp32"), (True, "fp32_bf16")):
+        mg = hx.Multigrid(ops, precision=prec, use_graph=use_graph, level_mode="auto")
         t0 = time.perf_counter()
         mg.update(ud)
         t_upd = time.perf_counter() - t0
         r32 = bd.float()
         z = mg.vcycle(r32)
         ms = timer.time(lambda: mg.vcycle(r32, z), reps)
-        key = "graph" if use_graph else "eager"
+        key = ("graph" if use_graph else "eager") + ("" if prec == "fp32" else "_" + prec)
         out[f"vcycle_ms_{key}"] = ms
         if use_graph:
-            out["update_s"] = t_upd
-            out["level_modes"] = [mg.level_mode(l) for l in range(len(ops))]
-            out["lambda_max"] = [mg.lambda_max(l) for l in range(len(ops))]
+            sfx = "" if prec == "fp32" else "_" + prec
+            out["update_s" + sfx] = t_upd
+            out["level_modes" + sfx] = [mg.level_mode(l) for l in range(len(ops))]
+            out["lambda_max" + sfx] = [mg.lambda_max(l) for l in range(len(ops))]
             ops[0].update_linearization(ud, mode="tangent", precision="fp64")
             x = torch.zeros_like(bd)
             r = bd.clone()
@@ -412,7 +414,7 @@ def mg_study(hx, workloads, torch, dev, timer, cells=(16, 8, 200), degrees=(6, 3
             for _ in range(its):
                 x += mg.vcycle(r.float()).double()
                 r = bd - ops[0].apply_tangent(x)
-            out["stationary_factor"] = (torch.linalg.norm(r).item() / np.linalg.norm(b)) ** (1.0 / its)
+            out["stationary_factor" + sfx] = (torch.linalg.norm(r).item() / np.linalg.norm(b)) ** (1.0 / its)
         mg.close()
         print(f"[bench] tube V-cycle ({key}): {ms:.2f} ms", file=sys.stderr, flush=True)
     for op in ops:
@@ -421,7 +423,7 @@ def mg_study(hx, workloads, torch, dev, timer, cells=(16, 8, 200), degrees=(6, 3
 
 
 def newton_study(hx, workloads, torch, dev, cells=(32, 16, 400), degrees=(4, 2, 1), pressure=0.1, load_steps=5,
-                 rel_tol=1e-8, krylov_rel_tol=1e-3):
+                 rel_tol=1e-8, krylov_rel_tol=1e-3, bf16=False):
     """Newton-Krylov solve of the pressurised tube: FP32 multigrid with FP64 outer CG (mixed) vs
     the all-FP64 solve on the same GPU, each from u = 0 with the same load steps and tolerances."""
     ops = tube_hierarchy(hx, workloads, cells, degrees)
@@ -431,7 +433,8 @@ def newton_study(hx, workloads, torch, dev, cells=(32, 16, 400), degrees=(4, 2, 
            "dofs": ops[0].num_dofs, "pressure": pressure, "material": dict(TUBE_MAT, **TUBE_FIBRES),
            "load_steps": load_steps, "newton_rel_tol": rel_tol, "krylov_rel_tol": krylov_rel_tol}
     sols = {}
-    for name, prec in (("mixed", "fp32"), ("fp64", "fp64")):
+    variants = [("mixed", "fp32"), ("fp64", "fp64")] + ([("mixed_bf16", "fp32_bf16")] if bf16 else [])
+    for name, prec in variants:
         mg = hx.Multigrid(ops, precision=prec, level_mode="auto")
         u = torch.zeros(ops[0].num_dofs, dtype=torch.float64, device=dev)
         torch.cuda.synchronize()

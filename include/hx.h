@@ -213,8 +213,10 @@ typedef struct {
   int32_t eig_iters;       /* Lanczos (Jacobi-preconditioned CG) steps that estimate the extreme
                               eigenvalues of D^-1 A (default 20) */
   double eig_safety;       /* the estimate is multiplied by this factor (default 1.2) */
-  hx_precision precision;  /* HX_FP32: levels apply in FP32 with FP32 stored tangents (the
-                              mixed-precision preconditioner); HX_FP64: everything in FP64 */
+  hx_precision precision;  /* HX_FP32: levels apply in FP32 with FP32 stored data (the
+                              mixed-precision preconditioner); HX_FP32_BF16DATA / _FP16DATA: FP32
+                              vectors and arithmetic with 16-bit stored tangents on all levels
+                              but the coarsest (FP32); HX_FP64: everything in FP64 */
   int32_t use_graph;       /* 1: one V-cycle is captured into a HIP graph per update */
   hx_storage level_mode;   /* storage mode of the level operators inside the V-cycle: NONE,
                               FINV_J, TANGENT (default), SPATIAL or AUTO (hx_autotune_storage on each

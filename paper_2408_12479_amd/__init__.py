@@ -311,7 +311,7 @@ class Multigrid:
 
     def vcycle(self, r, z=None, stream=None):
         import torch
-        dt = torch.float32 if self.precision == "fp32" else torch.float64
+        dt = torch.float64 if self.precision == "fp64" else torch.float32
         z = torch.empty_like(r) if z is None else z
         _check_mg(lib.hx_mg_vcycle(self.mg, self.levels[0]._vec(r, dt, "r"), self.levels[0]._vec(z, dt, "z"),
                                    _stream_handle(stream)), self.mg)
@@ -340,7 +340,7 @@ class Multigrid:
 
     def inverse_diagonal(self, level, stream=None):
         import torch
-        dt = torch.float32 if self.precision == "fp32" else torch.float64
+        dt = torch.float64 if self.precision == "fp64" else torch.float32
         op = self.levels[level]
         out = torch.empty(op.num_dofs, dtype=dt, device="cuda")
         _check_mg(lib.hx_mg_inverse_diagonal(self.mg, int(level), op._vec(out, dt, "out"),

@@ -557,7 +557,15 @@ hx_status mg_fail(hx_mg mg, hx_status s, const std::string& m) {
   return s;
 }
 
-hx_precision mg_prec(const hx_mg mg) { return mg->fp32 ? HX_FP32 : HX_FP64; }
+// Storage precision of level l: the hierarchy's, except that the coarsest level of a hierarchy
+// with 16-bit data keeps FP32 data (its operator is assembled and factored).
+hx_precision level_prec(const hx_mg mg, int l) {
+  if (!mg->fp32) return HX_FP64;
+  const bool coarsest = l == static_cast<int>(mg->lv.size()) - 1;
+  return coarsest ? HX_FP32 : mg->opt.precision;
+}
+
+bool sixteen_bit(hx_precision p) { return p == HX_FP32_BF16DATA || p == HX_FP32_FP16DATA; }
 
 size_t vec_bytes(const hx_mg mg, int l) {
   return static_cast<size_t>(3 * mg->lv[l]->L.n_nodes) * (mg->fp32 ? sizeof(float) : sizeof(double));
@@ -565,7 +573,7 @@ size_t vec_bytes(const hx_mg mg, int l) {
 
 template <typename T>
 hipError_t level_apply(hx_mg mg, int l, const T* x, T* y) {
-  const hx_status st = hx_apply_tangent(mg->lv[l], x, y, mg_prec(mg), mg->stream);
+  const hx_status st = hx_apply_tangent(mg->lv[l], x, y, level_prec(mg, l), mg->stream);
   return st == HX_OK ? hipSuccess : hipErrorLaunchFailure;
 }
 
@@ -837,14 +845,17 @@ hx_status hx_mg_create(const hx_ctx* levels, int32_t n_levels, const hx_mg_optio
                          o.level_mode == HX_STORE_TANGENT || o.level_mode == HX_STORE_SPATIAL ||
                          o.level_mode == HX_STORE_AUTO;
     if (o.smoother_degree < 1 || o.coarse_degree < 1 || o.eig_iters < 1 || !(o.smoothing_range > 1.0) ||
-        !(o.eig_safety >= 1.0) || (o.precision != HX_FP32 && o.precision != HX_FP64) || !mode_ok ||
+        !(o.eig_safety >= 1.0) ||
+        (o.precision != HX_FP32 && o.precision != HX_FP64 && o.precision != HX_FP32_BF16DATA &&
+         o.precision != HX_FP32_FP16DATA) ||
+        !mode_ok ||
         o.coarse_solver < 0 || o.coarse_solver > 2) {
       delete mg;
       return HX_E_ARG;
     }
   }
   mg->opt = o;
-  mg->fp32 = o.precision == HX_FP32;
+  mg->fp32 = o.precision != HX_FP64;
   const int64_t n_coarse = 3 * levels[n_levels - 1]->L.n_nodes;
   if (o.coarse_solver == 2 && n_coarse > kDenseCoarseMax) {
     delete mg;
@@ -934,22 +945,26 @@ hx_status hx_mg_update(hx_mg mg, const double* u, void* stream) {
       return mg_fail(mg, HX_E_HIP, "hx_mg_update: transfer of the linearisation point");
   }
   for (int l = 0; l < L; ++l) {
+    const hx_precision lp = level_prec(mg, l);
     const hx_status st = hx_update_linearization(mg->lv[l], mg->buf[l][B_U].as<double>(), HX_STORE_TANGENT,
-                                                 mg_prec(mg), mg->stream);
+                                                 lp, mg->stream);
     if (st != HX_OK) return mg_fail(mg, st, std::string("hx_mg_update: level update: ") + hx_last_error(mg->lv[l]));
     e = mg->fp32 ? level_diagonal<float>(mg, l) : level_diagonal<double>(mg, l);
     if (e != hipSuccess) return mg_fail(mg, HX_E_HIP, "hx_mg_update: diagonal");
     // the level operator's own storage mode (the diagonal above needed the tangent)
+    // (16-bit data exists for the stored tangent only)
     hx_status sm = HX_OK;
-    if (mg->mode[l] < 0 && mg->opt.level_mode == HX_STORE_AUTO) {
+    if (sixteen_bit(lp)) {
+      mg->mode[l] = HX_STORE_TANGENT;
+    } else if (mg->mode[l] < 0 && mg->opt.level_mode == HX_STORE_AUTO) {
       hx_storage best = HX_STORE_TANGENT;
-      sm = hx_autotune_storage(mg->lv[l], mg->buf[l][B_U].as<double>(), mg_prec(mg), 5, &best, nullptr, mg->stream);
+      sm = hx_autotune_storage(mg->lv[l], mg->buf[l][B_U].as<double>(), lp, 5, &best, nullptr, mg->stream);
       if (sm == HX_OK) mg->mode[l] = best;
     } else {
       if (mg->mode[l] < 0) mg->mode[l] = mg->opt.level_mode;
       if (mg->mode[l] != HX_STORE_TANGENT)
         sm = hx_update_linearization(mg->lv[l], mg->buf[l][B_U].as<double>(), static_cast<hx_storage>(mg->mode[l]),
-                                     mg_prec(mg), mg->stream);
+                                     lp, mg->stream);
     }
     if (sm != HX_OK) return mg_fail(mg, sm, std::string("hx_mg_update: level mode: ") + hx_last_error(mg->lv[l]));
     double lm = 1.0, ln = 1.0;

@@ -151,7 +151,7 @@ def test_surface_load_matches_oracle(device):
     assert rel(ops[0].surface_load(2, 0.1), fem.surface_load(pbs[0], 2, 0.1)) < 1e-14
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64", "fp32_bf16", "fp32_fp16"])
 def test_newton_solve_box(device, precision):
     ops, pbs = _levels((3, 2, 2), [2, 1], faces=(0,), mu=1.0, lam=10.0)
     f = -ops[0].surface_load(1, 0.1)   # outward traction (negative pressure) on +x
