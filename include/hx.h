@@ -165,7 +165,9 @@ hx_status hx_residual(hx_ctx ctx, const double* u, double* r, void* stream);
 /* Linearisation update at u (Algorithm 1, "update quadrature point data"): stores the data of
  * the requested mode in the requested storage precision. The FP64 class (prec == HX_FP64) and
  * the FP32 class (the three FP32 values) are separate slots, so one context can hold an FP64
- * operator and an FP32 operator at once. Waits for the stream; returns HX_E_INVERTED if J <= 0
+ * operator and an FP32 operator at once. For the fibre law in the FP32 NONE and FINV_J modes the
+ * tension switches (I*_i > 1) are decided here in FP64 and kept (one byte per q-point), so that
+ * rounding in the FP32 apply cannot flip them. Waits for the stream; returns HX_E_INVERTED if J <= 0
  * at some q-point and HX_E_NONFINITE on NaN/Inf. The data is kept even on those errors. */
 hx_status hx_update_linearization(hx_ctx ctx, const double* u, hx_storage mode,
                                   hx_precision prec, void* stream);

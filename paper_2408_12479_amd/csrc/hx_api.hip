@@ -356,7 +356,6 @@ hipError_t init_output(R* dst, const R* du, const Lattice& L, hipStream_t s) {
 HostArgs hx::args_for(const hx_ctx_s* c) {
   HostArgs h = c->base;
   h.vert64 = c->vert64;
-  h.vert32 = c->vert32;
   h.flag = c->flag;
   h.cblk64 = c->cblk64;
   h.cblk32 = c->cblk32;
@@ -388,6 +387,7 @@ void release_slot(Slot& s) {
   if (s.qdata) (void)hipFree(s.qdata);
   if (s.cscale) (void)hipFree(s.cscale);
   if (s.uk) (void)hipFree(s.uk);
+  if (s.act) (void)hipFree(s.act);
   s = Slot();
 }
 
@@ -552,10 +552,8 @@ hx_status hx_setup(const hx_mesh* mesh, int32_t p, const hx_material* mat, const
     return fail(nullptr, HX_E_INVERTED, "hx_setup: det J0 <= 0 at a Gauss point of some cell");
   }
 
-  std::vector<float> v32(c->vert_host.begin(), c->vert_host.end());
   hipError_t e;
   if ((e = hipMalloc(&c->vert64, 3 * nv * sizeof(double))) != hipSuccess ||
-      (e = hipMalloc(&c->vert32, 3 * nv * sizeof(float))) != hipSuccess ||
       (e = hipMalloc(&c->flag, sizeof(int))) != hipSuccess ||
       (e = hipMalloc(&c->cblk64, kConstBlockBytes)) != hipSuccess ||
       (e = hipMalloc(&c->cblk32, kConstBlockBytes)) != hipSuccess) {
@@ -563,7 +561,6 @@ hx_status hx_setup(const hx_mesh* mesh, int32_t p, const hx_material* mat, const
     return hip_fail(nullptr, e, "hx_setup: allocation");
   }
   if ((e = hipMemcpy(c->vert64, c->vert_host.data(), 3 * nv * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(c->vert32, v32.data(), 3 * nv * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemset(c->flag, 0, sizeof(int))) != hipSuccess) {
     hx_destroy(c);
     return hip_fail(nullptr, e, "hx_setup: copy");
@@ -599,7 +596,6 @@ hx_status hx_destroy(hx_ctx ctx) {
   (void)hipSetDevice(ctx->device);
   for (Slot& s : ctx->slot) release_slot(s);
   if (ctx->vert64) (void)hipFree(ctx->vert64);
-  if (ctx->vert32) (void)hipFree(ctx->vert32);
   if (ctx->flag) (void)hipFree(ctx->flag);
   if (ctx->cblk64) (void)hipFree(ctx->cblk64);
   if (ctx->cblk32) (void)hipFree(ctx->cblk32);
@@ -708,11 +704,30 @@ hx_status hx_update_linearization(hx_ctx ctx, const double* u, hx_storage mode, 
     else
       copy_convert<float><<<grid_for(n), 256, 0, s>>>(u, static_cast<float*>(sl.uk), n);
   }
+  // FP32 recompute and F^-1+J modes of the fibre law: the tension switches are decided here in
+  // FP64 and kept, so that the FP32 apply cannot flip them by rounding
+  const bool keep_act = ctx->base.mat.law == HX_LAW_FIBER && prec != HX_FP64 &&
+                        (mode == HX_STORE_NONE || mode == HX_STORE_FINV_J);
+  if (keep_act) {
+    const size_t ab = static_cast<size_t>(padded_cells) * Q;
+    if (sl.act_bytes < ab) {
+      if (sl.act) (void)hipFree(sl.act);
+      sl.act = nullptr;
+      sl.act_bytes = 0;
+      if ((e = hipMalloc(&sl.act, ab)) != hipSuccess) {
+        sl.valid = false;
+        return hip_fail(ctx, e, "hx_update_linearization: fibre switches");
+      }
+      sl.act_bytes = ab;
+    }
+  }
+  sl.keep_act = keep_act;
   clear_flag<<<1, 1, 0, s>>>(ctx->flag);
   HostArgs h = args_for(ctx);
   h.in0 = u;
   h.qdata_w = sl.qdata;
   h.cscale_w = sl.cscale;
+  h.act_w = keep_act ? sl.act : nullptr;
   HostOp op{OpKind::Update, ctx->base.mat.law, mode, st, false};
   bool ok = false;
   e = dispatch(ctx->p, op, h, s, &ok);
@@ -748,6 +763,7 @@ hx_status hx_apply_tangent(hx_ctx ctx, const void* du, void* dst, hx_precision p
   h.out = dst;
   h.qdata = sl.qdata;
   h.cscale = sl.cscale;
+  h.act = sl.keep_act ? sl.act : nullptr;
   HostOp op{OpKind::Apply, ctx->base.mat.law, sl.mode, sl.store, fp32};
   bool ok = false;
   e = dispatch(ctx->p, op, h, s, &ok);

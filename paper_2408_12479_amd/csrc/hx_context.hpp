@@ -18,6 +18,9 @@ struct Slot {
   size_t qcap = 0;     // bytes allocated (kept across mode switches)
   float* cscale = nullptr;
   void* uk = nullptr;  // linearisation point (recompute mode): double or float
+  uint8_t* act = nullptr;  // fibre switches per q-point (FP32 slot, recompute and F^-1+J modes)
+  size_t act_bytes = 0;
+  bool keep_act = false;   // the apply reads act
 };
 
 int cells_per_block(int p);
@@ -33,7 +36,6 @@ struct hx_ctx_s {
   std::vector<double> gll;
   std::vector<double> vert_host;  // [V][3]
   double* vert64 = nullptr;
-  float* vert32 = nullptr;
   int* flag = nullptr;
   void* cblk64 = nullptr;
   void* cblk32 = nullptr;

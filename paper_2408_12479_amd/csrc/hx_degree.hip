@@ -62,13 +62,12 @@ KernelArgs<N, R> make_args(const HostArgs& h) {
   a.L = h.L;
   if constexpr (std::is_same<R, double>::value) {
     a.c = static_cast<const Consts<N, R>*>(h.cblk64);
-    a.vert = h.vert64;
     a.fib = h.fib64;
   } else {
     a.c = static_cast<const Consts<N, R>*>(h.cblk32);
-    a.vert = h.vert32;
     a.fib = h.fib32;
   }
+  a.vert = h.vert64;
   a.in0 = static_cast<const R*>(h.in0);
   a.in1 = static_cast<const R*>(h.in1);
   a.out = static_cast<R*>(h.out);
@@ -77,6 +76,8 @@ KernelArgs<N, R> make_args(const HostArgs& h) {
   a.cscale = h.cscale;
   a.cscale_w = h.cscale_w;
   a.flag = h.flag;
+  a.act = h.act;
+  a.act_w = h.act_w;
   return a;
 }
 

@@ -57,7 +57,7 @@ template <int N, typename R>
 struct KernelArgs {
   Lattice L;
   const Consts<N, R>* __restrict__ c;
-  const R* vert;        // vertices [Vz][Vy][Vx][3]
+  const double* vert;   // vertices [Vz][Vy][Vx][3] (FP64 in every arithmetic)
   const R* in0;         // gathered vector (du, or u for residual/update)
   const R* in1;         // linearisation point u_k (recompute mode)
   R* out;               // output vector (apply, residual)
@@ -67,6 +67,8 @@ struct KernelArgs {
   float* cscale_w;
   int* flag;            // status bits (kFlagInverted | kFlagNonFinite)
   const R* fib;         // per-cell fibre tensors [cell][kFibWords] (fibre law with cell frames)
+  const uint8_t* act;   // fibre switches per q-point [block][cells_per_block * Q] (FP32 apply), or NULL
+  uint8_t* act_w;       // written by the update, or NULL
 };
 
 // Per-cell fibre data: H4 (3x3), H6 (3x3), M4, M6 in global coordinates.
@@ -93,7 +95,6 @@ struct HostArgs {
   hx_material mat;
   int32_t jpow_iters;
   const double* vert64;
-  const float* vert32;
   const void* in0;
   const void* in1;
   void* out;
@@ -104,6 +105,8 @@ struct HostArgs {
   int* flag;
   void* cblk64;   // device block holding Consts<N, double>
   void* cblk32;   // device block holding Consts<N, float>
+  const uint8_t* act;   // fibre switches decided by the FP64 update (FP32 recompute modes)
+  uint8_t* act_w;
   const double* fib64;  // per-cell fibre tensors, or NULL (material tensors everywhere)
   const float* fib32;
 };

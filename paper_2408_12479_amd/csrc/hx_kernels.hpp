@@ -191,13 +191,17 @@ struct QState {
   R F[9], Fi[9];
   R Jm, lnJ, Jp, c1, c2;
   R c3[2], Ei[2], dfac[2];
+  int forced = -1;  // fibre tension switches taken from the update (bit f: family f active), or -1
+  int bits = 0;     // the switches as decided (bit f: family f active)
 };
 
 template <int LAW, typename R>
 __device__ __forceinline__ void fiber_scalars(const MaterialK<R>& m, const R* Hf, const R* M,
                                               R Ei, R ImOne, int f, QState<R>& s) {
-  // c3 = 2 k1 exp(k2 E_i^2) if I*_i > 1 (strict), else 0  (fibre model, c3 definition)
-  const bool active = ImOne > R(0);
+  // c3 = 2 k1 exp(k2 E_i^2) if I*_i > 1 (strict), else 0  (fibre model, c3 definition). An FP32
+  // apply takes the switch as the FP64 update decided it, so that rounding cannot flip it.
+  const bool active = s.forced >= 0 ? ((s.forced >> f) & 1) != 0 : ImOne > R(0);
+  if (active) s.bits |= 1 << f;
   const R e2 = Ei * Ei;
   s.Ei[f] = Ei;
   s.c3[f] = active ? R(2) * m.k1 * m_exp(m.k2 * e2) : R(0);
@@ -496,18 +500,25 @@ __device__ __forceinline__ void apply1d(const R* M, const R* in, R* out) {
 }
 
 // Runs fn(le, set, a, b) for every pencil of NSETS fields of EB cells, spread over the
-// workgroup's threads.
+// workgroup's threads. The job decomposition is computed unconditionally from the thread index
+// (the guard comes after it), so that phases with the same NSETS share it instead of repeating
+// the integer divisions.
 template <int N, int EB, int NSETS, typename Fn>
 __device__ __forceinline__ void pencil_jobs(Fn&& fn) {
   constexpr int N2 = N * N;
   constexpr int NT = EB * N * N * N;
   constexpr int PER = NSETS * N2;
-  for (int job = threadIdx.x; job < EB * PER; job += NT) {
+  constexpr int TOTAL = EB * PER;
+  constexpr int ROUNDS = (TOTAL + NT - 1) / NT;
+#pragma unroll
+  for (int r = 0; r < ROUNDS; ++r) {
+    const int job = static_cast<int>(threadIdx.x) + r * NT;
     const int le = job / PER;
-    const int r = job - le * PER;
-    const int set = r / N2;
-    const int pl = r - set * N2;
-    fn(le, set, pl % N, pl / N);
+    const int rr = job - le * PER;
+    const int set = rr / N2;
+    const int pl = rr - set * N2;
+    const int a = pl % N, b = pl / N;
+    if (job < TOTAL) fn(le, set, a, b);
   }
 }
 
@@ -923,7 +934,9 @@ __device__ __forceinline__ void spatial_action(const R* d, const MaterialK<R>& m
 template <int N, int EB, typename R>
 __device__ __forceinline__ void load_vertices(const KernelArgs<N, R>& a, R* sv, int e0,
                                               const CellPos& c0) {
-  // 24 values per cell (8 vertices x 3 coordinates), spread over the workgroup
+  // 24 values per cell (8 vertices x 3 coordinates), spread over the workgroup, relative to the
+  // cell's first vertex and formed in FP64: the map uses only vertex differences, and differences
+  // of FP32 absolute coordinates would lose digits in proportion to |X| / h
   constexpr int NT = EB * N * N * N;
   for (int idx = threadIdx.x; idx < EB * 24; idx += NT) {
     const int le = idx / 24, q = idx - 24 * le;
@@ -936,7 +949,8 @@ __device__ __forceinline__ void load_vertices(const KernelArgs<N, R>& a, R* sv, 
     vy = vy >= a.L.Vy ? vy - a.L.Vy : vy;
     vz = vz >= a.L.Vz ? vz - a.L.Vz : vz;
     const int64_t vid = vx + static_cast<int64_t>(a.L.Vx) * (vy + static_cast<int64_t>(a.L.Vy) * vz);
-    sv[le * 24 + q] = a.vert[3 * vid + comp];
+    const int64_t v0 = cp.ex + static_cast<int64_t>(a.L.Vx) * (cp.ey + static_cast<int64_t>(a.L.Vy) * cp.ez);
+    sv[le * 24 + q] = static_cast<R>(a.vert[3 * vid + comp] - a.vert[3 * v0 + comp]);
   }
 }
 
@@ -1044,6 +1058,9 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
     R K[9];
     const R wdet = valid ? qpoint_geometry(a, sv + le * 24, q, K) : R(0);
     QState<R> st;
+    if constexpr (kIsFiber<LAW>) {
+      if (a.act && valid) st.forced = a.act[static_cast<int64_t>(blockIdx.x) * EBQ + qi];
+    }
     if constexpr (MODE == HX_STORE_NONE) {
       R H[9], E[9];
       to_physical(g1, K, H);
@@ -1082,6 +1099,9 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
     const bool ok = state_from_H<LAW>(H, m, fb, st, E);
     int bad = 0;
     if (valid && !ok) bad |= kFlagInverted;
+    if constexpr (kIsFiber<LAW>) {
+      if (a.act_w && valid) a.act_w[static_cast<int64_t>(blockIdx.x) * EBQ + qi] = static_cast<uint8_t>(st.bits);
+    }
     ST* qw = static_cast<ST*>(a.qdata_w) + qblk;
     if constexpr (MODE == HX_STORE_FINV_J) {
       R chk = st.Jm;
