@@ -256,70 +256,6 @@ __global__ void copy_convert(const double* __restrict__ src, T* __restrict__ dst
     dst[i] = static_cast<T>(src[i]);
 }
 
-// Output initialisation of the apply and the residual: zero fill with 16-byte stores when the
-// output is 16-byte aligned (the element kernels store interior nodes and add into shared ones),
-// then du copied into the rows of the constrained faces (apply only), one thread per face node.
-template <typename R>
-__global__ void zero_fill_kernel(R* __restrict__ out, int64_t n) {
-  constexpr int V = 16 / sizeof(R);
-  using Vec = typename std::conditional<sizeof(R) == 8, double2, float4>::type;
-  const int64_t nv = n / V;
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  Vec z;
-  std::memset(&z, 0, sizeof(z));
-  Vec* o = reinterpret_cast<Vec*>(out);
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < nv; i += stride) o[i] = z;
-  for (int64_t i = nv * V + blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n; i += stride)
-    out[i] = R(0);
-}
-
-template <typename R>
-__global__ void zero_fill_scalar_kernel(R* __restrict__ out, int64_t n) {
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n; i += stride) out[i] = R(0);
-}
-
-// face f (0..5 = -x,+x,-y,+y,-z,+z) node count and the node of face-local index k
-__device__ __host__ __forceinline__ int64_t face_nodes(const Lattice& L, int f) {
-  const int d = f >> 1;
-  return d == 0 ? static_cast<int64_t>(L.Ny) * L.Nz : (d == 1 ? static_cast<int64_t>(L.Nx) * L.Nz
-                                                             : static_cast<int64_t>(L.Nx) * L.Ny);
-}
-
-template <typename R>
-__global__ void copy_constrained_kernel(R* __restrict__ out, const R* __restrict__ du, Lattice L) {
-  const int64_t n = L.n_nodes;
-  int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  for (int f = 0; f < 6; ++f) {
-    const int64_t m = face_nodes(L, f);
-    if (!((L.dir_faces >> f) & 1u)) continue;
-    if (k >= m) {
-      k -= m;
-      continue;
-    }
-    const int d = f >> 1;
-    const int side = f & 1;
-    int I, J, K;
-    if (d == 0) {
-      I = side ? L.Nx - 1 : 0;
-      J = static_cast<int>(k % L.Ny);
-      K = static_cast<int>(k / L.Ny);
-    } else if (d == 1) {
-      J = side ? L.Ny - 1 : 0;
-      I = static_cast<int>(k % L.Nx);
-      K = static_cast<int>(k / L.Nx);
-    } else {
-      K = side ? L.Nz - 1 : 0;
-      I = static_cast<int>(k % L.Nx);
-      J = static_cast<int>(k / L.Nx);
-    }
-    const int64_t node = I + static_cast<int64_t>(L.Nx) * (J + static_cast<int64_t>(L.Ny) * K);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) out[c * n + node] = du[c * n + node];
-    return;
-  }
-}
-
 __global__ void clear_flag(int* f) { *f = 0; }
 
 // A fixed non-trivial direction for timing runs: x_i = 1 + (i mod 7) / 8.
@@ -334,29 +270,13 @@ int grid_for(int64_t n) {
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(b, 8192)));
 }
 
-// dst = 0, then dst = du on the constrained rows (if du is given)
-template <typename R>
-hipError_t init_output(R* dst, const R* du, const Lattice& L, hipStream_t s) {
-  const int64_t n = 3 * L.n_nodes;
-  if ((reinterpret_cast<uintptr_t>(dst) & 15u) == 0)
-    zero_fill_kernel<R><<<grid_for((n + 1) / 2), 256, 0, s>>>(dst, n);
-  else
-    zero_fill_scalar_kernel<R><<<grid_for(n), 256, 0, s>>>(dst, n);
-  if (du && L.dir_faces) {
-    int64_t m = 0;
-    for (int f = 0; f < 6; ++f)
-      if ((L.dir_faces >> f) & 1u) m += face_nodes(L, f);
-    copy_constrained_kernel<R><<<static_cast<unsigned>((m + 255) / 256), 256, 0, s>>>(dst, du, L);
-  }
-  return hipGetLastError();
-}
-
 }  // namespace
 
 HostArgs hx::args_for(const hx_ctx_s* c) {
   HostArgs h = c->base;
   h.vert64 = c->vert64;
   h.flag = c->flag;
+  h.ework = c->ework;
   h.cblk64 = c->cblk64;
   h.cblk32 = c->cblk32;
   h.fib64 = c->fib64;
@@ -555,6 +475,8 @@ hx_status hx_setup(const hx_mesh* mesh, int32_t p, const hx_material* mat, const
   hipError_t e;
   if ((e = hipMalloc(&c->vert64, 3 * nv * sizeof(double))) != hipSuccess ||
       (e = hipMalloc(&c->flag, sizeof(int))) != hipSuccess ||
+      (e = hipMalloc(&c->ework, 3 * cells * static_cast<int64_t>((p + 1) * (p + 1) * (p + 1)) * sizeof(double))) !=
+          hipSuccess ||
       (e = hipMalloc(&c->cblk64, kConstBlockBytes)) != hipSuccess ||
       (e = hipMalloc(&c->cblk32, kConstBlockBytes)) != hipSuccess) {
     hx_destroy(c);
@@ -597,6 +519,7 @@ hx_status hx_destroy(hx_ctx ctx) {
   for (Slot& s : ctx->slot) release_slot(s);
   if (ctx->vert64) (void)hipFree(ctx->vert64);
   if (ctx->flag) (void)hipFree(ctx->flag);
+  if (ctx->ework) (void)hipFree(ctx->ework);
   if (ctx->cblk64) (void)hipFree(ctx->cblk64);
   if (ctx->cblk32) (void)hipFree(ctx->cblk32);
   if (ctx->fib64) (void)hipFree(ctx->fib64);
@@ -639,15 +562,12 @@ hx_status hx_residual(hx_ctx ctx, const double* u, double* r, void* stream) {
   if (!ctx || !u || !r) return fail(ctx, HX_E_ARG, "hx_residual: NULL argument");
   if (static_cast<const void*>(u) == static_cast<const void*>(r)) return fail(ctx, HX_E_ARG, "hx_residual: u and r alias");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int64_t n = 3 * ctx->L.n_nodes;
-  hipError_t e = init_output<double>(r, nullptr, ctx->L, s);
-  if (e != hipSuccess) return hip_fail(ctx, e, "hx_residual: init");
   HostArgs h = args_for(ctx);
   h.in0 = u;
   h.out = r;
   HostOp op{OpKind::Residual, ctx->base.mat.law, HX_STORE_NONE, kStoreF64, false};
   bool ok = false;
-  e = dispatch(ctx->p, op, h, s, &ok);
+  const hipError_t e = dispatch(ctx->p, op, h, s, &ok);
   if (!ok) return fail(ctx, HX_E_UNSUPPORTED, "hx_residual: not built");
   if (e != hipSuccess) return hip_fail(ctx, e, "hx_residual: launch");
   return HX_OK;
@@ -753,10 +673,6 @@ hx_status hx_apply_tangent(hx_ctx ctx, const void* du, void* dst, hx_precision p
   const Slot& sl = ctx->slot[fp32 ? 1 : 0];
   if (!sl.valid) return fail(ctx, HX_E_STATE, "hx_apply_tangent: no linearisation stored for this precision");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int64_t n = 3 * ctx->L.n_nodes;
-  hipError_t e = fp32 ? init_output<float>(static_cast<float*>(dst), static_cast<const float*>(du), ctx->L, s)
-                      : init_output<double>(static_cast<double*>(dst), static_cast<const double*>(du), ctx->L, s);
-  if (e != hipSuccess) return hip_fail(ctx, e, "hx_apply_tangent: init");
   HostArgs h = args_for(ctx);
   h.in0 = du;
   h.in1 = sl.uk;
@@ -766,7 +682,7 @@ hx_status hx_apply_tangent(hx_ctx ctx, const void* du, void* dst, hx_precision p
   h.act = sl.keep_act ? sl.act : nullptr;
   HostOp op{OpKind::Apply, ctx->base.mat.law, sl.mode, sl.store, fp32};
   bool ok = false;
-  e = dispatch(ctx->p, op, h, s, &ok);
+  const hipError_t e = dispatch(ctx->p, op, h, s, &ok);
   if (!ok) return fail(ctx, HX_E_UNSUPPORTED, "hx_apply_tangent: combination not built");
   if (e != hipSuccess) return hip_fail(ctx, e, "hx_apply_tangent: launch");
   return HX_OK;

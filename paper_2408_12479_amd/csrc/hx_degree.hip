@@ -71,6 +71,7 @@ KernelArgs<N, R> make_args(const HostArgs& h) {
   a.in0 = static_cast<const R*>(h.in0);
   a.in1 = static_cast<const R*>(h.in1);
   a.out = static_cast<R*>(h.out);
+  a.ework = static_cast<R*>(h.ework);
   a.qdata = h.qdata;
   a.qdata_w = h.qdata_w;
   a.cscale = h.cscale;
@@ -88,6 +89,15 @@ hipError_t launch(const HostArgs& h, hipStream_t s) {
   const int nblk = (h.L.n_cells + EB - 1) / EB;
   if (nblk == 0) return hipSuccess;
   element_kernel<N, EB, R, KIND, MODE, LAW, S><<<dim3(nblk), dim3(EB * N * N * N), 0, s>>>(a);
+  if constexpr (KIND == 0 || KIND == 1) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // rows of the nodes on cell faces: sum of the cells' bricks; constrained rows du (apply) or 0
+    const int xb = (h.L.Nx + 63) / 64;
+    const int64_t rb = (static_cast<int64_t>(h.L.Ny) * h.L.Nz + 3) / 4;
+    assemble_kernel<N, R><<<dim3(static_cast<unsigned>(xb * rb)), dim3(64, 4), 0, s>>>(
+        h.L, a.ework, KIND == 0 ? a.in0 : nullptr, a.out, xb);
+  }
   return hipGetLastError();
 }
 

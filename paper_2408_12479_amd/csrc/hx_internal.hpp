@@ -61,6 +61,8 @@ struct KernelArgs {
   const R* in0;         // gathered vector (du, or u for residual/update)
   const R* in1;         // linearisation point u_k (recompute mode)
   R* out;               // output vector (apply, residual)
+  R* ework;             // cell-boundary rows of the element vectors on the broken lattice
+                        // [3][nz*N][ny*N][nx*N] (apply, residual; summed by assemble_kernel)
   const void* qdata;    // stored per-q-point planes [block][W][cells_per_block * Q]
   void* qdata_w;        // planes written by the update
   const float* cscale;  // per-cell power-of-two scale of binary16 data
@@ -98,6 +100,7 @@ struct HostArgs {
   const void* in0;
   const void* in1;
   void* out;
+  void* ework;    // 3 * n_cells * (p+1)^3 FP64 words, reused as FP32 by FP32 applies
   const void* qdata;
   void* qdata_w;
   const float* cscale;

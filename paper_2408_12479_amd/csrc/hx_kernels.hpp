@@ -628,11 +628,14 @@ __device__ __forceinline__ void forward_vector(const KernelArgs<N, R>& a, R* sb,
 }
 
 // Backward pass: integrates the test coefficients t[c*3 + d] of every q-thread against the
-// reference gradients of the basis and adds the element vectors into a.out.
-// The last contraction is written back to LDS so that the scatter runs one node per thread: the
-// lanes of a wavefront then cover contiguous x-rows and their atomics combine into few cache-line
-// requests (scattering straight from the pencil jobs costs about twice the kernel time).
-// Element-interior nodes belong to one cell only and are stored; shared nodes use atomics.
+// reference gradients of the basis and writes the element vector.
+// The last contraction is written back to LDS so that the output runs one node per thread, the
+// lanes of a wavefront covering contiguous x-rows. Element-interior nodes belong to one cell only
+// and are stored into a.out. The rows of nodes on the cell's faces go, without atomics, to the
+// broken lattice a.ework, where every cell owns an N^3 brick: the value of local node (i, j, k)
+// of cell (ex, ey, ez) sits at (ex N + i, ey N + j, ez N + k) of an (nx N) x (ny N) x (nz N)
+// array per component; assemble_kernel then sums the bricks that meet at each shared node.
+// (Device-scope FP64 atomics on the shared nodes cost about a third of the apply on MI355X.)
 template <int N, int EB, typename R>
 __device__ __forceinline__ void backward_scatter(const KernelArgs<N, R>& a, R* sb, int e0,
                                                  const CellPos& c0, int le_me, int q_me,
@@ -716,16 +719,93 @@ __device__ __forceinline__ void backward_scatter(const KernelArgs<N, R>& a, R* s
       const int64_t node = node_of(L, cp, i, j, k, cons);
       if (!cons) {
         const bool inner = i > 0 && i < P && j > 0 && j < P && k > 0 && k < P;
+        const int64_t EX = static_cast<int64_t>(L.nx) * N, EY = static_cast<int64_t>(L.ny) * N;
+        const int64_t ES = EX * EY * (static_cast<int64_t>(L.nz) * N);
+        const int64_t pos = (cp.ex * N + i) + EX * ((cp.ey * N + j) + EY * (static_cast<int64_t>(cp.ez) * N + k));
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const R v = sb[le_me * CB + (3 * c) * Q + q_me];
-          R* dst = a.out + c * L.n_nodes + node;
-          if (inner) *dst = v;
-          else unsafeAtomicAdd(dst, v);
+          if (inner) a.out[c * L.n_nodes + node] = v;
+          else a.ework[c * ES + pos] = v;
         }
       }
     }
   }
+}
+
+// ------------------------------------------------------------------------------------------
+// Assembly of the rows of cell-boundary nodes
+// ------------------------------------------------------------------------------------------
+// Cells meeting at lattice index Ig along one direction (ncell cells, Nn nodes; periodic if
+// Nn == ncell * P): up to two (cell, local index) pairs, the lower cell first.
+template <int P>
+__device__ __forceinline__ int cells_at(int Ig, int ncell, int Nn, int* cc, int* ll) {
+  const int ec = Ig / P, il = Ig - ec * P;
+  if (il) {
+    cc[0] = ec;
+    ll[0] = il;
+    return 1;
+  }
+  int cnt = 0;
+  if (ec > 0) {
+    cc[0] = ec - 1;
+    ll[0] = P;
+    cnt = 1;
+  } else if (Nn == ncell * P) {
+    cc[0] = ncell - 1;
+    ll[0] = P;
+    cnt = 1;
+  }
+  if (ec < ncell) {
+    cc[cnt] = ec;
+    ll[cnt] = 0;
+    ++cnt;
+  }
+  return cnt;
+}
+
+// One thread per lattice node of a 64 x 4 tile of x-rows; nodes inside a cell were stored by the
+// element kernel. Every other node gets the sum of the bricks of the 2, 4 or 8 cells that share
+// it, in a fixed order (the apply is deterministic), or, on constrained rows, cons_src (du of the
+// apply: identity rows) or zero (residual).
+template <int N, typename R>
+__global__ void __launch_bounds__(256) assemble_kernel(Lattice L, const R* __restrict__ E,
+                                                       const R* __restrict__ cons_src, R* __restrict__ out,
+                                                       int xblocks) {
+  constexpr int P = N - 1;
+  const int bx = static_cast<int>(blockIdx.x) % xblocks;
+  const int row = (static_cast<int>(blockIdx.x) / xblocks) * 4 + static_cast<int>(threadIdx.y);
+  const int I = bx * 64 + static_cast<int>(threadIdx.x);
+  if (I >= L.Nx || row >= static_cast<int64_t>(L.Ny) * L.Nz) return;
+  const int K = row / L.Ny, J = row - K * L.Ny;
+  if ((I % P) && (J % P) && (K % P)) return;
+  const int64_t n = L.n_nodes;
+  const int64_t node = I + static_cast<int64_t>(L.Nx) * row;
+  if (cons_x(L, I) || cons_yz(L, J, K)) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[c * n + node] = cons_src ? cons_src[c * n + node] : R(0);
+    return;
+  }
+  int cx[2], lx[2], cy[2], ly[2], cz[2], lz[2];
+  const int nxc = cells_at<P>(I, L.nx, L.Nx, cx, lx);
+  const int nyc = cells_at<P>(J, L.ny, L.Ny, cy, ly);
+  const int nzc = cells_at<P>(K, L.nz, L.Nz, cz, lz);
+  const int64_t EX = static_cast<int64_t>(L.nx) * N, EY = static_cast<int64_t>(L.ny) * N;
+  const int64_t ES = EX * EY * (static_cast<int64_t>(L.nz) * N);
+  R s0 = R(0), s1 = R(0), s2 = R(0);
+  for (int a = 0; a < nzc; ++a)
+    for (int b = 0; b < nyc; ++b) {
+      const int64_t rowpos = EX * ((cy[b] * N + ly[b]) + EY * (static_cast<int64_t>(cz[a]) * N + lz[a]));
+      for (int d = 0; d < nxc; ++d) {
+        const R* e = E + rowpos + cx[d] * N + lx[d];
+        s0 += e[0];
+        s1 += e[ES];
+        s2 += e[2 * ES];
+      }
+    }
+  out[node] = s0;
+  out[n + node] = s1;
+  out[2 * n + node] = s2;
 }
 
 // ------------------------------------------------------------------------------------------
