@@ -37,7 +37,14 @@
  *
  * Asynchrony: operator calls enqueue kernels on the given stream and return without waiting,
  * except hx_update_linearization, which waits on its stream to read the device status flag.
- * Calls on one context must not overlap in time on different streams.
+ * Calls on one context must not overlap in time on different streams: hx_residual and
+ * hx_apply_tangent share the context's element-vector buffer (below).
+ *
+ * Assembly (Section 6, the sum of the element vectors): an apply or residual is two kernels. The
+ * element kernel stores rows of nodes inside a cell directly and writes the rows of nodes on cell
+ * faces into a per-context buffer in which every cell owns its own (p+1)^3 brick; a node kernel
+ * then adds, in a fixed order, the bricks of the cells that share each such node and writes the
+ * constrained rows. No atomics are used, so repeated calls give bit-identical results.
  */
 #ifndef HX_H
 #define HX_H
@@ -139,7 +146,8 @@ typedef struct {
 /* Builds a context: copies the mesh to the device, sets up the 1D basis tables for degree p,
  * checks det J0 > 0 at every Gauss point of every cell (HX_E_INVERTED otherwise).
  * p in [1, 6]. opt may be NULL (defaults). On success *out owns device memory until
- * hx_destroy. The current HIP device at the time of the call is the context's device. */
+ * hx_destroy, among it the element-vector buffer of 24 * n_cells * (p+1)^3 bytes. The current
+ * HIP device at the time of the call is the context's device. */
 hx_status hx_setup(const hx_mesh* mesh, int32_t p, const hx_material* mat,
                    const hx_options* opt, hx_ctx* out);
 
