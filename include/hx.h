@@ -41,10 +41,10 @@
  * hx_apply_tangent share the context's element-vector buffer (below).
  *
  * Assembly (Section 6, the sum of the element vectors): an apply or residual is two kernels. The
- * element kernel stores rows of nodes inside a cell directly and writes the rows of nodes on cell
- * faces into a per-context buffer in which every cell owns its own (p+1)^3 brick; a node kernel
- * then adds, in a fixed order, the bricks of the cells that share each such node and writes the
- * constrained rows. No atomics are used, so repeated calls give bit-identical results.
+ * element kernel writes each cell's element vector into a per-context buffer in which every cell
+ * owns its own (p+1)^3 brick; a node kernel then adds, in a fixed order, the bricks of the cells
+ * that share each node and writes every row of the output, the constrained rows included. No
+ * atomics are used, so repeated calls give bit-identical results.
  */
 #ifndef HX_H
 #define HX_H

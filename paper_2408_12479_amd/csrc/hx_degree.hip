@@ -17,12 +17,14 @@ namespace {
 constexpr int N = HX_DEGREE + 1;
 
 // Cells per workgroup: the workgroup holds EB * N^3 q-threads; chosen so that the thread count
-// is close to a multiple of the 64-wide wavefront.
+// is close to a multiple of the 64-wide wavefront. Q3 and Q4 take 4 cells: their pencil phases
+// (3 N^2 jobs per cell) then fill whole wavefronts better than with 2, which measured faster in
+// the stored-data modes; Q6 stays at one cell (two were slower).
 template <int n> struct Blocking { static constexpr int EB = 1; };
 template <> struct Blocking<2> { static constexpr int EB = 8; };   //  64 threads
 template <> struct Blocking<3> { static constexpr int EB = 7; };   // 189 of 192
-template <> struct Blocking<4> { static constexpr int EB = 2; };   // 128
-template <> struct Blocking<5> { static constexpr int EB = 2; };   // 250 of 256
+template <> struct Blocking<4> { static constexpr int EB = 4; };   // 256
+template <> struct Blocking<5> { static constexpr int EB = 4; };   // 500 of 512
 template <> struct Blocking<6> { static constexpr int EB = 1; };   // 216 of 256
 template <> struct Blocking<7> { static constexpr int EB = 1; };   // 343 of 384
 

@@ -630,12 +630,13 @@ __device__ __forceinline__ void forward_vector(const KernelArgs<N, R>& a, R* sb,
 // Backward pass: integrates the test coefficients t[c*3 + d] of every q-thread against the
 // reference gradients of the basis and writes the element vector.
 // The last contraction is written back to LDS so that the output runs one node per thread, the
-// lanes of a wavefront covering contiguous x-rows. Element-interior nodes belong to one cell only
-// and are stored into a.out. The rows of nodes on the cell's faces go, without atomics, to the
-// broken lattice a.ework, where every cell owns an N^3 brick: the value of local node (i, j, k)
-// of cell (ex, ey, ez) sits at (ex N + i, ey N + j, ez N + k) of an (nx N) x (ny N) x (nz N)
-// array per component; assemble_kernel then sums the bricks that meet at each shared node.
-// (Device-scope FP64 atomics on the shared nodes cost about a third of the apply on MI355X.)
+// lanes of a wavefront covering contiguous x-rows. The element vector goes, without atomics, to
+// the broken lattice a.ework, where every cell owns an N^3 brick: the value of local node
+// (i, j, k) of cell (ex, ey, ez) sits at (ex N + i, ey N + j, ez N + k) of an
+// (nx N) x (ny N) x (nz N) array per component; assemble_kernel then sums the bricks that meet
+// at each node and writes every row of the output once, in whole cache lines. (Device-scope
+// FP64 atomics on the shared nodes cost about a third of the apply on MI355X; storing the
+// cell-interior rows directly from here, interleaved with the other kernel's rows, was slower.)
 template <int N, int EB, typename R>
 __device__ __forceinline__ void backward_scatter(const KernelArgs<N, R>& a, R* sb, int e0,
                                                  const CellPos& c0, int le_me, int q_me,
@@ -718,16 +719,11 @@ __device__ __forceinline__ void backward_scatter(const KernelArgs<N, R>& a, R* s
       bool cons;
       const int64_t node = node_of(L, cp, i, j, k, cons);
       if (!cons) {
-        const bool inner = i > 0 && i < P && j > 0 && j < P && k > 0 && k < P;
         const int64_t EX = static_cast<int64_t>(L.nx) * N, EY = static_cast<int64_t>(L.ny) * N;
         const int64_t ES = EX * EY * (static_cast<int64_t>(L.nz) * N);
         const int64_t pos = (cp.ex * N + i) + EX * ((cp.ey * N + j) + EY * (static_cast<int64_t>(cp.ez) * N + k));
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const R v = sb[le_me * CB + (3 * c) * Q + q_me];
-          if (inner) a.out[c * L.n_nodes + node] = v;
-          else a.ework[c * ES + pos] = v;
-        }
+        for (int c = 0; c < 3; ++c) a.ework[c * ES + pos] = sb[le_me * CB + (3 * c) * Q + q_me];
       }
     }
   }
@@ -764,10 +760,9 @@ __device__ __forceinline__ int cells_at(int Ig, int ncell, int Nn, int* cc, int*
   return cnt;
 }
 
-// One thread per lattice node of a 64 x 4 tile of x-rows; nodes inside a cell were stored by the
-// element kernel. Every other node gets the sum of the bricks of the 2, 4 or 8 cells that share
-// it, in a fixed order (the apply is deterministic), or, on constrained rows, cons_src (du of the
-// apply: identity rows) or zero (residual).
+// One thread per lattice node of a 64 x 4 tile of x-rows. Every node gets the sum of the bricks
+// of the 1, 2, 4 or 8 cells that share it, in a fixed order (the apply is deterministic), or, on
+// constrained rows, cons_src (du of the apply: identity rows) or zero (residual).
 template <int N, typename R>
 __global__ void __launch_bounds__(256) assemble_kernel(Lattice L, const R* __restrict__ E,
                                                        const R* __restrict__ cons_src, R* __restrict__ out,
@@ -778,7 +773,6 @@ __global__ void __launch_bounds__(256) assemble_kernel(Lattice L, const R* __res
   const int I = bx * 64 + static_cast<int>(threadIdx.x);
   if (I >= L.Nx || row >= static_cast<int64_t>(L.Ny) * L.Nz) return;
   const int K = row / L.Ny, J = row - K * L.Ny;
-  if ((I % P) && (J % P) && (K % P)) return;
   const int64_t n = L.n_nodes;
   const int64_t node = I + static_cast<int64_t>(L.Nx) * row;
   if (cons_x(L, I) || cons_yz(L, J, K)) {
