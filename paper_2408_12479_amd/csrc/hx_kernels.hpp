@@ -782,21 +782,45 @@ __global__ void __launch_bounds__(256) assemble_kernel(Lattice L, const R* __res
   }
   int cx[2], lx[2], cy[2], ly[2], cz[2], lz[2];
   const int nxc = cells_at<P>(I, L.nx, L.Nx, cx, lx);
-  const int nyc = cells_at<P>(J, L.ny, L.Ny, cy, ly);
+  const int nyc = cells_at<P>(J, L.ny, L.Ny, cy, ly);  // J, K: uniform across an x-row of lanes
   const int nzc = cells_at<P>(K, L.nz, L.Nz, cz, lz);
   const int64_t EX = static_cast<int64_t>(L.nx) * N, EY = static_cast<int64_t>(L.ny) * N;
   const int64_t ES = EX * EY * (static_cast<int64_t>(L.nz) * N);
-  R s0 = R(0), s1 = R(0), s2 = R(0);
-  for (int a = 0; a < nzc; ++a)
-    for (int b = 0; b < nyc; ++b) {
-      const int64_t rowpos = EX * ((cy[b] * N + ly[b]) + EY * (static_cast<int64_t>(cz[a]) * N + lz[a]));
-      for (int d = 0; d < nxc; ++d) {
-        const R* e = E + rowpos + cx[d] * N + lx[d];
-        s0 += e[0];
-        s1 += e[ES];
-        s2 += e[2 * ES];
+  // positions of the one or two bricks along x in a brick row (the same position twice if one)
+  const int x0 = cx[0] * N + lx[0];
+  const int x1 = nxc > 1 ? cx[1] * N + lx[1] : x0;
+  // all loads are issued before the first sum: summing each value as it arrives would wait for
+  // up to eight memory round trips one after the other
+  R v[4][3][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int k = 2 * a + b;
+      if (a < nzc && b < nyc) {
+        const int64_t rowpos = EX * ((cy[b] * N + ly[b]) + EY * (static_cast<int64_t>(cz[a]) * N + lz[a]));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          v[k][c][0] = E[c * ES + rowpos + x0];
+          v[k][c][1] = E[c * ES + rowpos + x1];
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[k][c][0] = v[k][c][1] = R(0);
       }
     }
+  R s0 = R(0), s1 = R(0), s2 = R(0);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    s0 += v[k][0][0];
+    s1 += v[k][1][0];
+    s2 += v[k][2][0];
+    if (nxc > 1) {
+      s0 += v[k][0][1];
+      s1 += v[k][1][1];
+      s2 += v[k][2][1];
+    }
+  }
   out[node] = s0;
   out[n + node] = s1;
   out[2 * n + node] = s2;
