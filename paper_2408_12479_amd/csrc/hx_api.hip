@@ -678,6 +678,9 @@ hx_status hx_apply_tangent(hx_ctx ctx, const void* du, void* dst, hx_precision p
   h.in1 = sl.uk;
   h.out = dst;
   h.qdata = sl.qdata;
+  // stored data larger than the last-level cache is streamed (non-temporal loads); smaller data
+  // may stay cached between applies
+  h.stream_qdata = sl.qbytes > (size_t(128) << 20) ? 1 : 0;
   h.cscale = sl.cscale;
   h.act = sl.keep_act ? sl.act : nullptr;
   HostOp op{OpKind::Apply, ctx->base.mat.law, sl.mode, sl.store, fp32};

@@ -90,7 +90,16 @@ hipError_t launch(const HostArgs& h, hipStream_t s) {
   const KernelArgs<N, R> a = make_args<R>(h);
   const int nblk = (h.L.n_cells + EB - 1) / EB;
   if (nblk == 0) return hipSuccess;
-  element_kernel<N, EB, R, KIND, MODE, LAW, S><<<dim3(nblk), dim3(EB * N * N * N), 0, s>>>(a);
+  if constexpr (KIND == 0 && MODE != HX_STORE_NONE) {
+    // stored data larger than the last-level cache: non-temporal loads (a separate instantiation,
+    // since a run-time choice between the two loads is merged into one by the compiler)
+    if (h.stream_qdata)
+      element_kernel<N, EB, R, KIND, MODE, LAW, S, true><<<dim3(nblk), dim3(EB * N * N * N), 0, s>>>(a);
+    else
+      element_kernel<N, EB, R, KIND, MODE, LAW, S><<<dim3(nblk), dim3(EB * N * N * N), 0, s>>>(a);
+  } else {
+    element_kernel<N, EB, R, KIND, MODE, LAW, S><<<dim3(nblk), dim3(EB * N * N * N), 0, s>>>(a);
+  }
   if constexpr (KIND == 0 || KIND == 1) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

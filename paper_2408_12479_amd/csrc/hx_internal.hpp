@@ -102,6 +102,7 @@ struct HostArgs {
   void* out;
   void* ework;    // 3 * n_cells * (p+1)^3 FP64 words, reused as FP32 by FP32 applies
   const void* qdata;
+  int stream_qdata;   // nonzero: the apply loads the planes with the non-temporal hint (large data)
   void* qdata_w;
   const float* cscale;
   float* cscale_w;

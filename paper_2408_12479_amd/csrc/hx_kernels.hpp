@@ -36,6 +36,16 @@ __device__ __forceinline__ float load_val(const bf16_t* p) {
 }
 __device__ __forceinline__ float load_val(const _Float16* p) { return static_cast<float>(*p); }
 
+// Loads of stored q-point words in the apply when the whole set is larger than the caches: the
+// words are read once per apply, and the non-temporal hint keeps them from evicting the vectors
+// and the brick buffer, which are reused within the apply.
+__device__ __forceinline__ double load_stream(const double* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float load_stream(const float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ _Float16 load_stream(const _Float16* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ bf16_t load_stream(const bf16_t* p) {
+  return bf16_t{__builtin_nontemporal_load(&p->v)};
+}
+
 // stored word as held in a register before conversion
 __device__ __forceinline__ double as_val(double v) { return v; }
 __device__ __forceinline__ float as_val(float v) { return v; }
@@ -1057,7 +1067,7 @@ __device__ __forceinline__ void load_vertices(const KernelArgs<N, R>& a, R* sv, 
 // The apply and residual kernels are held to at most 128 VGPRs (4 waves per SIMD; forcing 8
 // waves spills and is slower); the update runs once per Newton step and may use the whole
 // register file.
-template <int N, int EB, typename R, int KIND, int MODE, int LAW, int S>
+template <int N, int EB, typename R, int KIND, int MODE, int LAW, int S, bool NT = false>
 __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
     element_kernel(KernelArgs<N, R> a) {
   constexpr int Q = N * N * N;
@@ -1087,8 +1097,13 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
   if constexpr (WA > 0) {
     if (valid) {
       const ST* qd = static_cast<const ST*>(a.qdata) + qblk;
+      if constexpr (NT) {
 #pragma unroll
-      for (int w = 0; w < WA; ++w) qv[w] = qd[w * EBQ + qi];
+        for (int w = 0; w < WA; ++w) qv[w] = load_stream(qd + w * EBQ + qi);
+      } else {
+#pragma unroll
+        for (int w = 0; w < WA; ++w) qv[w] = qd[w * EBQ + qi];
+      }
     }
   }
 
