@@ -8,6 +8,10 @@ import ctypes
 import os
 
 import numpy as np
+# torch is imported before libhx.so is loaded: torch ships its own HIP runtime, and libhx.so's
+# libamdhip64 dependency must resolve to that already-loaded runtime. Loaded the other way round,
+# the process holds two HIP runtimes and the library's device calls fail ("no HIP device").
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhx.so")

@@ -59,3 +59,17 @@ def test_fiber_structure_rejects_bad_input():
     import paper_2408_12479_amd as hx
     with pytest.raises(hx.HxError):
         hx.fiber_structure(3.62, -1.0, 0.3)
+
+
+def test_one_hip_runtime_per_process():
+    """Importing the binding in a fresh process maps a single HIP runtime (torch's): libhx.so must
+    not bring a second libamdhip64 next to the one torch loads."""
+    import subprocess
+    import sys
+    code = ("import paper_2408_12479_amd, torch\n"
+            "torch.cuda.is_available()\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "print(len({l.split()[-1] for l in maps if 'libamdhip64' in l}))\n")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
