@@ -104,10 +104,8 @@ hipError_t launch(const HostArgs& h, hipStream_t s) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // rows of the nodes on cell faces: sum of the cells' bricks; constrained rows du (apply) or 0
-    const int xb = (h.L.Nx + 63) / 64;
-    const int64_t rb = (static_cast<int64_t>(h.L.Ny) * h.L.Nz + 3) / 4;
-    assemble_kernel<N, R><<<dim3(static_cast<unsigned>(xb * rb)), dim3(64, 4), 0, s>>>(
-        h.L, a.ework, KIND == 0 ? a.in0 : nullptr, a.out, xb);
+    assemble_kernel<N, R><<<dim3(static_cast<unsigned>((h.L.n_nodes + 255) / 256)), dim3(256), 0, s>>>(
+        h.L, a.ework, KIND == 0 ? a.in0 : nullptr, a.out);
   }
   return hipGetLastError();
 }

@@ -770,21 +770,22 @@ __device__ __forceinline__ int cells_at(int Ig, int ncell, int Nn, int* cc, int*
   return cnt;
 }
 
-// One thread per lattice node of a 64 x 4 tile of x-rows. Every node gets the sum of the bricks
-// of the 1, 2, 4 or 8 cells that share it, in a fixed order (the apply is deterministic), or, on
+// One thread per lattice node, in node order (consecutive lanes walk the x-rows and continue on
+// the next row, so no lane idles at the end of a row). Every node gets the sum of the bricks of
+// the 1, 2, 4 or 8 cells that share it, in a fixed order (the apply is deterministic), or, on
 // constrained rows, cons_src (du of the apply: identity rows) or zero (residual).
 template <int N, typename R>
 __global__ void __launch_bounds__(256) assemble_kernel(Lattice L, const R* __restrict__ E,
-                                                       const R* __restrict__ cons_src, R* __restrict__ out,
-                                                       int xblocks) {
+                                                       const R* __restrict__ cons_src, R* __restrict__ out) {
   constexpr int P = N - 1;
-  const int bx = static_cast<int>(blockIdx.x) % xblocks;
-  const int row = (static_cast<int>(blockIdx.x) / xblocks) * 4 + static_cast<int>(threadIdx.y);
-  const int I = bx * 64 + static_cast<int>(threadIdx.x);
-  if (I >= L.Nx || row >= static_cast<int64_t>(L.Ny) * L.Nz) return;
-  const int K = row / L.Ny, J = row - K * L.Ny;
   const int64_t n = L.n_nodes;
-  const int64_t node = I + static_cast<int64_t>(L.Nx) * row;
+  // n_nodes < 2^31 (the setup bounds cells * (p+1)^3), so the index arithmetic is 32-bit
+  const uint32_t nd = blockIdx.x * 256u + threadIdx.x;
+  if (nd >= static_cast<uint64_t>(n)) return;
+  const int64_t node = nd;
+  const uint32_t row = nd / static_cast<uint32_t>(L.Nx);
+  const int I = static_cast<int>(nd - row * static_cast<uint32_t>(L.Nx));
+  const int K = static_cast<int>(row / static_cast<uint32_t>(L.Ny)), J = static_cast<int>(row) - K * L.Ny;
   if (cons_x(L, I) || cons_yz(L, J, K)) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) out[c * n + node] = cons_src ? cons_src[c * n + node] : R(0);
@@ -792,7 +793,7 @@ __global__ void __launch_bounds__(256) assemble_kernel(Lattice L, const R* __res
   }
   int cx[2], lx[2], cy[2], ly[2], cz[2], lz[2];
   const int nxc = cells_at<P>(I, L.nx, L.Nx, cx, lx);
-  const int nyc = cells_at<P>(J, L.ny, L.Ny, cy, ly);  // J, K: uniform across an x-row of lanes
+  const int nyc = cells_at<P>(J, L.ny, L.Ny, cy, ly);
   const int nzc = cells_at<P>(K, L.nz, L.Nz, cz, lz);
   const int64_t EX = static_cast<int64_t>(L.nx) * N, EY = static_cast<int64_t>(L.ny) * N;
   const int64_t ES = EX * EY * (static_cast<int64_t>(L.nz) * N);
