@@ -532,6 +532,27 @@ __device__ __forceinline__ void pencil_jobs(Fn&& fn) {
   }
 }
 
+// Cell and node of a thread in the gather and in the final store: the block's EB cells are
+// interleaved along x (thread t: i = t mod N, then the cell, then j and k), so that consecutive
+// lanes walk a whole x-row of the block (EB rows of N values side by side in the lattice and in
+// the brick buffer) and each load or store instruction covers longer contiguous runs than the
+// row of one cell.
+// Used for odd N only: with N even the per-cell LDS stride (9 N^3 words) is a multiple of the
+// bank count, the cells' rows fall on the same banks and the interleaved LDS writes conflict
+// (measured slower at Q3); with N odd they are spread over the banks (Q4: +5 %).
+template <int N, int EB>
+__device__ __forceinline__ void interleaved_slot(int t, int& le, int& q) {
+  if constexpr (EB > 1 && N % 2 == 1) {
+    const int i = t % N;
+    const int r = t / N;
+    le = r % EB;
+    q = i + N * (r / EB);
+  } else {
+    le = t / (N * N * N);
+    q = t - le * N * N * N;
+  }
+}
+
 // LDS per cell: 9 fields of N^3 values. Forward: values (then d/dx in place) in c, d/dz in
 // 3 + c, d/dy in 6 + c; backward: the nine test coefficients.
 constexpr int kBuffers = 9;
@@ -545,24 +566,27 @@ __device__ __forceinline__ void forward_vector(const KernelArgs<N, R>& a, R* sb,
   constexpr int Q = N * N * N;
   constexpr int CB = kBuffers * Q;  // per-cell stride in LDS
   const Lattice& L = a.L;
-  // F0: gather, one node per thread: the lanes of a wavefront walk contiguous x-rows of the
-  // lattice, so each load instruction touches few cache lines (a pencil-per-lane gather touches
-  // one line per lane and was the most expensive part of the kernel)
+  // F0: gather, one node per thread, the block's cells interleaved along x so that the lanes of
+  // a wavefront walk contiguous x-rows of the lattice and each load instruction touches few cache
+  // lines (a pencil-per-lane gather touches one line per lane and was the most expensive part of
+  // the kernel)
   {
-    R* cb = sb + le_me * CB;
-    if (e0 + le_me < L.n_cells) {
-      const int i = q_me % N, j = (q_me / N) % N, k = q_me / (N * N);
-      const CellPos cp = cell_advance(L, c0, le_me);
+    int lg, qg;
+    interleaved_slot<N, EB>(le_me * Q + q_me, lg, qg);
+    R* cb = sb + lg * CB;
+    if (e0 + lg < L.n_cells) {
+      const int i = qg % N, j = (qg / N) % N, k = qg / (N * N);
+      const CellPos cp = cell_advance(L, c0, lg);
       bool cons;
       const int64_t node = node_of(L, cp, i, j, k, cons);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const R v = V[c * L.n_nodes + node];
-        cb[c * Q + q_me] = (MASK && cons) ? R(0) : v;
+        cb[c * Q + qg] = (MASK && cons) ? R(0) : v;
       }
     } else {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) cb[c * Q + q_me] = R(0);
+      for (int c = 0; c < 3; ++c) cb[c * Q + qg] = R(0);
     }
   }
   __syncthreads();
@@ -720,20 +744,22 @@ __device__ __forceinline__ void backward_scatter(const KernelArgs<N, R>& a, R* s
     for (int m = 0; m < N; ++m) buf[pidx<N, 0>(j, k, m)] = out[m];
   });
   __syncthreads();
-  constexpr int P = N - 1;
   {
-    const int e = e0 + le_me;
+    // the store runs with the block's cells interleaved along x, like the gather
+    int lg, qg;
+    interleaved_slot<N, EB>(le_me * Q + q_me, lg, qg);
+    const int e = e0 + lg;
     if (e < L.n_cells) {
-      const int i = q_me % N, j = (q_me / N) % N, k = q_me / (N * N);
-      const CellPos cp = cell_advance(L, c0, le_me);
+      const int i = qg % N, j = (qg / N) % N, k = qg / (N * N);
+      const CellPos cp = cell_advance(L, c0, lg);
       bool cons;
-      const int64_t node = node_of(L, cp, i, j, k, cons);
+      (void)node_of(L, cp, i, j, k, cons);
       if (!cons) {
         const int64_t EX = static_cast<int64_t>(L.nx) * N, EY = static_cast<int64_t>(L.ny) * N;
         const int64_t ES = EX * EY * (static_cast<int64_t>(L.nz) * N);
         const int64_t pos = (cp.ex * N + i) + EX * ((cp.ey * N + j) + EY * (static_cast<int64_t>(cp.ez) * N + k));
 #pragma unroll
-        for (int c = 0; c < 3; ++c) a.ework[c * ES + pos] = sb[le_me * CB + (3 * c) * Q + q_me];
+        for (int c = 0; c < 3; ++c) a.ework[c * ES + pos] = sb[lg * CB + (3 * c) * Q + qg];
       }
     }
   }
