@@ -1089,6 +1089,17 @@ __device__ __forceinline__ void load_vertices(const KernelArgs<N, R>& a, R* sv, 
   }
 }
 
+// Block of cells of workgroup b in a grid of g: the hardware deals workgroups to the 8 XCDs in
+// turn (b mod 8), so the blocks are renumbered to give each XCD a contiguous range of them (a
+// slab of the lattice): neighbouring blocks, which gather the nodes on their common faces, then
+// mostly run on one XCD and share its L2. A bijection of [0, g) for any g.
+__device__ __forceinline__ int xcd_block(int b, int g) {
+  constexpr int kXcd = 8;
+  const int per = g / kXcd, rem = g - per * kXcd;
+  const int x = b % kXcd;
+  return x * per + (x < rem ? x : rem) + b / kXcd;
+}
+
 // Kernel: ops = residual, apply (four storage modes) and update (four storage modes).
 //   KIND 0 apply, 1 residual, 2 update; MODE = hx_storage; S = StoreType; LAW
 // The apply and residual kernels are held to at most 128 VGPRs (4 waves per SIMD; forcing 8
@@ -1104,7 +1115,8 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
   __shared__ float sred[EB];
   const int le = threadIdx.x / Q;
   const int q = threadIdx.x - le * Q;
-  const int e0 = blockIdx.x * EB;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int e0 = blk * EB;
   const int e = e0 + le;
   const bool valid = e < a.L.n_cells;
   const CellPos c0 = cell_pos(a.L, e0);
@@ -1114,7 +1126,7 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
                         ? 45
                         : (MODE == HX_STORE_FINV_J ? 10 : (MODE == HX_STORE_SPATIAL ? kSpatialWords<LAW> : 0));
   constexpr int EBQ = EB * Q;
-  const int64_t qblk = static_cast<int64_t>(blockIdx.x) * W * EBQ;
+  const int64_t qblk = static_cast<int64_t>(blk) * W * EBQ;
   const int qi = threadIdx.x;
 
   // stored q-point data of this thread (apply), requested before the sum factorisation so that
@@ -1199,7 +1211,7 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
     const R wdet = valid ? qpoint_geometry(a, sv + le * 24, q, K) : R(0);
     QState<R> st;
     if constexpr (kIsFiber<LAW>) {
-      if (a.act && valid) st.forced = a.act[static_cast<int64_t>(blockIdx.x) * EBQ + qi];
+      if (a.act && valid) st.forced = a.act[static_cast<int64_t>(blk) * EBQ + qi];
     }
     if constexpr (MODE == HX_STORE_NONE) {
       R H[9], E[9];
@@ -1240,7 +1252,7 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
     int bad = 0;
     if (valid && !ok) bad |= kFlagInverted;
     if constexpr (kIsFiber<LAW>) {
-      if (a.act_w && valid) a.act_w[static_cast<int64_t>(blockIdx.x) * EBQ + qi] = static_cast<uint8_t>(st.bits);
+      if (a.act_w && valid) a.act_w[static_cast<int64_t>(blk) * EBQ + qi] = static_cast<uint8_t>(st.bits);
     }
     ST* qw = static_cast<ST*>(a.qdata_w) + qblk;
     if constexpr (MODE == HX_STORE_FINV_J) {
