@@ -206,8 +206,7 @@ struct QState {
 };
 
 template <int LAW, typename R>
-__device__ __forceinline__ void fiber_scalars(const MaterialK<R>& m, const R* Hf, const R* M,
-                                              R Ei, R ImOne, int f, QState<R>& s) {
+__device__ __forceinline__ void fiber_scalars(const MaterialK<R>& m, R Ei, R ImOne, int f, QState<R>& s) {
   // c3 = 2 k1 exp(k2 E_i^2) if I*_i > 1 (strict), else 0  (fibre model, c3 definition). An FP32
   // apply takes the switch as the FP64 update decided it, so that rounding cannot flip it.
   const bool active = s.forced >= 0 ? ((s.forced >> f) & 1) != 0 : ImOne > R(0);
@@ -266,7 +265,7 @@ __device__ __forceinline__ bool state_from_H(const R* H, const MaterialK<R>& m,
 #pragma unroll
           for (int j = 0; j < 3; ++j) mem += M[i] * E[3 * i + j] * M[j];
         // E_i = 2 H_i : E,  I*_i - 1 = 2 (M (x) M) : E
-        fiber_scalars<LAW>(m, Hf, M, R(2) * Ei, R(2) * mem, f, s);
+        fiber_scalars<LAW>(m, R(2) * Ei, R(2) * mem, f, s);
       }
     }
   }
@@ -312,7 +311,7 @@ __device__ __forceinline__ void state_from_finv(const R* Fi, R Jm, const Materia
         for (int i = 0; i < 3; ++i)
 #pragma unroll
           for (int j = 0; j < 3; ++j) mcm += M[i] * C[3 * i + j] * M[j];
-        fiber_scalars<LAW>(m, Hf, M, Ei, mcm - R(1), f, s);
+        fiber_scalars<LAW>(m, Ei, mcm - R(1), f, s);
       }
     }
   }
@@ -878,7 +877,7 @@ __device__ __forceinline__ R pick(const R* arr, int idx) {
 }
 
 template <int N, typename R>
-__device__ __forceinline__ R qpoint_geometry(const KernelArgs<N, R>& a, const R* X, int q, R* K) {
+__device__ __forceinline__ R qpoint_geometry(const R* X, int q, R* K) {
   const int qx = q % N, qy = (q / N) % N, qz = q / (N * N);
   const R det = trilinear_geometry(X, pick<N>(Tab1D<N, R>::x, qx), pick<N>(Tab1D<N, R>::x, qy), pick<N>(Tab1D<N, R>::x, qz), K);
   return det * (pick<N>(Tab1D<N, R>::w, qx) * pick<N>(Tab1D<N, R>::w, qy) * pick<N>(Tab1D<N, R>::w, qz));
@@ -1208,7 +1207,7 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
     spatial_action<LAW>(d, m, g0, t);
   } else if constexpr (KIND == 0) {
     R K[9];
-    const R wdet = valid ? qpoint_geometry(a, sv + le * 24, q, K) : R(0);
+    const R wdet = valid ? qpoint_geometry<N>(sv + le * 24, q, K) : R(0);
     QState<R> st;
     if constexpr (kIsFiber<LAW>) {
       if (a.act && valid) st.forced = a.act[static_cast<int64_t>(blk) * EBQ + qi];
@@ -1236,7 +1235,7 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
     to_reference(Pd, K, wdet, t);
   } else if constexpr (KIND == 1) {
     R K[9], H[9], E[9], P[9];
-    const R wdet = valid ? qpoint_geometry(a, sv + le * 24, q, K) : R(0);
+    const R wdet = valid ? qpoint_geometry<N>(sv + le * 24, q, K) : R(0);
     to_physical(g0, K, H);
     QState<R> st;
     state_from_H<LAW>(H, m, fb, st, E);
@@ -1245,7 +1244,7 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
   } else {
     // linearisation update (always FP64 arithmetic)
     R K[9], H[9], E[9];
-    const R wdet = valid ? qpoint_geometry(a, sv + le * 24, q, K) : R(0);
+    const R wdet = valid ? qpoint_geometry<N>(sv + le * 24, q, K) : R(0);
     to_physical(g0, K, H);
     QState<R> st;
     const bool ok = state_from_H<LAW>(H, m, fb, st, E);
