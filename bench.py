@@ -231,6 +231,9 @@ def main():
     else:
         roof = {"bound": "alu", "achieved": tfl, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": tfl / FP64_PEAK_TFLOPS, "traffic": measured_traffic(head["p"], head["mode"])}
+    # the timed unit is one hx_apply_tangent: the element kernel and the node kernel that sums the
+    # element vectors, back to back on the same stream
+    roof["launch"] = "hx_apply_tangent = element_kernel + assemble_kernel"
 
     out = {
         "metric": "GDoF/s of tangent apply (Q2-Q6), FP64",
