@@ -488,12 +488,28 @@ __device__ __forceinline__ int64_t node_of(const Lattice& L, const CellPos& c, i
 // ------------------------------------------------------------------------------------------
 // Pencil machinery
 // ------------------------------------------------------------------------------------------
-// index of point m on pencil (a, b) along direction DIR in an N^3 block (x fastest)
+// LDS layout of one field of an N^3 block: x fastest, rows of N values, planes of PS values; a
+// field takes FS values. Q3 pads its planes (16 -> 19 values) and fields (64 -> 73): unpadded,
+// the pencils that the lanes of a wavefront read fall on the same banks (4-way conflicts).
+template <int N>
+struct Lds {
+  static constexpr int PS = N == 4 ? 19 : N * N;
+  static constexpr int FS = N == 4 ? 73 : N * N * N;
+};
+
+// LDS offset of local point q = i + N j + N^2 k within its field
+template <int N>
+__device__ __forceinline__ int lds_q(int q) {
+  return q + (Lds<N>::PS - N * N) * (q / (N * N));
+}
+
+// index of point m on pencil (a, b) along direction DIR in a field (x fastest)
 template <int N, int DIR>
 __device__ __forceinline__ int pidx(int a, int b, int m) {
-  if constexpr (DIR == 0) return m + N * a + N * N * b;
-  else if constexpr (DIR == 1) return a + N * m + N * N * b;
-  else return a + N * b + N * N * m;
+  constexpr int PS = Lds<N>::PS;
+  if constexpr (DIR == 0) return m + N * a + PS * b;
+  else if constexpr (DIR == 1) return a + N * m + PS * b;
+  else return a + N * b + PS * m;
 }
 
 // out = M in (TR: M^T in), M row-major N x N with wave-uniform coefficients
@@ -643,7 +659,7 @@ __device__ __forceinline__ void forward_vector(const KernelArgs<N, R>& a, R* sb,
                                                int e0, const CellPos& c0, int le_me, int q_me,
                                                R* g) {
   constexpr int Q = N * N * N;
-  constexpr int CB = kBuffers * Q;  // per-cell stride in LDS
+  constexpr int CB = kBuffers * Lds<N>::FS;  // per-cell stride in LDS
   const Lattice& L = a.L;
   // F0: gather, one node per thread, the block's cells interleaved along x so that the lanes of
   // a wavefront walk contiguous x-rows of the lattice and each load instruction touches few cache
@@ -661,18 +677,18 @@ __device__ __forceinline__ void forward_vector(const KernelArgs<N, R>& a, R* sb,
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const R v = V[c * L.n_nodes + node];
-        cb[c * Q + qg] = (MASK && cons) ? R(0) : v;
+        cb[c * Lds<N>::FS + lds_q<N>(qg)] = (MASK && cons) ? R(0) : v;
       }
     } else {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) cb[c * Q + qg] = R(0);
+      for (int c = 0; c < 3; ++c) cb[c * Lds<N>::FS + lds_q<N>(qg)] = R(0);
     }
   }
   __syncthreads();
   // F1: interpolate along x
   pencil_jobs<N, EB, 3>([&](int le, int c, int j, int k) __attribute__((always_inline)) {
     R in[N], out[N];
-    R* buf = sb + le * CB + c * Q;
+    R* buf = sb + le * CB + c * Lds<N>::FS;
 #pragma unroll
     for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 0>(j, k, m)];
     contract1d<N, false, 1>(Tab1D<N, R>::B, in, out);
@@ -683,7 +699,7 @@ __device__ __forceinline__ void forward_vector(const KernelArgs<N, R>& a, R* sb,
   // F2: interpolate along y
   pencil_jobs<N, EB, 3>([&](int le, int c, int i, int k) __attribute__((always_inline)) {
     R in[N], out[N];
-    R* buf = sb + le * CB + c * Q;
+    R* buf = sb + le * CB + c * Lds<N>::FS;
 #pragma unroll
     for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 1>(i, k, m)];
     contract1d<N, false, 1>(Tab1D<N, R>::B, in, out);
@@ -694,8 +710,8 @@ __device__ __forceinline__ void forward_vector(const KernelArgs<N, R>& a, R* sb,
   // F3: interpolate along z (values at Gauss points, in place) and differentiate along z
   pencil_jobs<N, EB, 3>([&](int le, int c, int i, int j) __attribute__((always_inline)) {
     R in[N], v[N], d[N];
-    R* buf = sb + le * CB + c * Q;
-    R* bz = sb + le * CB + (3 + c) * Q;
+    R* buf = sb + le * CB + c * Lds<N>::FS;
+    R* bz = sb + le * CB + (3 + c) * Lds<N>::FS;
 #pragma unroll
     for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 2>(i, j, m)];
     contract1d<N, false, 1>(Tab1D<N, R>::B, in, v);
@@ -710,8 +726,8 @@ __device__ __forceinline__ void forward_vector(const KernelArgs<N, R>& a, R* sb,
   // F4: differentiate along y (into 6 + c)
   pencil_jobs<N, EB, 3>([&](int le, int c, int a1, int b1) __attribute__((always_inline)) {
     R in[N], d[N];
-    const R* buf = sb + le * CB + c * Q;
-    R* by = sb + le * CB + (6 + c) * Q;
+    const R* buf = sb + le * CB + c * Lds<N>::FS;
+    R* by = sb + le * CB + (6 + c) * Lds<N>::FS;
 #pragma unroll
     for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 1>(a1, b1, m)];
     contract1d<N, false, -1>(Tab1D<N, R>::D, in, d);
@@ -722,7 +738,7 @@ __device__ __forceinline__ void forward_vector(const KernelArgs<N, R>& a, R* sb,
   // F5: differentiate along x, in place
   pencil_jobs<N, EB, 3>([&](int le, int c, int a1, int b1) __attribute__((always_inline)) {
     R in[N], d[N];
-    R* buf = sb + le * CB + c * Q;
+    R* buf = sb + le * CB + c * Lds<N>::FS;
 #pragma unroll
     for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 0>(a1, b1, m)];
     contract1d<N, false, -1>(Tab1D<N, R>::D, in, d);
@@ -734,9 +750,9 @@ __device__ __forceinline__ void forward_vector(const KernelArgs<N, R>& a, R* sb,
   const R* cb = sb + le_me * CB;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    g[3 * c + 0] = cb[c * Q + q_me];
-    g[3 * c + 1] = cb[(6 + c) * Q + q_me];
-    g[3 * c + 2] = cb[(3 + c) * Q + q_me];
+    g[3 * c + 0] = cb[c * Lds<N>::FS + lds_q<N>(q_me)];
+    g[3 * c + 1] = cb[(6 + c) * Lds<N>::FS + lds_q<N>(q_me)];
+    g[3 * c + 2] = cb[(3 + c) * Lds<N>::FS + lds_q<N>(q_me)];
   }
 }
 
@@ -755,13 +771,13 @@ __device__ __forceinline__ void backward_scatter(const KernelArgs<N, R>& a, R* s
                                                  const CellPos& c0, int le_me, int q_me,
                                                  const R* t) {
   constexpr int Q = N * N * N;
-  constexpr int CB = kBuffers * Q;
+  constexpr int CB = kBuffers * Lds<N>::FS;
   const Lattice& L = a.L;
   __syncthreads();  // buffers may still be read by the forward pass
   {
     R* cb = sb + le_me * CB;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) cb[i * Q + q_me] = t[i];
+    for (int i = 0; i < 9; ++i) cb[i * Lds<N>::FS + lds_q<N>(q_me)] = t[i];
   }
   __syncthreads();
   // B2: D^T along x on t[c][0], D^T along y on t[c][1]
@@ -769,14 +785,14 @@ __device__ __forceinline__ void backward_scatter(const KernelArgs<N, R>& a, R* s
     const int c = set >> 1;
     R in[N], out[N];
     if ((set & 1) == 0) {
-      R* buf = sb + le * CB + (3 * c) * Q;
+      R* buf = sb + le * CB + (3 * c) * Lds<N>::FS;
 #pragma unroll
       for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 0>(a1, b1, m)];
       contract1d<N, true, -1>(Tab1D<N, R>::D, in, out);
 #pragma unroll
       for (int m = 0; m < N; ++m) buf[pidx<N, 0>(a1, b1, m)] = out[m];
     } else {
-      R* buf = sb + le * CB + (3 * c + 1) * Q;
+      R* buf = sb + le * CB + (3 * c + 1) * Lds<N>::FS;
 #pragma unroll
       for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 1>(a1, b1, m)];
       contract1d<N, true, -1>(Tab1D<N, R>::D, in, out);
@@ -788,9 +804,9 @@ __device__ __forceinline__ void backward_scatter(const KernelArgs<N, R>& a, R* s
   // B3: along z: s = tx' + ty' + D^T tz, then B^T
   pencil_jobs<N, EB, 3>([&](int le, int c, int i, int j) __attribute__((always_inline)) {
     R tz[N], s[N], out[N];
-    R* bx = sb + le * CB + (3 * c) * Q;
-    const R* by = sb + le * CB + (3 * c + 1) * Q;
-    const R* bzp = sb + le * CB + (3 * c + 2) * Q;
+    R* bx = sb + le * CB + (3 * c) * Lds<N>::FS;
+    const R* by = sb + le * CB + (3 * c + 1) * Lds<N>::FS;
+    const R* bzp = sb + le * CB + (3 * c + 2) * Lds<N>::FS;
 #pragma unroll
     for (int m = 0; m < N; ++m) tz[m] = bzp[pidx<N, 2>(i, j, m)];
     contract1d<N, true, -1>(Tab1D<N, R>::D, tz, s);
@@ -804,7 +820,7 @@ __device__ __forceinline__ void backward_scatter(const KernelArgs<N, R>& a, R* s
   // B4: B^T along y
   pencil_jobs<N, EB, 3>([&](int le, int c, int i, int k) __attribute__((always_inline)) {
     R in[N], out[N];
-    R* buf = sb + le * CB + (3 * c) * Q;
+    R* buf = sb + le * CB + (3 * c) * Lds<N>::FS;
 #pragma unroll
     for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 1>(i, k, m)];
     contract1d<N, true, 1>(Tab1D<N, R>::B, in, out);
@@ -815,7 +831,7 @@ __device__ __forceinline__ void backward_scatter(const KernelArgs<N, R>& a, R* s
   // B5: B^T along x in place, then one node per thread scatters (contiguous rows per wave)
   pencil_jobs<N, EB, 3>([&](int le, int c, int j, int k) __attribute__((always_inline)) {
     R in[N], out[N];
-    R* buf = sb + le * CB + (3 * c) * Q;
+    R* buf = sb + le * CB + (3 * c) * Lds<N>::FS;
 #pragma unroll
     for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 0>(j, k, m)];
     contract1d<N, true, 1>(Tab1D<N, R>::B, in, out);
@@ -838,7 +854,7 @@ __device__ __forceinline__ void backward_scatter(const KernelArgs<N, R>& a, R* s
         const int64_t ES = EX * EY * (static_cast<int64_t>(L.nz) * N);
         const int64_t pos = (cp.ex * N + i) + EX * ((cp.ey * N + j) + EY * (static_cast<int64_t>(cp.ez) * N + k));
 #pragma unroll
-        for (int c = 0; c < 3; ++c) a.ework[c * ES + pos] = sb[lg * CB + (3 * c) * Q + qg];
+        for (int c = 0; c < 3; ++c) a.ework[c * ES + pos] = sb[lg * CB + (3 * c) * Lds<N>::FS + lds_q<N>(qg)];
       }
     }
   }
@@ -1189,7 +1205,7 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
     element_kernel(KernelArgs<N, R> a) {
   constexpr int Q = N * N * N;
   using ST = typename StoreOf<S>::T;
-  __shared__ R sb[EB * kBuffers * Q];
+  __shared__ R sb[EB * kBuffers * Lds<N>::FS];
   __shared__ R sv[EB * 24];
   __shared__ float sred[EB];
   const int le = threadIdx.x / Q;
@@ -1450,15 +1466,15 @@ __host__ __device__ constexpr int packed_index(int a, int b) { return a * 9 - a 
 template <int N, int EB, int AL, int BE, typename R>
 __device__ __forceinline__ void diag_pair(R* sb, const R* Dv, int le_me, int q_me) {
   constexpr int Q = N * N * N;
-  constexpr int CB = 6 * Q;
+  constexpr int CB = 6 * Lds<N>::FS;
   constexpr R fac = AL == BE ? R(1) : R(2);
   R* cb = sb + le_me * CB;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) cb[c * Q + q_me] = fac * Dv[packed_index(3 * c + AL, 3 * c + BE)];
+  for (int c = 0; c < 3; ++c) cb[c * Lds<N>::FS + lds_q<N>(q_me)] = fac * Dv[packed_index(3 * c + AL, 3 * c + BE)];
   __syncthreads();
   pencil_jobs<N, EB, 3>([&](int le, int c, int i, int j) __attribute__((always_inline)) {
     R in[N], out[N];
-    R* buf = sb + le * CB + c * Q;
+    R* buf = sb + le * CB + c * Lds<N>::FS;
 #pragma unroll
     for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 2>(i, j, m)];
     diag_apply1d<N, AL, BE, 2>(in, out);
@@ -1468,7 +1484,7 @@ __device__ __forceinline__ void diag_pair(R* sb, const R* Dv, int le_me, int q_m
   __syncthreads();
   pencil_jobs<N, EB, 3>([&](int le, int c, int i, int k) __attribute__((always_inline)) {
     R in[N], out[N];
-    R* buf = sb + le * CB + c * Q;
+    R* buf = sb + le * CB + c * Lds<N>::FS;
 #pragma unroll
     for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 1>(i, k, m)];
     diag_apply1d<N, AL, BE, 1>(in, out);
@@ -1478,8 +1494,8 @@ __device__ __forceinline__ void diag_pair(R* sb, const R* Dv, int le_me, int q_m
   __syncthreads();
   pencil_jobs<N, EB, 3>([&](int le, int c, int j, int k) __attribute__((always_inline)) {
     R in[N], out[N];
-    R* buf = sb + le * CB + c * Q;
-    R* acc = sb + le * CB + (3 + c) * Q;
+    R* buf = sb + le * CB + c * Lds<N>::FS;
+    R* acc = sb + le * CB + (3 + c) * Lds<N>::FS;
 #pragma unroll
     for (int m = 0; m < N; ++m) in[m] = buf[pidx<N, 0>(j, k, m)];
     diag_apply1d<N, AL, BE, 0>(in, out);
@@ -1494,7 +1510,7 @@ __global__ void __launch_bounds__(EB * N * N * N) diag_kernel(KernelArgs<N, R> a
   constexpr int Q = N * N * N;
   constexpr int EBQ = EB * Q;
   using ST = typename StoreOf<S>::T;
-  __shared__ R sb[EB * 6 * Q];
+  __shared__ R sb[EB * 6 * Lds<N>::FS];
   const int le = threadIdx.x / Q;
   const int q = threadIdx.x - le * Q;
   const int e0 = blockIdx.x * EB;
@@ -1509,9 +1525,9 @@ __global__ void __launch_bounds__(EB * N * N * N) diag_kernel(KernelArgs<N, R> a
   }
 #pragma unroll
   for (int w = 0; w < 45; ++w) Dv[w] = valid ? static_cast<R>(load_val(qd + w * EBQ + threadIdx.x)) * inv : R(0);
-  R* cb = sb + le * 6 * Q;
+  R* cb = sb + le * 6 * Lds<N>::FS;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) cb[(3 + c) * Q + q] = R(0);
+  for (int c = 0; c < 3; ++c) cb[(3 + c) * Lds<N>::FS + lds_q<N>(q)] = R(0);
   diag_pair<N, EB, 0, 0>(sb, Dv, le, q);
   diag_pair<N, EB, 1, 1>(sb, Dv, le, q);
   diag_pair<N, EB, 2, 2>(sb, Dv, le, q);
@@ -1529,7 +1545,7 @@ __global__ void __launch_bounds__(EB * N * N * N) diag_kernel(KernelArgs<N, R> a
   const bool inner = i > 0 && i < P && j > 0 && j < P && k > 0 && k < P;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const R v = cb[(3 + c) * Q + q];
+    const R v = cb[(3 + c) * Lds<N>::FS + lds_q<N>(q)];
     R* dst = a.out + c * L.n_nodes + node;
     if (inner)
       *dst = v;
