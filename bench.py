@@ -405,6 +405,15 @@ def mg_study(hx, workloads, torch, dev, timer, cells=(16, 8, 200), degrees=(6, 3
         ms = timer.time(lambda: mg.vcycle(r32, z), reps)
         key = ("graph" if use_graph else "eager") + ("" if prec == "fp32" else "_" + prec)
         out[f"vcycle_ms_{key}"] = ms
+        if use_graph and prec == "fp32":
+            # the finest level's FP32 apply on its own: the V-cycle's dominant cost, against the
+            # HBM roof with its algorithmic bytes (stored data + direction read + output write)
+            x32 = torch.randn(n, device=dev, dtype=torch.float32)
+            y32 = torch.empty_like(x32)
+            t_fine = timer.time(lambda: ops[0].apply_tangent(x32, y32, precision="fp32"), reps)
+            fine_bytes = ops[0].linearization_bytes("fp32") + 2 * 4 * n
+            out["finest_apply_fp32"] = {"mode": mg.level_mode(0), "ms": t_fine, "bytes": fine_bytes,
+                                        "hbm_frac": fine_bytes / (t_fine * 1e-3) / 1e9 / HBM_PEAK_GBS}
         if use_graph:
             sfx = "" if prec == "fp32" else "_" + prec
             out["update_s" + sfx] = t_upd
