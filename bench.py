@@ -94,8 +94,10 @@ def cube_operator(hx, workloads, p, cells):
     return op, V
 
 
-def cpu_baseline(p, cells, budget_s=15.0):
-    """The FP64 oracle's element-by-element tangent apply on a bounded block of cells."""
+def cpu_baseline(p, cells, budget_s=15.0, gpu_dst=None):
+    """The FP64 oracle's element-by-element tangent apply on a bounded block of cells. With the
+    headline apply's output (gpu_dst, host [3 * n_nodes]), also its relative error against the
+    oracle on the rows the timed cells complete (whole z-layers of cells, constrained rows out)."""
     try:
         from threadpoolctl import threadpool_limits
     except Exception:  # pragma: no cover
@@ -109,19 +111,32 @@ def cpu_baseline(p, cells, budget_s=15.0):
     ctx = threadpool_limits(1) if threadpool_limits else None
     done, t_total, block = 0, 0.0, 64
     start = 0
+    acc = np.zeros((3, m.n_nodes))
     while t_total < budget_s and start < m.n_cells:
         cells_blk = np.arange(start, min(start + block, m.n_cells))
         t0 = time.perf_counter()
-        pb.apply_tangent(u, du, cells=cells_blk)
+        y = pb.apply_tangent(u, du, cells=cells_blk)
         t_total += time.perf_counter() - t0
+        acc += y
         done += len(cells_blk)
         start += block
     if ctx is not None:
         ctx.__exit__(None, None, None)
     dofs_per_cell = 3 * m.n_nodes / m.n_cells
-    return {"value": done * dofs_per_cell / t_total / 1e9, "unit": "GDoF/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} of {m.n_cells} cells of the {cells}^3 Q{p} cube (cNH), "
-                      f"{t_total:.1f} s single-threaded; DoF/s scaled by 3*n_nodes/n_cells"}
+    out = {"value": done * dofs_per_cell / t_total / 1e9, "unit": "GDoF/s", "cores": 1, "kind": "oracle",
+           "sample": f"{done} of {m.n_cells} cells of the {cells}^3 Q{p} cube (cNH), "
+                     f"{t_total:.1f} s single-threaded; DoF/s scaled by 3*n_nodes/n_cells"}
+    layers = done // (cells * cells)
+    if gpu_dst is not None and layers > 0:
+        # nodes below the top plane of the timed whole layers get every cell contribution
+        Nx, Ny, _ = m.ndims
+        sel = np.arange(Nx * Ny * layers * p)
+        sel = sel[~m.constrained[sel]]
+        g = np.asarray(gpu_dst).reshape(3, m.n_nodes)[:, sel]
+        ref = acc[:, sel]
+        out["rel_err_vs_oracle"] = float(np.linalg.norm(g - ref) / np.linalg.norm(ref))
+        out["rows_compared"] = int(3 * len(sel))
+    return out
 
 
 def measured_traffic(p, mode):
@@ -205,7 +220,8 @@ def main():
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / args.steps
             b, f = algorithmic(p, mode, op.num_cells, op.num_dofs)
-            head = dict(p=p, mode=mode, ms=ms, dofs=op.num_dofs, cells=op.num_cells, bytes=b, flops=f)
+            head = dict(p=p, mode=mode, ms=ms, dofs=op.num_dofs, cells=op.num_cells, bytes=b, flops=f,
+                        dst=dst.cpu().numpy())
         op.close()
         del ud, dud, dst, r
         torch.cuda.empty_cache()
@@ -254,7 +270,7 @@ def main():
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(head["p"], args.cells)
+        out["cpu_baseline"] = cpu_baseline(head["p"], args.cells, gpu_dst=head["dst"])
     out["sweep"] = sweep
     out["extra"] = extra
     print(json.dumps(out), flush=True)
