@@ -1,5 +1,7 @@
 // Device code: sum-factorised element kernels for the residual, the linearisation update and the
-// linearised operator of finite-strain hyperelasticity (material configuration).
+// linearised operator of finite-strain hyperelasticity (material configuration, and the spatial
+// configuration as a storage mode of the linearised operator), and the node kernel that sums the
+// element vectors.
 //
 // Thread layout. A workgroup processes EB cells; it has EB * (p+1)^3 threads, one per Gauss
 // point of each cell ("q-threads"). The tensor-product contractions run as pencil jobs: a job
@@ -11,7 +13,11 @@
 // Interpolation (Section 6: sum factorisation): values at Gauss points v = (B x B x B) u, then
 // reference derivatives g_d = D_d v with the collocation derivative D on the Gauss points. The
 // transposed sequence integrates the test-function gradients: s = sum_d D_d^T t_d, out =
-// (B^T x B^T x B^T) s. Cost per field: 6 sweeps of n^4 fused multiply-adds.
+// (B^T x B^T x B^T) s. Cost per field: 6 sweeps of n^4 fused multiply-adds (fewer in the even-odd
+// form used from n = 5 on).
+//
+// Assembly: each cell writes its element vector into its own brick of a per-context buffer (no
+// atomics); assemble_kernel then sums, in a fixed order, the bricks meeting at every node.
 #pragma once
 
 #include <hip/hip_fp16.h>
