@@ -88,6 +88,22 @@ class Timer:
         return e0.elapsed_time(e1) / reps
 
 
+def hbm_probe(hx, torch, dev, timer, n=192 << 20, reps=20):
+    """Sustained HBM rate of the library's STREAM triad (a = b + s c) on three FP64 arrays of n
+    words (1.6 GB each at the default n, 24 n bytes per call), well beyond the last-level cache."""
+    a = torch.empty(n, dtype=torch.float64, device=dev)
+    b = torch.ones(n, dtype=torch.float64, device=dev)
+    c = torch.full((n,), 0.5, dtype=torch.float64, device=dev)
+    for _ in range(3):
+        hx.stream_triad(a, b, c, 3.0)
+    ms = timer.time(lambda: hx.stream_triad(a, b, c, 3.0), reps)
+    ok = bool(torch.all(a == 2.5).item())
+    del a, b, c
+    torch.cuda.empty_cache()
+    return {"kernel": "STREAM triad a = b + s c, FP64", "bytes_per_call": 24 * n, "ms": ms,
+            "GBps": 24 * n / (ms * 1e-3) / 1e9, "result_ok": ok}
+
+
 def cube_operator(hx, workloads, p, cells):
     V = workloads.box_vertices(cells, cells, cells, perturb=0.2, seed=2)
     op = hx.Operator(cells, cells, cells, V, p, law="cnh", mu=1.0, lam=100.0, dirichlet_faces=(0,))
@@ -170,6 +186,8 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     timer = Timer(torch, stream)
+    triad = hbm_probe(hx, torch, dev, timer)
+    print(f"[bench] STREAM triad: {triad['GBps']:.0f} GB/s", file=sys.stderr, flush=True)
     degrees = [int(x) for x in args.degrees.split(",")]
     if args.p not in degrees:
         degrees.append(args.p)
@@ -244,6 +262,11 @@ def main():
         roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
         tr = measured_traffic(head["p"], head["mode"])
         roof["traffic"] = tr
+        # context: the rate a plain streaming kernel sustains on this device (not the peak)
+        roof["achievable"] = triad["GBps"]
+        roof["frac_of_achievable"] = gbs / triad["GBps"]
+        if tr:
+            roof["traffic_rate"] = tr / (ms * 1e-3) / 1e9
     else:
         roof = {"bound": "alu", "achieved": tfl, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": tfl / FP64_PEAK_TFLOPS, "traffic": measured_traffic(head["p"], head["mode"])}
@@ -272,6 +295,7 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(head["p"], args.cells, gpu_dst=head["dst"])
     out["sweep"] = sweep
+    extra["hbm_triad"] = triad
     out["extra"] = extra
     print(json.dumps(out), flush=True)
 

@@ -335,6 +335,17 @@ hx_status hx_qpoint_eval(const hx_material* mat, int32_t form, hx_precision prec
                          int64_t n, const double* H, const double* G, double* P, double* dP,
                          void* stream);
 
+/* ------------------------------------------------------------------------------------------
+ * Device bandwidth probe (not part of the method).
+ * ------------------------------------------------------------------------------------------ */
+/* STREAM "triad" (McCalpin's memory benchmark): a[i] = b[i] + s * c[i] for 0 <= i < n, FP64
+ * device arrays owned by the caller, each 16-byte aligned and not overlapping; moves 24 n bytes.
+ * It states the HBM rate a plain streaming kernel sustains on the device, against which the
+ * operator's bytes per apply can be read. Asynchronous on the stream; HX_E_ARG for n < 0, a NULL
+ * or misaligned array, or n beyond 2^39. */
+hx_status hx_stream_triad(int64_t n, double* a, const double* b, const double* c, double s,
+                          void* stream);
+
 const char* hx_last_error(hx_ctx ctx);
 const char* hx_status_string(hx_status s);
 

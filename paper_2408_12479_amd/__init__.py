@@ -110,6 +110,7 @@ def _load():
         "hx_surface_load": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
         "hx_qpoint_eval": (ctypes.c_int, [ctypes.POINTER(_Material), ctypes.c_int32, ctypes.c_int, ctypes.c_int32,
                                           i64, vp, vp, vp, vp, vp]),
+        "hx_stream_triad": (ctypes.c_int, [i64, vp, vp, vp, ctypes.c_double, vp]),
         "hx_last_error": (ctypes.c_char_p, [vp]),
         "hx_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     }
@@ -167,6 +168,20 @@ def qpoint_eval(H, G, law, form="stable", precision="fp64", jpow_newton_iters=0,
                               int(jpow_newton_iters), n, ctypes.c_void_p(H.data_ptr()), ctypes.c_void_p(G.data_ptr()),
                               ctypes.c_void_p(P.data_ptr()), ctypes.c_void_p(dP.data_ptr()), _stream_handle(stream)))
     return P, dP
+
+
+def stream_triad(a, b, c, s, stream=None):
+    """a = b + s c on contiguous CUDA float64 tensors of one length (hx_stream_triad, the STREAM
+    triad bandwidth probe)."""
+    import torch
+    for t in (a, b, c):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+            raise TypeError("a, b and c must be contiguous CUDA float64 tensors")
+    if not a.numel() == b.numel() == c.numel():
+        raise ValueError("a, b and c must have the same length")
+    _check(lib.hx_stream_triad(a.numel(), ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                               ctypes.c_void_p(c.data_ptr()), float(s), _stream_handle(stream)))
+    return a
 
 
 def _stream_handle(stream):

@@ -265,6 +265,20 @@ __global__ void fill_timing_direction(T* __restrict__ x, int64_t n) {
   if (i < n) x[i] = T(1) + T(i % 7) * T(0.125);
 }
 
+// STREAM triad, two elements per thread with 16-byte loads and stores (the last thread of an odd
+// n takes one element)
+__global__ void stream_triad(double* __restrict__ a, const double* __restrict__ b,
+                             const double* __restrict__ c, double s, int64_t n) {
+  const int64_t i = 2 * (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x);
+  if (i + 1 < n) {
+    const double2 x = *reinterpret_cast<const double2*>(b + i);
+    const double2 y = *reinterpret_cast<const double2*>(c + i);
+    *reinterpret_cast<double2*>(a + i) = make_double2(x.x + s * y.x, x.y + s * y.y);
+  } else if (i < n) {
+    a[i] = b[i] + s * c[i];
+  }
+}
+
 int grid_for(int64_t n) {
   const int64_t b = (n + 255) / 256;
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(b, 8192)));
@@ -756,6 +770,17 @@ int64_t hx_linearization_bytes(hx_ctx ctx, hx_precision prec) {
   if (!ctx || store_of(prec) < 0) return -1;
   const Slot& sl = ctx->slot[prec == HX_FP64 ? 0 : 1];
   return sl.valid ? static_cast<int64_t>(sl.qbytes) : 0;
+}
+
+hx_status hx_stream_triad(int64_t n, double* a, const double* b, const double* c, double s, void* stream) {
+  const auto misaligned = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15) != 0; };
+  if (n < 0 || n > (int64_t(1) << 39)) return HX_E_ARG;
+  if (n == 0) return HX_OK;
+  if (!a || !b || !c || misaligned(a) || misaligned(b) || misaligned(c)) return HX_E_ARG;
+  const int64_t blocks = (n + 511) / 512;  // 256 threads x 2 elements
+  hipLaunchKernelGGL(stream_triad, dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), a, b, c, s, n);
+  return hipGetLastError() == hipSuccess ? HX_OK : HX_E_HIP;
 }
 
 }  // extern "C"
