@@ -37,7 +37,7 @@ struct hx_ctx_s {
   std::vector<double> vert_host;  // [V][3]
   double* vert64 = nullptr;
   int* flag = nullptr;
-  void* ework = nullptr;  // element-vector rows of cell-boundary nodes (apply, residual)
+  void* ework = nullptr;  // element vectors on the broken lattice (apply, residual)
   void* cblk64 = nullptr;
   void* cblk32 = nullptr;
   double* fib64 = nullptr;  // per-cell fibre tensors (frames given), else NULL

@@ -61,8 +61,8 @@ struct KernelArgs {
   const R* in0;         // gathered vector (du, or u for residual/update)
   const R* in1;         // linearisation point u_k (recompute mode)
   R* out;               // output vector (apply, residual)
-  R* ework;             // cell-boundary rows of the element vectors on the broken lattice
-                        // [3][nz*N][ny*N][nx*N] (apply, residual; summed by assemble_kernel)
+  R* ework;             // element vectors on the broken lattice [3][nz*N][ny*N][nx*N]
+                        // (apply, residual; summed by assemble_kernel)
   const void* qdata;    // stored per-q-point planes [block][W][cells_per_block * Q]
   void* qdata_w;        // planes written by the update
   const float* cscale;  // per-cell power-of-two scale of binary16 data
