@@ -244,15 +244,25 @@ def main():
         del ud, dud, dst, r
         torch.cuda.empty_cache()
 
+    def study(name, fn):
+        # a failing side study is reported in its entry; the headline line is still printed
+        try:
+            extra[name] = fn()
+        except Exception as exc:  # noqa: BLE001
+            print(f"[bench] {name} failed: {exc!r}", file=sys.stderr, flush=True)
+            extra[name] = {"error": repr(exc)}
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+
     if not args.no_fp32:
-        extra["fiber_box_q3"] = fp32_study(hx, workloads, torch, dev, timer, args)
+        study("fiber_box_q3", lambda: fp32_study(hx, workloads, torch, dev, timer, args))
     if not args.no_stability:
-        extra["forward_stability"] = stability_study(hx, workloads, torch)
+        study("forward_stability", lambda: stability_study(hx, workloads, torch))
     if not args.no_mg:
-        extra["tube_vcycle_p6321"] = mg_study(hx, workloads, torch, dev, timer)
+        study("tube_vcycle_p6321", lambda: mg_study(hx, workloads, torch, dev, timer))
     if not args.no_newton:
         cells = tuple(int(c) for c in args.newton_cells.split(","))
-        extra["tube_newton_q4"] = newton_study(hx, workloads, torch, dev, cells=cells, bf16=args.newton_bf16)
+        study("tube_newton_q4", lambda: newton_study(hx, workloads, torch, dev, cells=cells, bf16=args.newton_bf16))
 
     # roofline of the headline kernel
     ms = head["ms"]
