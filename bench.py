@@ -12,7 +12,8 @@ timed region starts.
 Also reported: GDoF/s of every (p, storage mode) pair for p = 2, 3, 4, 6, the update and
 residual times, FP32 / BF16 / FP16 applies of the anisotropic 64x32x32 Q3 workload with their
 errors against the FP64 apply, the live roofline of the headline kernel and the FP64 oracle
-timed on a bounded sample of cells on the host (cpu_baseline).
+timed on a bounded sample of cells on the host (cpu_baseline). The oracle leg also states the
+error of every sweep entry against the oracle on sampled output rows (rel_err_vs_oracle_sampled).
 """
 import argparse
 import hashlib
@@ -155,6 +156,30 @@ def cpu_baseline(p, cells, budget_s=15.0, gpu_dst=None):
     return out
 
 
+def sample_nodes(n_nodes, p, k=12):
+    """Output rows checked against the oracle in every sweep entry: the first and last node and k
+    seeded random ones."""
+    rng = np.random.default_rng(100 + p)
+    return np.unique(np.concatenate([[0, n_nodes - 1], rng.integers(0, n_nodes, k)]))
+
+
+def sweep_parity(samples, cells):
+    """Part of the oracle leg: relative 2-norm error of every sweep entry's apply on its sampled
+    rows, against the FP64 oracle evaluated on all cells that touch those nodes."""
+    import workloads
+    from oracle import fem, material, mesh
+    out = {}
+    for p, (nodes, rows) in samples.items():
+        V = workloads.box_vertices(cells, cells, cells, perturb=0.2, seed=2)
+        m = mesh.BoxMesh(cells, cells, cells, V, p, dirichlet_faces=(0,))
+        pb = fem.Problem(m, material.Material("cnh", mu=1.0, lam=100.0), chunk=32)
+        u, du = workloads.sweep_fields(m.node_coords, m.constrained)
+        ref = pb.apply_tangent(u, du, cells=pb.cells_touching(nodes)).reshape(3, m.n_nodes)[:, nodes]
+        out[f"p{p}"] = {mode: float(np.linalg.norm(y - ref) / np.linalg.norm(ref)) for mode, y in rows.items()}
+        out[f"p{p}"]["rows"] = int(ref.size)
+    return out
+
+
 def measured_traffic(p, mode):
     """HBM bytes per apply from the committed rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE,
     scaled by the plain copy kernel's reading), if they were taken on this kernel source."""
@@ -193,6 +218,7 @@ def main():
         degrees.append(args.p)
     modes = ["none", "finv_j", "tangent", "spatial"]
     sweep = {}
+    samples = {}
     extra = {}
     head = None
     for p in sorted(degrees):
@@ -206,6 +232,9 @@ def main():
         dud = torch.tensor(du.reshape(-1), dtype=torch.float64, device=dev)
         dst = torch.empty_like(dud)
         r = torch.empty_like(ud)
+        nodes = sample_nodes(op.num_nodes, p)
+        nodes_d = torch.tensor(nodes, device=dev)
+        rows = {}
         t_res = timer.time(lambda: op.residual(ud, r), 5)
         res = {"dofs": op.num_dofs, "cells": op.num_cells, "residual_ms": t_res}
         for mode in modes:
@@ -217,11 +246,13 @@ def main():
             reps = args.steps if p == args.p else max(5, args.steps // 4)
             ms = timer.time(lambda: op.apply_tangent(dud, dst), reps)
             b, f = algorithmic(p, mode, op.num_cells, op.num_dofs)
+            rows[mode] = dst.view(3, -1)[:, nodes_d].cpu().numpy()
             res[mode] = {"apply_ms": ms, "gdofs": op.num_dofs / ms / 1e6, "update_ms": t_upd,
                          "data_bytes": op.linearization_bytes("fp64"),
                          "hbm_frac": b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                          "fp64_frac": f / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}
         sweep[f"p{p}"] = res
+        samples[p] = (nodes, rows)
         print(f"[bench] p={p}: " + ", ".join(f"{m_} {res[m_]['gdofs']:.2f} GDoF/s" for m_ in modes),
               file=sys.stderr, flush=True)
         if p == args.p:
@@ -304,6 +335,12 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(head["p"], args.cells, gpu_dst=head["dst"])
+        par = sweep_parity(samples, args.cells)
+        out["cpu_baseline"]["sweep_parity"] = par
+        for key, errs in par.items():
+            for mode, err in errs.items():
+                if mode in sweep[key]:
+                    sweep[key][mode]["rel_err_vs_oracle_sampled"] = err
     out["sweep"] = sweep
     extra["hbm_triad"] = triad
     out["extra"] = extra
