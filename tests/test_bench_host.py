@@ -68,3 +68,24 @@ def test_traffic_reader_checks_the_kernel_source(tmp_path, monkeypatch):
     assert bench.measured_traffic(6, "spatial") is None      # not measured
     kernel.write_text("// kernel B\n")
     assert bench.measured_traffic(4, "spatial") is None      # source changed since
+
+
+def test_sweep_parity_on_a_small_cube():
+    """The oracle leg's sampled-row check: rows equal to the oracle's full apply give zero error, a
+    relative perturbation of 1e-9 gives 1e-9."""
+    import numpy as np
+
+    import workloads
+    from oracle import fem, material, mesh
+    p, cells = 2, 4
+    V = workloads.box_vertices(cells, cells, cells, perturb=0.2, seed=2)
+    m = mesh.BoxMesh(cells, cells, cells, V, p, dirichlet_faces=(0,))
+    pb = fem.Problem(m, material.Material("cnh", mu=1.0, lam=100.0))
+    u, du = workloads.sweep_fields(m.node_coords, m.constrained)
+    nodes = bench.sample_nodes(m.n_nodes, p)
+    assert nodes[0] == 0 and nodes[-1] == m.n_nodes - 1
+    full = pb.apply_tangent(u, du).reshape(3, m.n_nodes)[:, nodes]
+    out = bench.sweep_parity({p: (nodes, {"same": full, "scaled": full * (1 + 1e-9)})}, cells)
+    assert out["p2"]["same"] == 0.0
+    assert out["p2"]["scaled"] == pytest.approx(1e-9, rel=1e-3)
+    assert out["p2"]["rows"] == 3 * len(nodes)

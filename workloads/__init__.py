@@ -20,6 +20,8 @@ Workload recipes (stand-ins for the paper's unspecified "deformed cube", Section
   psi = sin(pi x) sin(pi y) sin(pi z) / pi, alpha such that max |J - 1| = 0.05 for the
   continuous field; du ~ N(0,1) (seed 4); no constraints.
 """
+import functools
+
 import numpy as np
 
 FACE_MINUS_X, FACE_PLUS_X, FACE_MINUS_Y, FACE_PLUS_Y, FACE_MINUS_Z, FACE_PLUS_Z = range(6)
@@ -92,6 +94,7 @@ def _max_stretch_of_bump(alpha, samples=41):
     return np.sqrt(np.max(np.linalg.eigvalsh(C)[:, -1])), np.min(np.linalg.det(F))
 
 
+@functools.lru_cache(maxsize=None)
 def bump_amplitude_for_stretch(target=1.3):
     """alpha with max principal stretch of u = alpha s(x)(1,1,1) equal to ``target`` (bisection)."""
     lo, hi = 0.0, 1.0
@@ -137,6 +140,7 @@ def _max_dev_J(alpha, lengths=(2.0, 1.0, 1.0), samples=(61, 31, 31)):
     return np.max(np.abs(J - 1.0))
 
 
+@functools.lru_cache(maxsize=None)
 def gradient_field_amplitude(target=0.05):
     lo, hi = 0.0, 1.0
     for _ in range(60):
