@@ -64,10 +64,8 @@ def algorithmic(p, mode, n_cells, n_dofs):
     words = QPOINT_WORDS[mode]
     vec_words = 2 + (1 if mode == "none" else 0)
     bytes_ = 8.0 * (vec_words * n_dofs + words * Q * n_cells)
-    fields = 3 + (3 if mode == "none" else 0)
     sumfac_fma = (12 * n ** 4) * 3 + (6 * n ** 4 * 3 if mode == "none" else 0)
     flops = n_cells * (2.0 * sumfac_fma + QPOINT_FLOPS[mode] * Q)
-    del fields
     return bytes_, flops
 
 
