@@ -1,6 +1,7 @@
 """Assembly of the element vectors (the node kernel that sums the cells' bricks) on lattices that
 are periodic in the second or the third direction and on the smallest lattices, against the
-oracle: residual and the applies of every storage mode, FP64 <= 1e-12 and FP32 <= 1e-5.
+oracle: residual and the applies of every storage mode, FP64 <= 1e-12 and FP32 <= 1e-5; and the
+largest lattice the 32-bit indexing admits.
 
 The periodic cases place the tube's circumferential index on lattice direction y or z by an even
 (cyclic) permutation of the lattice axes, which keeps every cell right-handed; the clamped faces
@@ -98,3 +99,16 @@ def test_repeated_applies_bit_identical(device):
     for _ in range(5):
         assert np.array_equal(op.apply_tangent(dud).cpu().numpy(), y0)
     op.close()
+
+
+def test_lattice_beyond_the_index_range_is_refused(device):
+    """The kernels index Gauss points and nodes in 32 bits: hx_setup refuses a lattice with
+    cells * (p+1)^3 >= 2^31 (here 200 x 200 x 157 cells at Q6, 2.16e9 Gauss points) before it
+    allocates or checks anything else."""
+    nx, ny, nz = 200, 200, 157
+    assert nx * ny * nz * 343 > 2 ** 31 - 1
+    V = np.zeros(((nz + 1) * (ny + 1) * (nx + 1), 3))
+    with pytest.raises(hx.HxError) as err:
+        hx.Operator(nx, ny, nz, V, 6, law="cnh", mu=1.0, lam=1.0)
+    assert err.value.name == "HX_E_ARG"
+    assert "too large" in str(err.value)
