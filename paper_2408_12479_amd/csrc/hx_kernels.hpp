@@ -867,7 +867,7 @@ __device__ __forceinline__ void backward_scatter(const KernelArgs<N, R>& a, R* s
 }
 
 // ------------------------------------------------------------------------------------------
-// Assembly of the rows of cell-boundary nodes
+// Assembly of the element vectors at the lattice nodes
 // ------------------------------------------------------------------------------------------
 // Cells meeting at lattice index Ig along one direction (ncell cells, Nn nodes; periodic if
 // Nn == ncell * P): up to two (cell, local index) pairs, the lower cell first.
