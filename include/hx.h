@@ -235,9 +235,11 @@ typedef struct {
   int32_t coarse_solver;   /* coarsest level: 0 = dense if it has at most 8192 DoFs, else
                               Chebyshev (default); 1 = Chebyshev of coarse_degree; 2 = dense
                               (HX_E_UNSUPPORTED above 8192 DoFs). Dense: the level operator is
-                              assembled by probing with 3 k_x k_y k_z coloured vectors, factored
-                              by Cholesky (rocSOLVER, FP64) at each update and applied as its
-                              explicit inverse. */
+                              assembled by probing with 3 k_x k_y k_z coloured vectors (k_d >=
+                              2p + 1 colours along direction d for a coarsest degree p, so that
+                              no two coupled nodes share a colour), factored by Cholesky
+                              (rocSOLVER, FP64) at each update and applied as its explicit
+                              inverse. */
 } hx_mg_options;
 
 /* Fills *opt with the defaults listed above. */

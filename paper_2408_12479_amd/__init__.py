@@ -199,6 +199,10 @@ class Operator:
         """frames: optional [n_cells, 3, 3] local fibre frames (rows E1, E2, E3); H4..M6 are then
         components in each cell's frame."""
         V = np.ascontiguousarray(vertices, dtype=np.float64)
+        vdims = [int(n) + (0 if periodic[d] else 1) for d, n in enumerate((nx, ny, nz))]
+        if V.size != 3 * vdims[0] * vdims[1] * vdims[2]:
+            raise ValueError(f"vertices must hold 3 * {vdims[0]} * {vdims[1]} * {vdims[2]} values for this "
+                             f"lattice and periodicity, got {V.size}")
         self._vert = V
         fr = None
         if frames is not None:

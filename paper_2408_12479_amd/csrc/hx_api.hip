@@ -606,12 +606,14 @@ hx_status hx_update_linearization(hx_ctx ctx, const double* u, hx_storage mode, 
   const size_t need = static_cast<size_t>(mode_words(mode, ctx->base.mat.law)) * padded_cells * Q * store_bytes(st);
   hipError_t e = hipStreamSynchronize(s);  // the slot's buffers may still be in use
   if (e != hipSuccess) return hip_fail(ctx, e, "hx_update_linearization: sync");
+  // the slot is unusable from here until the new data has been written: a failure below leaves it
+  // invalid (an apply then returns HX_E_STATE instead of reading stale or partial data)
+  sl.valid = false;
   if (need > sl.qcap) {
     if (sl.qdata) (void)hipFree(sl.qdata);
     sl.qdata = nullptr;
     sl.qcap = 0;
     if ((e = hipMalloc(&sl.qdata, need)) != hipSuccess) {
-      sl.valid = false;
       sl.qbytes = 0;
       return hip_fail(ctx, e, "hx_update_linearization: q-point data");
     }
@@ -620,7 +622,6 @@ hx_status hx_update_linearization(hx_ctx ctx, const double* u, hx_storage mode, 
   sl.qbytes = need;
   if (st == kStoreF16 && !sl.cscale) {
     if ((e = hipMalloc(&sl.cscale, L.n_cells * sizeof(float))) != hipSuccess) {
-      sl.valid = false;
       return hip_fail(ctx, e, "hx_update_linearization: cell scales");
     }
   }
@@ -629,8 +630,7 @@ hx_status hx_update_linearization(hx_ctx ctx, const double* u, hx_storage mode, 
     const size_t ub = n * (prec == HX_FP64 ? sizeof(double) : sizeof(float));
     if (!sl.uk) {
       if ((e = hipMalloc(&sl.uk, ub)) != hipSuccess) {
-        sl.valid = false;
-        return hip_fail(ctx, e, "hx_update_linearization: u_k");
+          return hip_fail(ctx, e, "hx_update_linearization: u_k");
       }
     }
     if (prec == HX_FP64)
@@ -649,8 +649,7 @@ hx_status hx_update_linearization(hx_ctx ctx, const double* u, hx_storage mode, 
       sl.act = nullptr;
       sl.act_bytes = 0;
       if ((e = hipMalloc(&sl.act, ab)) != hipSuccess) {
-        sl.valid = false;
-        return hip_fail(ctx, e, "hx_update_linearization: fibre switches");
+          return hip_fail(ctx, e, "hx_update_linearization: fibre switches");
       }
       sl.act_bytes = ab;
     }

@@ -83,14 +83,12 @@ template <> struct StoreOf<kStoreF16> { using T = _Float16; };
 // ------------------------------------------------------------------------------------------
 // Scalar math, per arithmetic type
 // ------------------------------------------------------------------------------------------
-__device__ __forceinline__ double m_log1p(double x) { return log1p(x); }
-__device__ __forceinline__ float m_log1p(float x) { return log1pf(x); }
 __device__ __forceinline__ double m_exp(double x) { return exp(x); }
 // FP32: the hardware base-2 exponential after scaling by log2(e)
 __device__ __forceinline__ float m_exp(float x) { return __expf(x); }
 
-// J^(-2/3): FP64 by the cube root; FP32 by Newton steps on f(x) = x^-3 - J^2 from x0 = 1
-// (Algorithm 2, Section 4) when iters > 0.
+// J^(-2/3): by the cube root in FP64 (also for FP32 arithmetic, see vol_scalars); FP32 by Newton
+// steps on f(x) = x^-3 - J^2 from x0 = 1 (Algorithm 2, Section 4) when iters > 0.
 __device__ __forceinline__ double jpow(double Jm, int) {
   const double c = cbrt(1.0 + Jm);
   return 1.0 / (c * c);
@@ -105,8 +103,7 @@ __device__ __forceinline__ float jpow(float Jm, int iters) {
     }
     return beta;
   }
-  const float c = cbrtf(1.0f + Jm);
-  return 1.0f / (c * c);
+  return static_cast<float>(jpow(static_cast<double>(Jm), 0));
 }
 
 // ------------------------------------------------------------------------------------------
@@ -223,6 +220,20 @@ __device__ __forceinline__ void fiber_scalars(const MaterialK<R>& m, R Ei, R ImO
   s.dfac[f] = R(2) * m.k2 * e2 + R(1);
 }
 
+// iNH and fibre scalars from J - 1 and I1 = tr C (Section 5 definitions): J^-2/3,
+// c1 = kappa/2 (J^2 - 1) - mu/3 J^-2/3 I1 and c2 = 2 mu/9 J^-2/3 I1 + kappa J^2, evaluated in FP64
+// for both arithmetics and rounded once (FP32 keeps Algorithm 2 for J^-2/3 when asked for).
+template <typename R>
+__device__ __forceinline__ void vol_scalars(double Jm, double I1, const MaterialK<R>& m, QState<R>& s) {
+  const double Jp = (sizeof(R) == 4 && m.jpow_iters > 0) ? static_cast<double>(jpow(static_cast<R>(Jm), m.jpow_iters))
+                                                          : jpow(Jm, 0);
+  const double kap = static_cast<double>(m.kappa), mu = static_cast<double>(m.mu);
+  const double J = 1.0 + Jm;
+  s.Jp = static_cast<R>(Jp);
+  s.c1 = static_cast<R>(0.5 * kap * Jm * (Jm + 2.0) - mu / 3.0 * Jp * I1);
+  s.c2 = static_cast<R>(2.0 * mu / 9.0 * Jp * I1 + kap * J * J);
+}
+
 // State from the displacement gradient H = Grad u (stable forms of Section 4):
 // E = (H + H^T + H^T H)/2, J - 1 from the invariants of H, C^-1 via F^-1.
 // Returns false when J <= 0. E is written to Eout (for the residual).
@@ -234,10 +245,15 @@ __device__ __forceinline__ bool state_from_H(const R* H, const MaterialK<R>& m,
   s.F[0] += R(1);
   s.F[4] += R(1);
   s.F[8] += R(1);
-  const R trH = H[0] + H[4] + H[8];
-  const R I2 = H[0] * H[4] + H[0] * H[8] + H[4] * H[8] - H[1] * H[3] - H[2] * H[6] - H[5] * H[7];
-  const R I3 = det3(H);
-  s.Jm = I3 + I2 + trH;  // det(I + H) - 1 = I1(H) + I2(H) + I3(H)
+  // det(I + H) - 1 = I1(H) + I2(H) + I3(H), in FP64 also for FP32 arithmetic: J and the volumetric
+  // terms near J = 1 keep double precision, and the FP32 kernels round their results once
+  double Hd[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Hd[i] = static_cast<double>(H[i]);
+  const double trH = Hd[0] + Hd[4] + Hd[8];
+  const double I2 = Hd[0] * Hd[4] + Hd[0] * Hd[8] + Hd[4] * Hd[8] - Hd[1] * Hd[3] - Hd[2] * Hd[6] - Hd[5] * Hd[7];
+  const double Jmd = det3(Hd) + I2 + trH;
+  s.Jm = static_cast<R>(Jmd);
   const R J = R(1) + s.Jm;
   R A[9];
   adj3(s.F, A);
@@ -252,12 +268,9 @@ __device__ __forceinline__ bool state_from_H(const R* H, const MaterialK<R>& m,
       E[3 * i + j] = R(0.5) * (H[3 * i + j] + H[3 * j + i] + H[i] * H[j] + H[3 + i] * H[3 + j] +
                                H[6 + i] * H[6 + j]);
   if constexpr (LAW == kCNH) {
-    s.lnJ = m_log1p(s.Jm);
+    s.lnJ = static_cast<R>(log1p(Jmd));
   } else {
-    s.Jp = jpow(s.Jm, m.jpow_iters);
-    const R I1 = R(3) + R(2) * (E[0] + E[4] + E[8]);
-    s.c1 = R(0.5) * m.kappa * s.Jm * (s.Jm + R(2)) - m.mu / R(3) * s.Jp * I1;
-    s.c2 = R(2) * m.mu / R(9) * s.Jp * I1 + m.kappa * J * J;
+    vol_scalars<R>(Jmd, static_cast<double>(R(3) + R(2) * (E[0] + E[4] + E[8])), m, s);
     if constexpr (kIsFiber<LAW>) {
 #pragma unroll
       for (int f = 0; f < 2; ++f) {
@@ -286,19 +299,17 @@ __device__ __forceinline__ void state_from_finv(const R* Fi, R Jm, const Materia
   for (int i = 0; i < 9; ++i) s.Fi[i] = Fi[i];
   s.Jm = Jm;
   if constexpr (LAW == kCNH) {
-    s.lnJ = m_log1p(Jm);
+    s.lnJ = static_cast<R>(log1p(static_cast<double>(Jm)));
   } else {
     const R J = R(1) + Jm;
     R A[9];
     adj3(Fi, A);
 #pragma unroll
     for (int i = 0; i < 9; ++i) s.F[i] = A[i] * J;
-    s.Jp = jpow(Jm, m.jpow_iters);
     R I1 = R(0);
 #pragma unroll
     for (int i = 0; i < 9; ++i) I1 += s.F[i] * s.F[i];
-    s.c1 = R(0.5) * m.kappa * Jm * (Jm + R(2)) - m.mu / R(3) * s.Jp * I1;
-    s.c2 = R(2) * m.mu / R(9) * s.Jp * I1 + m.kappa * J * J;
+    vol_scalars<R>(static_cast<double>(Jm), static_cast<double>(I1), m, s);
     if constexpr (kIsFiber<LAW>) {
       R C[9];
 #pragma unroll

@@ -149,9 +149,12 @@ __global__ void k_probe(T* x, Lattice L, int kx, int ky, int kz, int cx, int cy,
   }
 }
 
-// index in {I-1, I, I+1} (wrapped if periodic, skipped if outside) congruent to col mod k; -1 if none
-__device__ __forceinline__ int probe_hit(int I, int N, bool periodic, int k, int col) {
-  for (int d = -1; d <= 1; ++d) {
+// index in {I-p, ..., I+p} (wrapped if periodic, skipped if outside) congruent to col mod k; -1 if
+// none. Nodes of degree-p cells couple with the nodes up to p lattice indices away, and k >= 2p + 1
+// colours (or k = N, one colour per index) leave at most one candidate in that window.
+__device__ __forceinline__ int probe_hit(int I, int N, bool periodic, int k, int col, int p) {
+  if (k == N) return col;
+  for (int d = -p; d <= p; ++d) {
     int J = I + d;
     if (periodic) {
       J = J < 0 ? J + N : (J >= N ? J - N : J);
@@ -174,9 +177,9 @@ __global__ void k_probe_extract(const T* __restrict__ y, double* __restrict__ A,
     const int I = static_cast<int>(node % L.Nx);
     const int J = static_cast<int>((node / L.Nx) % L.Ny);
     const int K = static_cast<int>(node / (static_cast<int64_t>(L.Nx) * L.Ny));
-    const int a = probe_hit(I, L.Nx, L.Nx == L.nx, kx, cx);
-    const int b = probe_hit(J, L.Ny, L.Ny == L.ny, ky, cy);
-    const int c = probe_hit(K, L.Nz, L.Nz == L.nz, kz, cz);
+    const int a = probe_hit(I, L.Nx, L.Nx == L.nx * L.p, kx, cx, L.p);
+    const int b = probe_hit(J, L.Ny, L.Ny == L.ny * L.p, ky, cy, L.p);
+    const int c = probe_hit(K, L.Nz, L.Nz == L.nz * L.p, kz, cz, L.p);
     if (a < 0 || b < 0 || c < 0) continue;
     const int64_t col = cc * L.n_nodes + a + static_cast<int64_t>(L.Nx) * (b + static_cast<int64_t>(L.Ny) * c);
     A[col * n + i] = static_cast<double>(y[i]);
@@ -737,18 +740,21 @@ hipError_t estimate_spectrum(hx_mg mg, int l, double* lmax, double* lmin) {
   return hipGetLastError();
 }
 
-// smallest colour count >= 3 along a lattice direction that keeps probe columns apart: any k
-// >= 3 for an open direction (at most N), a divisor of N for a periodic one (so the wrap keeps
-// same-coloured nodes 3 or more indices apart)
-int probe_colours(int N, bool periodic) {
-  if (!periodic) return std::min(3, N);
-  for (int k = 3; k <= N; ++k)
+// smallest colour count >= 2p + 1 along a lattice direction that keeps probe columns apart (a node
+// couples with the nodes up to p indices away): any such k for an open direction (at most N, where
+// every index is its own colour), a divisor of N for a periodic one (so the wrap keeps
+// same-coloured nodes 2p + 1 or more indices apart), else N
+int probe_colours(int N, bool periodic, int p) {
+  const int k0 = 2 * p + 1;
+  if (!periodic) return std::min(k0, N);
+  for (int k = k0; k <= N; ++k)
     if (N % k == 0) return k;
   return N;
 }
 
-// Assembles the coarsest operator by probing (3 * kx * ky * kz applies), factors it by Cholesky
-// (rocSOLVER, FP64) and stores its inverse in the hierarchy precision.
+// Assembles the coarsest operator by probing (3 * kx * ky * kz applies, k >= 2p + 1 colours per
+// direction), factors it by Cholesky (rocSOLVER, FP64) and stores its inverse in the hierarchy
+// precision.
 template <typename T>
 hx_status dense_coarse_update(hx_mg mg) {
   const int l = static_cast<int>(mg->lv.size()) - 1;
@@ -758,8 +764,8 @@ hx_status dense_coarse_update(hx_mg mg) {
   T* x = B[B_X].as<T>();
   T* y = B[B_T].as<T>();
   double* A = mg->cA.as<double>();
-  const int kx = probe_colours(L.Nx, L.Nx == L.nx), ky = probe_colours(L.Ny, L.Ny == L.ny),
-            kz = probe_colours(L.Nz, L.Nz == L.nz);
+  const int kx = probe_colours(L.Nx, L.Nx == L.nx * L.p, L.p), ky = probe_colours(L.Ny, L.Ny == L.ny * L.p, L.p),
+            kz = probe_colours(L.Nz, L.Nz == L.nz * L.p, L.p);
   k_fill<double><<<grid_for(n * n), 256, 0, mg->stream>>>(A, 0.0, n * n);
   for (int cc = 0; cc < 3; ++cc)
     for (int cz = 0; cz < kz; ++cz)

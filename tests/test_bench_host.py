@@ -89,3 +89,36 @@ def test_sweep_parity_on_a_small_cube():
     assert out["p2"]["same"] == 0.0
     assert out["p2"]["scaled"] == pytest.approx(1e-9, rel=1e-3)
     assert out["p2"]["rows"] == 3 * len(nodes)
+
+
+def test_line_flops_follow_the_even_odd_form():
+    """Flops of one 1D contraction as executed: plain n^2 multiply-adds up to n = 4; from n = 5 on
+    the even-odd form (n = 5: 13 multiply-adds and 8 additions for the interpolation matrix, n = 7:
+    25 and 12), always below the plain count."""
+    assert bench.line_flops(3, 1) == 18 and bench.line_flops(4, -1) == 32
+    assert bench.line_flops(5, 1) == 2 * 13 + 8
+    assert bench.line_flops(7, 1) == 2 * 25 + 12
+    for n in (5, 6, 7):
+        assert bench.line_flops(n, 1) < 2 * n * n and bench.line_flops(n, -1) < 2 * n * n
+
+
+def test_oracle_leg_runs_in_a_worker_pool():
+    """The cpu_baseline leg on a tiny cube: every cell is timed, all rows compared give zero error
+    against the oracle's own full apply, and the cores and host model are stated."""
+    import numpy as np
+
+    import workloads
+    from oracle import fem, material, mesh
+    p, cells = 2, 3
+    V = workloads.box_vertices(cells, cells, cells, perturb=0.2, seed=2)
+    m = mesh.BoxMesh(cells, cells, cells, V, p, dirichlet_faces=(0,))
+    pb = fem.Problem(m, material.Material("cnh", mu=1.0, lam=100.0))
+    u, du = workloads.sweep_fields(m.node_coords, m.constrained)
+    full = pb.apply_tangent(u, du).reshape(-1)
+    pool = bench.start_oracle_pool(2)
+    out = bench.cpu_baseline(pool, 2, p, cells, budget_s=30.0, gpu_dst=full)
+    assert out["cores"] == 2 and out["host"]["nproc"] >= 1 and out["host"]["model"]
+    assert f"{m.n_cells} of {m.n_cells} cells" in out["sample"]
+    assert out["rel_err_vs_oracle"] < 1e-14
+    assert out["rows_compared"] > 0
+    assert np.isfinite(out["value"]) and out["value"] > 0

@@ -274,12 +274,19 @@ def test_lattice_transfers_match_oracle(device):
         mg.close()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_dense_coarse_solve_is_exact(device, precision):
-    # a one-level hierarchy is its coarse solve: z = K~^-1 r
-    V = workloads.tube_vertices(4, 2, 3, length=1.0, bend=0.2)
-    op, pb = _operator((4, 2, 3), V, 1, law="fiber", faces=(4,), periodic=(True, False, False),
-                       frames=workloads.tube_frames(4, 2, 3, length=1.0, bend=0.2))
+@pytest.mark.parametrize("precision,p", [("fp64", 1), ("fp32", 1), ("fp64", 2), ("fp32", 2), ("fp64", 3)])
+def test_dense_coarse_solve_is_exact(device, precision, p):
+    # a one-level hierarchy is its coarse solve: z = K~^-1 r. At degree p a node couples with the
+    # nodes up to p lattice indices away, which the probing colours must keep apart (p = 2 on the
+    # periodic ring of 8 node planes: every plane its own colour; p = 3 on 3 x 2 x 2 cells: 7 colours
+    # along x)
+    if p == 3:
+        V = workloads.box_vertices(3, 2, 2, perturb=0.2, seed=2)
+        op, pb = _operator((3, 2, 2), V, 3, law="inh", faces=(0,), mu=2.0, kappa=50.0)
+    else:
+        V = workloads.tube_vertices(4, 2, 3, length=1.0, bend=0.2)
+        op, pb = _operator((4, 2, 3), V, p, law="fiber", faces=(4,), periodic=(True, False, False),
+                           frames=workloads.tube_frames(4, 2, 3, length=1.0, bend=0.2))
     u = _smooth_u(pb, scale=0.01)
     u[:, pb.mesh.constrained] = 0.0
     mg = hx.Multigrid([op], precision=precision, coarse_solver="dense")
