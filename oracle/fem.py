@@ -8,7 +8,8 @@ configurations):
                with A = dP/dF, i.e. the directional derivative of the residual (Problem 2.2)
 * energy       Pi(u) = sum_q w_q detJ0 Psi(C_q)  (whose gradient is the residual)
 
-Geometry: trilinear map of each hexahedron from its 8 vertices, J0 = dX/dxi at every Gauss point,
+Geometry: the map of each hexahedron, trilinear from its 8 vertices or of degree g from its values
+at the equispaced points of the reference cell (curved cells), J0 = dX/dxi at every Gauss point,
 Grad phi = J0^-T grad_xi phi, weights w_q det J0 (Gauss weights are tensor products on [0,1]^3).
 
 Constraints (the test space H^1_0 with homogeneous data, Problems 2.1-2.2; the operator reading
@@ -74,6 +75,25 @@ class ElementTables:
                     TN[:, v, 1] = fa * db * fc
                     TN[:, v, 2] = fa * fb * dc
         self.TN = TN
+        self._geo = {1: TN}
+
+    def geometry_derivatives(self, g):
+        """dG[q, a, d]: reference derivatives of the degree-g geometry basis (Lagrange on the g+1
+        equispaced points per direction, a = i + (g+1)(j + (g+1) k)) at the Gauss points. For
+        g = 1 these are the trilinear vertex functions' derivatives (TN)."""
+        if g not in self._geo:
+            n = self.n
+            xe = np.linspace(0.0, 1.0, g + 1)
+            L = basis.lagrange_values(xe, self.xq)
+            dL = basis.lagrange_derivatives(xe, self.xq)
+            m3 = (g + 1) ** 3
+
+            def t3(A, B, C):
+                # [qz, qy, qx, k, j, i] -> [q, a]
+                return np.einsum("xi,yj,zk->zyxkji", A, B, C).reshape(n ** 3, m3)
+
+            self._geo[g] = np.stack([t3(dL, L, L), t3(L, dL, L), t3(L, L, dL)], axis=-1)
+        return self._geo[g]
 
 
 class Problem:
@@ -106,8 +126,9 @@ class Problem:
     # -- geometry -----------------------------------------------------------------------------
     def geometry(self, cells):
         """(invJ0 [E, Q, 3(d), 3(J)], wdet [E, Q]) for the given cells; asserts det J0 > 0."""
-        X8 = self.mesh.cell_vertex_xyz[cells]                       # [E, 8, 3]
-        J0 = np.einsum("evc,qvd->eqcd", X8, self.tab.TN)            # dX_c / dxi_d
+        g = getattr(self.mesh, "geom_degree", 1)
+        Xg = self.mesh.cell_geom_xyz[cells]                         # [E, (g+1)^3, 3]
+        J0 = np.einsum("evc,qvd->eqcd", Xg, self.tab.geometry_derivatives(g))   # dX_c / dxi_d
         det = np.linalg.det(J0)
         if np.any(det <= 0.0):
             raise ValueError("inverted or degenerate cell: det J0 <= 0")
@@ -206,50 +227,73 @@ class Problem:
         return K
 
 
-def surface_load(problem, face, pressure):
-    """Dead-load pressure vector f_(c,a) = -p sum over boundary cells of int phi_a N_c dA.
+def surface_load_faces(problem, faces, pressure):
+    """Dead-load pressure vector f_(c,a) = -p sum over the listed cell faces of int phi_a N_c dA.
 
     Section 2 residual, Neumann term: h_N = -p N with N the outward unit normal of the reference
-    body; integrated with (p+1)^2 Gauss points on each cell face of the trilinear map.
+    body, integrated with (p+1)^2 Gauss points on each listed (cell, local face) of the cell's map
+    (trilinear or of degree g). The outward normal area element of local face f = (d, side) is
+    sign * (dX/dxi_a x dX/dxi_b), (a, b) = (d + 1, d + 2) mod 3, sign +1 on the side xi_d = 1.
     """
+    m = problem.mesh
+    p, n = m.p, m.n
+    g = getattr(m, "geom_degree", 1)
+    xg = basis.gll_points(p)
+    xq, wq = basis.gauss_rule(n)
+    xe = np.linspace(0.0, 1.0, g + 1)
+    L = basis.lagrange_values(xg, xq)             # L[q, i], the Q_p basis on the face
+    f = np.zeros((3, m.n_nodes))
+    for e, face in faces:
+        d, side = face // 2, face % 2
+        da, db = (d + 1) % 3, (d + 2) % 3
+        Xg = m.cell_geom_xyz[e]                   # [(g+1)^3, 3]
+        for q2 in range(n):
+            for q1 in range(n):
+                xi = [0.0, 0.0, 0.0]
+                xi[d], xi[da], xi[db] = (1.0 if side else 0.0), xq[q1], xq[q2]
+                val = [basis.lagrange_values(xe, [xi[k]])[0] for k in range(3)]
+                der = [basis.lagrange_derivatives(xe, [xi[k]])[0] for k in range(3)]
+
+                def grad(dir_):
+                    f3 = [der[k] if k == dir_ else val[k] for k in range(3)]
+                    w3 = np.einsum("k,j,i->kji", f3[2], f3[1], f3[0]).ravel()
+                    return w3 @ Xg
+
+                ta, tb = grad(da), grad(db)
+                NdA = np.cross(ta, tb) * (1.0 if side else -1.0)
+                w = wq[q1] * wq[q2]
+                for j2 in range(n):
+                    for j1 in range(n):
+                        loc = [0, 0, 0]
+                        loc[d], loc[da], loc[db] = (n - 1 if side else 0), j1, j2
+                        node = m.cell_nodes[e, loc[0] + n * (loc[1] + n * loc[2])]
+                        f[:, node] += -pressure * NdA * w * L[q1, j1] * L[q2, j2]
+    return f
+
+
+def surface_load(problem, face, pressure):
+    """Dead-load pressure vector on lattice boundary face ``face`` (0..5) of a BoxMesh."""
     m = problem.mesh
     d, side = face // 2, face % 2
     if m.periodic[d]:
         raise ValueError("face of a periodic direction")
-    p, n = m.p, m.n
-    xg = basis.gll_points(p)
-    xq, wq = basis.gauss_rule(n)
-    L = basis.lagrange_values(xg, xq)             # L[q, i]
     da, db = (d + 1) % 3, (d + 2) % 3
     ncells = (m.nx, m.ny, m.nz)
-    f = np.zeros((3, m.n_nodes))
     cd = ncells[d] - 1 if side else 0
+    faces = []
     for c2 in range(ncells[db]):
         for c1 in range(ncells[da]):
             cell = [0, 0, 0]
             cell[d], cell[da], cell[db] = cd, c1, c2
-            e = cell[0] + m.nx * (cell[1] + m.ny * cell[2])
-            X8 = m.cell_vertex_xyz[e]
-            for q2 in range(n):
-                for q1 in range(n):
-                    xi = [0.0, 0.0, 0.0]
-                    xi[d], xi[da], xi[db] = (1.0 if side else 0.0), xq[q1], xq[q2]
-                    ta, tb = np.zeros(3), np.zeros(3)
-                    for v in range(8):
-                        bit = (v & 1, (v >> 1) & 1, v >> 2)
-                        phi = [xi[k] if bit[k] else 1.0 - xi[k] for k in range(3)]
-                        dphi = [1.0 if bit[k] else -1.0 for k in range(3)]
-                        ta += dphi[da] * phi[db] * phi[d] * X8[v]
-                        tb += phi[da] * dphi[db] * phi[d] * X8[v]
-                    NdA = np.cross(ta, tb) * (1.0 if side else -1.0)
-                    w = wq[q1] * wq[q2]
-                    for j2 in range(n):
-                        for j1 in range(n):
-                            loc = [0, 0, 0]
-                            loc[d], loc[da], loc[db] = (n - 1 if side else 0), j1, j2
-                            node = m.cell_nodes[e, loc[0] + n * (loc[1] + n * loc[2])]
-                            f[:, node] += -pressure * NdA * w * L[q1, j1] * L[q2, j2]
-    return f
+            faces.append((cell[0] + m.nx * (cell[1] + m.ny * cell[2]), face))
+    return surface_load_faces(problem, faces, pressure)
+
+
+def surface_load_bid(problem, bid, pressure):
+    """Dead-load pressure vector on every cell face of a HexMesh whose boundary id is ``bid``."""
+    m = problem.mesh
+    faces = [(e, f) for e in range(m.n_cells) for f in range(6) if m.face_bid[e, f] == bid]
+    return surface_load_faces(problem, faces, pressure)
 
 
 def _owner_local(mesh, node):

@@ -19,6 +19,13 @@ Workload recipes (stand-ins for the paper's unspecified "deformed cube", Section
   families at +-45 deg in the x-y plane, k1=1, k2=10; u = alpha grad(psi),
   psi = sin(pi x) sin(pi y) sin(pi z) / pi, alpha such that max |J - 1| = 0.05 for the
   continuous field; du ~ N(0,1) (seed 4); no constraints.
+
+General meshes (connectivity input): ``lattice_as_hex`` writes a lattice as vertex list, cell
+corner lists and face boundary ids, optionally with renumbered vertices, shuffled cells and each
+cell's local orientation turned by one of the 24 rotations of the cube (seeded); ``ogrid_cylinder``
+is a genuinely unstructured mesh (an O-grid of a disk, corner vertices of valence 3, extruded
+along z) with curved cells on the outer circle. Curved cells are described by their map sampled at
+the (g+1)^3 equispaced points (i/g, j/g, k/g) of the reference cell (``*_geometry_nodes``).
 """
 import functools
 
@@ -220,3 +227,182 @@ def random_direction(n_nodes, seed, mask=None):
     if mask is not None:
         du[:, mask] = 0.0
     return du
+
+
+# ----------------------------------------------------------------------------------------------
+# General (connectivity) meshes and curved cells
+# ----------------------------------------------------------------------------------------------
+def _cube_rotations():
+    """The 24 rotations of the reference cube as signed permutation matrices (det +1)."""
+    import itertools
+    out = []
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product((1, -1), repeat=3):
+            R = np.zeros((3, 3), dtype=np.int64)
+            for r in range(3):
+                R[r, perm[r]] = signs[r]
+            if round(np.linalg.det(R)) == 1:
+                out.append(R)
+    return out
+
+
+def _rotated_index(R, m):
+    """For a cell whose local points form an (m+1)^3 lattice (x fastest), new_of_old[old index] =
+    index of the same point after turning the local frame by R (centred integer coordinates
+    u = 2 i - m are mapped by R)."""
+    idx = np.arange((m + 1) ** 3)
+    i, j, k = idx % (m + 1), (idx // (m + 1)) % (m + 1), idx // (m + 1) ** 2
+    u = np.stack([2 * i - m, 2 * j - m, 2 * k - m])
+    v = R @ u
+    ni, nj, nk = (v + m) // 2
+    return ni + (m + 1) * (nj + (m + 1) * nk)
+
+
+def _rotated_faces(R):
+    """new_face_of_old[f]: local face f = (d, side) has outward normal (2 side - 1) e_d."""
+    out = np.zeros(6, dtype=np.int64)
+    for f in range(6):
+        nrm = np.zeros(3, dtype=np.int64)
+        nrm[f // 2] = 2 * (f % 2) - 1
+        v = R @ nrm
+        d = int(np.nonzero(v)[0][0])
+        out[f] = 2 * d + (1 if v[d] > 0 else 0)
+    return out
+
+
+def scramble_hex(vertices, cells, face_bid, geom_nodes=None, geom_degree=1, seed=0, frames=None):
+    """The same mesh with renumbered vertices, cells in a random order and each cell's local frame
+    turned by a random rotation of the cube (seeded). Returns (vertices, cells, face_bid,
+    geom_nodes, frames, cell_order) with cell_order[new cell] = old cell."""
+    rng = np.random.default_rng(seed)
+    vertices = np.asarray(vertices, dtype=np.float64)
+    cells = np.asarray(cells, dtype=np.int64)
+    face_bid = np.asarray(face_bid, dtype=np.int64)
+    nv, ne = len(vertices), len(cells)
+    vperm = rng.permutation(nv)          # new id of old vertex v: vperm[v]
+    Vn = np.zeros_like(vertices)
+    Vn[vperm] = vertices
+    order = rng.permutation(ne)
+    rots = _cube_rotations()
+    Cn = np.zeros_like(cells)
+    Fn = np.zeros_like(face_bid)
+    Gn = None if geom_nodes is None else np.zeros_like(np.asarray(geom_nodes, dtype=np.float64))
+    for new, old in enumerate(order):
+        R = rots[rng.integers(len(rots))]
+        nidx = _rotated_index(R, 1)
+        Cn[new, nidx] = vperm[cells[old]]
+        Fn[new, _rotated_faces(R)] = face_bid[old]
+        if Gn is not None:
+            Gn[new, _rotated_index(R, geom_degree)] = geom_nodes[old]
+    Fr = None if frames is None else np.asarray(frames)[order]
+    return Vn, Cn, Fn, Gn, Fr, order
+
+
+def lattice_as_hex(nx, ny, nz, V, periodic=(False, False, False), faces=()):
+    """A lattice (vertices V as for the lattice meshes) as connectivity: (vertices, cells [E, 8],
+    face_bid [E, 6]) with cells in lattice order, corner a + 2b + 4c at lattice offset (a, b, c),
+    and boundary id f + 1 on the cell faces that lie on lattice boundary face f (0..5, x fastest),
+    for the faces listed (all six boundary faces when ``faces`` is None)."""
+    per = tuple(bool(x) for x in periodic)
+    Vx, Vy, Vz = (n + (0 if q else 1) for n, q in zip((nx, ny, nz), per))
+    E = nx * ny * nz
+    e = np.arange(E)
+    ex, ey, ez = e % nx, (e // nx) % ny, e // (nx * ny)
+    cells = np.zeros((E, 8), dtype=np.int64)
+    for c in range(2):
+        for b in range(2):
+            for a in range(2):
+                cells[:, a + 2 * b + 4 * c] = ((ex + a) % Vx) + Vx * (((ey + b) % Vy) + Vy * ((ez + c) % Vz))
+    fb = np.zeros((E, 6), dtype=np.int64)
+    pos = (ex, ey, ez)
+    ncell = (nx, ny, nz)
+    for f in (range(6) if faces is None else faces):
+        d, side = f // 2, f % 2
+        if per[d]:
+            continue
+        on = pos[d] == (ncell[d] - 1 if side else 0)
+        fb[on, f] = f + 1
+    return np.asarray(V, dtype=np.float64).reshape(-1, 3), cells, fb
+
+
+def tube_geometry_nodes(n_theta, n_wall, n_axial, g, r_in=1.0, wall=0.2, length=10.0, bend=1.0):
+    """The curved tube's map sampled at the (g+1)^3 equispaced points of every lattice cell:
+    [cells, (g+1)^3, 3], cells x fastest, local point i + (g+1)(j + (g+1) k) at (i/g, j/g, k/g).
+
+    Cell (ei, ej, ek) at local point (s, t, r) sits at lattice coordinates (ei + s, ej + t, ek + r):
+    angle -2 pi (ei + s) / n_theta, radius r_in + wall (ej + t) / n_wall, centreline parameter
+    length (ek + r) / n_axial (the same map as ``tube_vertices`` at the lattice vertices).
+    """
+    t1 = np.arange(g + 1) / g
+    k3, j3, i3 = np.meshgrid(t1, t1, t1, indexing="ij")
+    loc = np.stack([i3.ravel(), j3.ravel(), k3.ravel()], axis=1)       # [(g+1)^3, 3]
+    E = n_theta * n_wall * n_axial
+    e = np.arange(E)
+    ex, ey, ez = e % n_theta, (e // n_theta) % n_wall, e // (n_theta * n_wall)
+    th = -2.0 * np.pi * (ex[:, None] + loc[None, :, 0]) / n_theta
+    rr = r_in + wall * (ey[:, None] + loc[None, :, 1]) / n_wall
+    sa = length * (ez[:, None] + loc[None, :, 2]) / n_axial
+    X = bend * np.sin(np.pi * sa / length) + rr * np.cos(th)
+    Y = rr * np.sin(th)
+    return np.stack([X, Y, sa], axis=-1)
+
+
+def ogrid_cylinder(m, nz, radius=1.0, inner=0.4, height=1.0, g=1, bottom_bid=1, side_bid=2, top_bid=3):
+    """An O-grid of the disk of the given radius extruded over [0, height]: a central square
+    [-inner, inner]^2 of m x m cells and four blocks of m x m cells between its sides and the circle
+    (radial lines blended linearly from the square's side to the arc), nz layers along z. The
+    square's corners are vertices of valence 3 in each layer, so the mesh is not a lattice.
+
+    Returns (vertices, cells [E, 8], face_bid [E, 6], geom_nodes [E, (g+1)^3, 3]): every cell
+    right-handed, corner a + 2b + 4c at its local (a, b, c); boundary ids on the bottom (z = 0),
+    the curved side and the top; the map of each cell sampled at its equispaced points of degree g
+    (the blocks' arcs are then curved for g > 1; g = 1 gives the vertices).
+    """
+    a = inner
+
+    def block_map(b, u, v):
+        # (u, v) in [0,1]^2 of block b -> (x, y); b = 0 square, 1..4 the blocks east, north, west, south
+        if b == 0:
+            return -a + 2 * a * u, -a + 2 * a * v
+        th0 = -0.25 * np.pi + 0.5 * np.pi * (b - 1)
+        th = th0 + 0.5 * np.pi * v
+        # inner side of the square under the arc, running counter-clockwise
+        c, s_ = np.cos(th0 + 0.25 * np.pi), np.sin(th0 + 0.25 * np.pi)   # outward normal of the side
+        tx, ty = -s_, c                                                   # counter-clockwise tangent
+        px = a * c + a * (2 * v - 1) * tx
+        py = a * s_ + a * (2 * v - 1) * ty
+        qx, qy = radius * np.cos(th), radius * np.sin(th)
+        return (1 - u) * px + u * qx, (1 - u) * py + u * qy
+
+    t1 = np.arange(g + 1) / g
+    kk, jj, ii = np.meshgrid(t1, t1, t1, indexing="ij")
+    loc = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1)
+    corner = np.array([[a_, b_, c_] for c_ in (0, 1) for b_ in (0, 1) for a_ in (0, 1)], dtype=np.float64)
+    geo, corners, fbs = [], [], []
+    for kz in range(nz):
+        for b in range(5):
+            for j in range(m):
+                for i in range(m):
+                    def pts(L):
+                        u = (i + L[:, 0]) / m
+                        v = (j + L[:, 1]) / m
+                        x, y = block_map(b, u, v)
+                        z = height * (kz + L[:, 2]) / nz
+                        return np.stack([x, y, z], axis=1)
+                    geo.append(pts(loc))
+                    corners.append(pts(corner))
+                    fb = np.zeros(6, dtype=np.int64)
+                    if kz == 0:
+                        fb[4] = bottom_bid
+                    if kz == nz - 1:
+                        fb[5] = top_bid
+                    if b > 0 and i == m - 1:
+                        fb[1] = side_bid
+                    fbs.append(fb)
+    C = np.array(corners)                                                 # [E, 8, 3]
+    # vertices: corner positions merged where they coincide (to 1e-9)
+    key = np.round(C.reshape(-1, 3) / (1e-9 * max(radius, height)))
+    _, first, inv = np.unique(key, axis=0, return_index=True, return_inverse=True)
+    verts = C.reshape(-1, 3)[first]
+    cells = inv.reshape(-1, 8)
+    return verts, cells, np.array(fbs), np.array(geo)
