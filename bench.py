@@ -538,27 +538,35 @@ TUBE_MAT = dict(law="fiber", mu=2.0, kappa=3084.3 * TISSUE_SCALE, k1=1.4 * TISSU
 TUBE_FIBRES = dict(phi_deg=27.47, dispersion="none (H = M M)")
 
 
-def tube_levels(hx, workloads, cells, degrees):
+def tube_levels(hx, workloads, cells, degrees, geom_degree):
     """Operators of the fibre-reinforced curved tube (periodic circumference, both ends clamped),
-    one per degree, with the circumferential/axial/radial frame of every cell."""
+    one per degree, with the circumferential/axial/radial frame of every cell. Every cell is curved:
+    its map is the tube's, sampled at the cell's equispaced points of degree geom_degree."""
     import math
-    V = workloads.tube_vertices(*cells, **TUBE)
+    G = workloads.tube_geometry_nodes(*cells, geom_degree, **TUBE)
     frames = workloads.tube_frames(*cells, length=TUBE["length"], bend=TUBE["bend"])
     _, _, M4, M6 = hx.fiber_structure(1.0, 1.0, math.radians(TUBE_FIBRES["phi_deg"]))
     H4, H6 = np.outer(M4, M4), np.outer(M6, M6)
-    return [hx.Operator(*cells, V, p, H4=H4, H6=H6, M4=M4, M6=M6, dirichlet_faces=(4, 5),
-                        periodic=(True, False, False), frames=frames, **TUBE_MAT) for p in degrees]
+    ops = [hx.Operator(*cells, None, p, H4=H4, H6=H6, M4=M4, M6=M6, dirichlet_faces=(4, 5),
+                       periodic=(True, False, False), frames=frames, geom_degree=geom_degree, geom_nodes=G,
+                       **TUBE_MAT) for p in degrees]
+    del G
+    return ops
 
 
 def tube_hierarchy(hx, workloads, cells, degrees):
     """Degree levels on the tube lattice, then degree-1 levels with the wall and axial cell counts
     halved while both allow it (the circumference keeps its cells, so the coarse lattices trace
-    the same circular section); the last level is solved densely."""
-    ops = tube_levels(hx, workloads, cells, degrees)
+    the same circular section); the last level is solved densely. The finest level is
+    isoparametric (geometry of its own degree); every coarser level keeps that geometry degree,
+    so the degree levels see exactly the finest level's map and the lattice levels the tube's map
+    at their own points."""
+    g = degrees[0]
+    ops = tube_levels(hx, workloads, cells, degrees, g)
     nx, ny, nz = cells
     while ny > 1 and ny % 2 == 0 and nz % 2 == 0:
         ny, nz = ny // 2, nz // 2
-        ops += tube_levels(hx, workloads, (nx, ny, nz), (1,))
+        ops += tube_levels(hx, workloads, (nx, ny, nz), (1,), g)
     return ops
 
 
@@ -587,7 +595,8 @@ def mg_study(hx, workloads, torch, dev, timer, cells=(16, 8, 200), degrees=(6, 3
     b = rng.standard_normal(n)
     b[mask] = 0.0
     bd = torch.tensor(b, dtype=torch.float64, device=dev)
-    out = {"cells": list(cells), "levels": [[op.p, op.num_cells, op.num_dofs] for op in ops]}
+    out = {"cells": list(cells), "levels": [[op.p, op.num_cells, op.num_dofs] for op in ops],
+           "geometry": f"isoparametric: every level's cells map by the tube's map at degree {degrees[0]}"}
     for use_graph, prec in ((True, "fp32"), (False, "fp32"), (True, "fp32_bf16")):
         mg = hx.Multigrid(ops, precision=prec, use_graph=use_graph, level_mode="auto")
         t0 = time.perf_counter()
@@ -635,6 +644,7 @@ def newton_study(hx, workloads, torch, dev, cells=(32, 16, 400), degrees=(4, 2, 
     f = ops[0].surface_load(2, pressure)   # inner wall: lattice face -y
     fd = torch.tensor(f.reshape(-1), dtype=torch.float64, device=dev)
     out = {"cells": list(cells), "levels": [[op.p, op.num_cells, op.num_dofs] for op in ops],
+           "geometry": f"isoparametric: every level's cells map by the tube's map at degree {degrees[0]}",
            "dofs": ops[0].num_dofs, "pressure": pressure, "material": dict(TUBE_MAT, **TUBE_FIBRES),
            "load_steps": load_steps, "newton_rel_tol": rel_tol, "krylov_rel_tol": krylov_rel_tol}
     sols = {}

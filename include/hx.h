@@ -20,17 +20,31 @@
  *
  * Conventions shared by all calls
  * -------------------------------
- * Mesh: a structured nx x ny x nz lattice of hexahedra with given vertex positions (interior
- * vertices may be perturbed; each lattice direction may be periodic). Cells are numbered
- * e = ex + nx*(ey + ny*ez). The geometry of a cell is the trilinear map of its 8 vertices.
+ * Meshes (the domain Omega0 of Problem 2.1 in Section 2, cut into hexahedra), in two forms:
+ *   - hx_setup: a general conforming mesh of hexahedra given by connectivity (vertex ids of each
+ *     cell's 8 corners) with boundary ids on the cell faces;
+ *   - hx_setup_lattice: a structured nx x ny x nz lattice (cells e = ex + nx*(ey + ny*ez)),
+ *     each lattice direction optionally periodic; the fast case, addressed by index arithmetic.
+ * The geometry of a cell is the trilinear map of its 8 vertices, or a polynomial map of degree g
+ * given by its values at the (g+1)^3 equispaced points (i/g, j/g, k/g) of the reference cell
+ * [0,1]^3, local point index i + (g+1)(j + (g+1)k) (curved cells, as high-order mesh files
+ * describe them; g = p is the isoparametric case). Corner a + 2b + 4c of a cell is its reference
+ * corner (a, b, c), and every cell must be positively oriented (det J0 > 0 at its Gauss points).
  *
- * Nodes: the lattice of Gauss-Lobatto points of degree p, N_d = n_d*p (+1 if direction d is not
- * periodic) points per direction, node = I + N_x*(J + N_y*K). Quadrature: (p+1)^3 Gauss points.
+ * Nodes: the Gauss-Lobatto points of degree p in every cell, shared between cells along common
+ * vertices, edges and faces. Lattice: N_d = n_d*p (+1 if direction d is not periodic) points per
+ * direction, node = I + N_x*(J + N_y*K). General mesh: first-touch order - cells in order, each
+ * cell's local nodes (i, j, k) with i fastest, a node numbered where it is first met; which local
+ * nodes coincide is decided by the vertex ids of the vertex, edge or face they lie on, whatever
+ * the cells' local orientations (meshes in which two distinct edges join the same two vertices,
+ * or two distinct faces the same four, are outside this contract). Quadrature: (p+1)^3 Gauss
+ * points per cell.
  *
  * Vectors: device arrays in structure-of-arrays layout [3][n_nodes] (DoF index c*n_nodes+node),
  * contiguous, owned by the caller. FP64 (double) unless a call says otherwise.
  *
- * Dirichlet: nodes on the faces selected by hx_mesh.dirichlet_faces carry homogeneous data
+ * Dirichlet: nodes on the constrained faces (lattice: hx_lattice.dirichlet_faces; general mesh:
+ * the faces whose boundary id is in hx_options.dirichlet_bid_mask) carry homogeneous data
  * (the test space H^1_0 of Problems 2.1/2.2). hx_residual writes 0 on constrained rows;
  * hx_apply_tangent treats du as 0 on constrained DoFs for the free rows and writes dst = du on
  * constrained rows (operator P_f K P_f + P_c, symmetric).
@@ -44,7 +58,8 @@
  * element kernel writes each cell's element vector into a per-context buffer in which every cell
  * owns its own (p+1)^3 brick; a node kernel then adds, in a fixed order, the bricks of the cells
  * that share each node and writes every row of the output, the constrained rows included. No
- * atomics are used, so repeated calls give bit-identical results.
+ * atomics are used, so repeated calls give bit-identical results. (General meshes read each
+ * cell's nodes from an int32 map and each node's brick entries from a list built at setup.)
  */
 #ifndef HX_H
 #define HX_H
@@ -107,21 +122,45 @@ typedef enum {
   HX_FP32_FP16DATA = 3
 } hx_precision;
 
+/* A general conforming mesh of hexahedra (Section 2: the domain Omega0 and its boundary parts;
+ * Section 5: the geometry J0 enters every stored set). All arrays are HOST arrays copied by
+ * hx_setup; the caller keeps ownership. */
+typedef struct {
+  int64_t n_vertices, n_cells;  /* n_cells >= 1; every cell's corners are 8 distinct vertex ids */
+  const double* vertices;       /* [n_vertices][3] */
+  const int64_t* cells;         /* [n_cells][8] vertex ids, corner a + 2b + 4c at reference corner
+                                   (a, b, c) */
+  const uint8_t* face_bid;      /* [n_cells][6] or NULL: boundary id of each local face
+                                   (-x, +x, -y, +y, -z, +z of the reference cell), 0 = none,
+                                   1..31 may be constrained (hx_options.dirichlet_bid_mask) and
+                                   carry pressure loads (hx_surface_load) */
+  int32_t geom_degree;          /* g in [1, 8]: degree of every cell's map */
+  const double* geom_nodes;     /* [n_cells][(g+1)^3][3] or NULL (only for g = 1: the trilinear
+                                   map of the vertices): each cell's map at its equispaced points */
+  const double* frames;         /* [n_cells][3][3] or NULL: local fibre frames, as for lattices */
+} hx_mesh;
+
+/* A structured lattice of hexahedra, the fast case (index arithmetic instead of a node map). */
 typedef struct {
   int32_t nx, ny, nz;       /* cells per lattice direction, each >= 1 */
   int32_t periodic;         /* bit d (d = 0,1,2 for x,y,z) set: direction d is periodic */
   const double* vertices;   /* HOST array [V_z][V_y][V_x][3], V_d = n_d (+1 if not periodic),
-                               x fastest; copied by hx_setup */
+                               x fastest; copied by hx_setup_lattice; may be NULL when geom_nodes
+                               is given */
   uint32_t dirichlet_faces; /* bit f set: face f is constrained, f = 0..5 = -x,+x,-y,+y,-z,+z;
                                bits of periodic directions are ignored */
   const double* frames;     /* HOST array [n_cells][3][3] or NULL: per cell the rows E1, E2, E3 of
                                an orthonormal right-handed local frame (fibre frame of Section 3;
-                               cells in lattice order, x fastest); copied by hx_setup. With frames,
+                               cells in lattice order, x fastest); copied by the setup. With frames,
                                the FIBER law's H4, H6, M4, M6 are components in the local frame,
                                H_i = sum_ab H_i[a][b] E_a (x) E_b in each cell; NULL = the global
                                axes. Ignored by the other laws. A frame that is not orthonormal
                                to 1e-8 or not right-handed gives HX_E_ARG. */
-} hx_mesh;
+  int32_t geom_degree;      /* g in [1, 8] with geom_nodes, else 1 */
+  const double* geom_nodes; /* HOST array [n_cells][(g+1)^3][3] or NULL: curved cells, each cell's
+                               map at its equispaced points (cells in lattice order); NULL = the
+                               trilinear map of the vertices */
+} hx_lattice;
 
 /* Material parameters (Section 3). cNH uses mu, lambda with Psi = mu/2 (I1 - 3 - 2 ln J) +
  * lambda ln^2 J. iNH uses mu, kappa with Psi = mu/2 (J^-2/3 I1 - 3) + kappa/4 (J^2 - 1 - 2 ln J).
@@ -136,20 +175,39 @@ typedef struct {
 } hx_material;
 
 typedef struct {
-  int32_t jpow_newton_iters; /* FP32 arithmetic: J^-2/3 by this many Newton steps from x0 = 1
-                                (Algorithm 2, Section 4), accurate only near J = 1;
-                                0 = cube root (the default, also with opt == NULL). FP64
-                                always uses the cube root. */
-  int32_t reserved[7];       /* must be zero */
+  int32_t jpow_newton_iters;   /* FP32 arithmetic: J^-2/3 by this many Newton steps from x0 = 1
+                                  (Algorithm 2, Section 4), accurate only near J = 1;
+                                  0 = cube root (the default, also with opt == NULL). FP64
+                                  always uses the cube root. */
+  uint32_t dirichlet_bid_mask; /* hx_setup: bit b set (b = 1..31) = the faces with boundary id b
+                                  are constrained (homogeneous Dirichlet data, Problems 2.1/2.2);
+                                  bit 0 must be clear; ignored by hx_setup_lattice */
+  int32_t reserved[6];         /* must be zero */
 } hx_options;
 
-/* Builds a context: copies the mesh to the device, sets up the 1D basis tables for degree p,
- * checks det J0 > 0 at every Gauss point of every cell (HX_E_INVERTED otherwise).
- * p in [1, 6]. opt may be NULL (defaults). On success *out owns device memory until
- * hx_destroy, among it the element-vector buffer of 24 * n_cells * (p+1)^3 bytes. The current
- * HIP device at the time of the call is the context's device. */
+/* Builds a context on a general hexahedral mesh for the residual and the linearised operator of
+ * Section 2 (Problem 2.1: find u with r(v, u) = 0 for all v in H^1_0; Problem 2.2: Newton steps
+ * with the directional derivative), discretised with Q_p Lagrange elements on the Gauss-Lobatto
+ * points and (p+1)^3 Gauss points per cell (Section 6).
+ * Numbers the nodes (first-touch order, header preamble), builds the int32 cell -> node map and
+ * the node -> element-vector lists of the assembly, and stores J0^-1 and w det J0 of every Gauss
+ * point (Section 5: J0 is part of every stored set), FP64 and FP32.
+ * p in [1, 6]. opt may be NULL (defaults: no constraints). Errors: HX_E_ARG for NULL arrays, a
+ * vertex id out of range or repeated within a cell, non-finite coordinates, g out of [1, 8],
+ * bit 0 of the mask, more than 2^31 - 1 nodes or cells * (p+1)^3; HX_E_INVERTED if det J0 <= 0
+ * at some Gauss point; HX_E_NOMEM, HX_E_HIP. On success *out owns device memory until hx_destroy,
+ * among it the element-vector buffer of 24 * n_cells * (p+1)^3 bytes (rounded up to whole
+ * workgroups of cells). The current HIP device at the time of the call is the context's device.
+ * General-mesh contexts have no multigrid (hx_mg_create returns HX_E_UNSUPPORTED). */
 hx_status hx_setup(const hx_mesh* mesh, int32_t p, const hx_material* mat,
                    const hx_options* opt, hx_ctx* out);
+
+/* The same for a structured lattice (the fast case: nodes by index arithmetic, trilinear
+ * geometry formed from the vertices at every Gauss point, or, with geom_nodes, stored per Gauss
+ * point like hx_setup's). Checks det J0 > 0 at every Gauss point of every cell (HX_E_INVERTED
+ * otherwise); HX_E_ARG also for geom_degree out of [1, 8] or > 1 without geom_nodes. */
+hx_status hx_setup_lattice(const hx_lattice* mesh, int32_t p, const hx_material* mat,
+                           const hx_options* opt, hx_ctx* out);
 
 /* Frees every device and host resource of the context. NULL is accepted. */
 hx_status hx_destroy(hx_ctx ctx);
@@ -159,8 +217,10 @@ int64_t hx_num_dofs(hx_ctx ctx);
 int64_t hx_num_nodes(hx_ctx ctx);
 int64_t hx_num_cells(hx_ctx ctx);
 
-/* Writes the node positions, HOST array [n_nodes][3]: the trilinear map of the cell with lattice
- * index min(I / p, n_d - 1) per direction, at the Gauss-Lobatto point of the local index. */
+/* Writes the node positions, HOST array [n_nodes][3]: the map of the node's owning cell at the
+ * Gauss-Lobatto point of its local index; the owning cell is, on a lattice, the cell with lattice
+ * index min(I / p, n_d - 1) per direction, on a general mesh the cell where the node is first
+ * met. */
 hx_status hx_node_coords(hx_ctx ctx, double* host_xyz);
 
 /* Writes the constraint mask, HOST array [n_nodes] of 0/1. */
@@ -180,9 +240,14 @@ hx_status hx_residual(hx_ctx ctx, const double* u, double* r, void* stream);
 hx_status hx_update_linearization(hx_ctx ctx, const double* u, hx_storage mode,
                                   hx_precision prec, void* stream);
 
-/* dst = K~(u_k) du with the linearisation of the slot selected by prec (HX_FP64: double du and
- * dst; any FP32 value: float du and dst, data as last stored in the FP32 slot). du and dst are
- * device arrays [3][n_nodes] and must not alias. HX_E_STATE if that slot was never updated. */
+/* dst = K~(u_k) du: the linearised operator of Problem 2.2 (Section 2, the directional derivative
+ * (Grad v, Grad du S + F D_u S) of the residual), evaluated matrix-free by sum factorisation
+ * (Section 6) from the data of the last linearisation update (Section 5, Algorithm 1), with the
+ * slot selected by prec (HX_FP64: double du and dst; any FP32 value: float du and dst, data as
+ * last stored in the FP32 slot). du and dst are device arrays [3][n_nodes] owned by the caller
+ * and must not alias. Constrained rows: dst = du (identity rows and columns). Allocates nothing;
+ * asynchronous on the stream. HX_E_STATE if that slot was never updated; HX_E_ARG for NULL or
+ * aliasing pointers or an unknown precision; HX_E_HIP if a launch fails. */
 hx_status hx_apply_tangent(hx_ctx ctx, const void* du, void* dst, hx_precision prec,
                            void* stream);
 
@@ -314,9 +379,12 @@ typedef struct {
 hx_status hx_newton_solve(hx_mg mg, double* u, const double* f_ext, const hx_newton_opts* opt,
                           hx_newton_report* report, void* stream);
 
-/* Host helper: dead-load pressure on boundary face `face` (0..5 = -x,+x,-y,+y,-z,+z):
- * f_(c,a) = -p int_face phi_a N_c dA with N the outward unit normal of the reference body
- * (Section 2, Neumann term of the residual). f: HOST array [3][n_nodes], overwritten. */
+/* Host helper: dead-load pressure (Section 2, Neumann term of the residual):
+ * f_(c,a) = -p int phi_a N_c dA with N the outward unit normal of the reference body, over the
+ * lattice boundary face `face` (0..5 = -x,+x,-y,+y,-z,+z) of a lattice context, or over every
+ * cell face with boundary id `face` (1..255) of a general-mesh context; (p+1)^2 Gauss points per
+ * cell face of the cell's map (trilinear or curved). f: HOST array [3][n_nodes], overwritten.
+ * HX_E_ARG for a face of a periodic direction or an id out of range. */
 hx_status hx_surface_load(hx_ctx ctx, int32_t face, double pressure, double* f);
 
 /* ------------------------------------------------------------------------------------------

@@ -33,10 +33,18 @@ class HxError(RuntimeError):
         self.name = STATUS.get(status, str(status))
 
 
-class _Mesh(ctypes.Structure):
+class _Lattice(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("periodic", ctypes.c_int32), ("vertices", ctypes.POINTER(ctypes.c_double)),
-                ("dirichlet_faces", ctypes.c_uint32), ("frames", ctypes.POINTER(ctypes.c_double))]
+                ("dirichlet_faces", ctypes.c_uint32), ("frames", ctypes.POINTER(ctypes.c_double)),
+                ("geom_degree", ctypes.c_int32), ("geom_nodes", ctypes.POINTER(ctypes.c_double))]
+
+
+class _Mesh(ctypes.Structure):
+    _fields_ = [("n_vertices", ctypes.c_int64), ("n_cells", ctypes.c_int64),
+                ("vertices", ctypes.POINTER(ctypes.c_double)), ("cells", ctypes.POINTER(ctypes.c_int64)),
+                ("face_bid", ctypes.POINTER(ctypes.c_uint8)), ("geom_degree", ctypes.c_int32),
+                ("geom_nodes", ctypes.POINTER(ctypes.c_double)), ("frames", ctypes.POINTER(ctypes.c_double))]
 
 
 class _Material(ctypes.Structure):
@@ -47,7 +55,8 @@ class _Material(ctypes.Structure):
 
 
 class _Options(ctypes.Structure):
-    _fields_ = [("jpow_newton_iters", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+    _fields_ = [("jpow_newton_iters", ctypes.c_int32), ("dirichlet_bid_mask", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class _MgOptions(ctypes.Structure):
@@ -79,6 +88,8 @@ def _load():
     sig = {
         "hx_setup": (ctypes.c_int, [ctypes.POINTER(_Mesh), ctypes.c_int32, ctypes.POINTER(_Material),
                                     ctypes.POINTER(_Options), ctypes.POINTER(vp)]),
+        "hx_setup_lattice": (ctypes.c_int, [ctypes.POINTER(_Lattice), ctypes.c_int32, ctypes.POINTER(_Material),
+                                            ctypes.POINTER(_Options), ctypes.POINTER(vp)]),
         "hx_destroy": (ctypes.c_int, [vp]),
         "hx_num_dofs": (i64, [vp]),
         "hx_num_nodes": (i64, [vp]),
@@ -190,34 +201,31 @@ def _stream_handle(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-class Operator:
+def _frames_arg(frames, n_cells):
+    if frames is None:
+        return None
+    fr = np.ascontiguousarray(frames, dtype=np.float64)
+    if fr.shape != (n_cells, 3, 3):
+        raise ValueError("frames must have shape [n_cells, 3, 3]")
+    return fr
+
+
+def _geom_arg(geom_nodes, geom_degree, n_cells):
+    if geom_nodes is None:
+        if int(geom_degree) != 1:
+            raise ValueError("geom_degree > 1 needs geom_nodes")
+        return None
+    g = int(geom_degree)
+    G = np.ascontiguousarray(geom_nodes, dtype=np.float64)
+    if G.shape != (n_cells, (g + 1) ** 3, 3):
+        raise ValueError(f"geom_nodes must have shape [{n_cells}, {(g + 1) ** 3}, 3]")
+    return G
+
+
+class _Context:
     """A context of the library: mesh, degree, material; owns device memory until close()."""
 
-    def __init__(self, nx, ny, nz, vertices, p, law="cnh", mu=1.0, lam=0.0, kappa=0.0, k1=0.0,
-                 k2=0.0, H4=None, H6=None, M4=None, M6=None, dirichlet_faces=(),
-                 periodic=(False, False, False), jpow_newton_iters=0, frames=None):
-        """frames: optional [n_cells, 3, 3] local fibre frames (rows E1, E2, E3); H4..M6 are then
-        components in each cell's frame."""
-        V = np.ascontiguousarray(vertices, dtype=np.float64)
-        vdims = [int(n) + (0 if periodic[d] else 1) for d, n in enumerate((nx, ny, nz))]
-        if V.size != 3 * vdims[0] * vdims[1] * vdims[2]:
-            raise ValueError(f"vertices must hold 3 * {vdims[0]} * {vdims[1]} * {vdims[2]} values for this "
-                             f"lattice and periodicity, got {V.size}")
-        self._vert = V
-        fr = None
-        if frames is not None:
-            fr = np.ascontiguousarray(frames, dtype=np.float64)
-            if fr.shape != (int(nx) * int(ny) * int(nz), 3, 3):
-                raise ValueError("frames must have shape [n_cells, 3, 3]")
-        self._frames = fr
-        mesh = _Mesh(int(nx), int(ny), int(nz),
-                     int(sum(1 << d for d in range(3) if periodic[d])), _dptr(V),
-                     int(sum(1 << f for f in dirichlet_faces)), None if fr is None else _dptr(fr))
-        mat = _material(law, mu, lam, kappa, k1, k2, H4, H6, M4, M6)
-        opt = _Options()
-        opt.jpow_newton_iters = int(jpow_newton_iters)
-        ctx = ctypes.c_void_p()
-        _check(lib.hx_setup(ctypes.byref(mesh), int(p), ctypes.byref(mat), ctypes.byref(opt), ctypes.byref(ctx)))
+    def _finish(self, ctx, p):
         self.ctx = ctx
         self.p = int(p)
         self.num_nodes = int(lib.hx_num_nodes(ctx))
@@ -288,10 +296,84 @@ class Operator:
         return MODE_NAMES[best.value], {"none": ms[0], "finv_j": ms[1], "tangent": ms[2], "spatial": ms[3]}
 
     def surface_load(self, face, pressure):
-        """Dead-load pressure vector on a boundary face, host array (3, n_nodes)."""
+        """Dead-load pressure vector on a lattice boundary face (0..5) or, on a general mesh, on the
+        faces with boundary id ``face``; host array (3, n_nodes)."""
         out = np.zeros(3 * self.num_nodes)
         _check(lib.hx_surface_load(self.ctx, int(face), float(pressure), _dptr(out)), self.ctx)
         return out.reshape(3, self.num_nodes)
+
+
+class Operator(_Context):
+    """A context on a structured lattice (hx_setup_lattice)."""
+
+    def __init__(self, nx, ny, nz, vertices, p, law="cnh", mu=1.0, lam=0.0, kappa=0.0, k1=0.0,
+                 k2=0.0, H4=None, H6=None, M4=None, M6=None, dirichlet_faces=(),
+                 periodic=(False, False, False), jpow_newton_iters=0, frames=None, geom_degree=1,
+                 geom_nodes=None):
+        """frames: optional [n_cells, 3, 3] local fibre frames (rows E1, E2, E3); H4..M6 are then
+        components in each cell's frame. geom_nodes: optional [n_cells, (g+1)^3, 3] curved cells
+        (each cell's map at its equispaced points), g = geom_degree; the vertices may then be None."""
+        n_cells = int(nx) * int(ny) * int(nz)
+        G = _geom_arg(geom_nodes, geom_degree, n_cells)
+        V = None
+        if vertices is not None:
+            V = np.ascontiguousarray(vertices, dtype=np.float64)
+            vdims = [int(n) + (0 if periodic[d] else 1) for d, n in enumerate((nx, ny, nz))]
+            if V.size != 3 * vdims[0] * vdims[1] * vdims[2]:
+                raise ValueError(f"vertices must hold 3 * {vdims[0]} * {vdims[1]} * {vdims[2]} values for this "
+                                 f"lattice and periodicity, got {V.size}")
+        elif G is None:
+            raise ValueError("a lattice needs vertices or geom_nodes")
+        fr = _frames_arg(frames, n_cells)
+        self._keep = (V, G, fr)
+        mesh = _Lattice(int(nx), int(ny), int(nz),
+                        int(sum(1 << d for d in range(3) if periodic[d])), None if V is None else _dptr(V),
+                        int(sum(1 << f for f in dirichlet_faces)), None if fr is None else _dptr(fr),
+                        int(geom_degree), None if G is None else _dptr(G))
+        mat = _material(law, mu, lam, kappa, k1, k2, H4, H6, M4, M6)
+        opt = _Options()
+        opt.jpow_newton_iters = int(jpow_newton_iters)
+        ctx = ctypes.c_void_p()
+        _check(lib.hx_setup_lattice(ctypes.byref(mesh), int(p), ctypes.byref(mat), ctypes.byref(opt),
+                                    ctypes.byref(ctx)))
+        self._finish(ctx, p)
+
+
+class HexOperator(_Context):
+    """A context on a general hexahedral mesh given by connectivity (hx_setup)."""
+
+    def __init__(self, vertices, cells, p, face_bid=None, dirichlet_bids=(), geom_degree=1, geom_nodes=None,
+                 law="cnh", mu=1.0, lam=0.0, kappa=0.0, k1=0.0, k2=0.0, H4=None, H6=None, M4=None, M6=None,
+                 jpow_newton_iters=0, frames=None):
+        """vertices [V, 3]; cells [E, 8] vertex ids (corner a + 2b + 4c at reference corner (a, b, c));
+        face_bid [E, 6] boundary ids (0 none, 1..31 may be constrained) or None; the faces whose id is
+        in dirichlet_bids are constrained; geom_nodes [E, (g+1)^3, 3] curved cells or None."""
+        V = np.ascontiguousarray(vertices, dtype=np.float64).reshape(-1, 3)
+        C = np.ascontiguousarray(cells, dtype=np.int64).reshape(-1, 8)
+        n_cells = C.shape[0]
+        F = None
+        if face_bid is not None:
+            F = np.ascontiguousarray(face_bid, dtype=np.uint8).reshape(-1, 6)
+            if F.shape[0] != n_cells:
+                raise ValueError("face_bid must have shape [n_cells, 6]")
+        G = _geom_arg(geom_nodes, geom_degree, n_cells)
+        fr = _frames_arg(frames, n_cells)
+        self._keep = (V, C, F, G, fr)
+        mesh = _Mesh(V.shape[0], n_cells, _dptr(V), C.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                     None if F is None else F.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), int(geom_degree),
+                     None if G is None else _dptr(G), None if fr is None else _dptr(fr))
+        mat = _material(law, mu, lam, kappa, k1, k2, H4, H6, M4, M6)
+        opt = _Options()
+        opt.jpow_newton_iters = int(jpow_newton_iters)
+        mask = 0
+        for b in dirichlet_bids:
+            if not 1 <= int(b) <= 31:
+                raise ValueError("constrained boundary ids must be in [1, 31]")
+            mask |= 1 << int(b)
+        opt.dirichlet_bid_mask = mask
+        ctx = ctypes.c_void_p()
+        _check(lib.hx_setup(ctypes.byref(mesh), int(p), ctypes.byref(mat), ctypes.byref(opt), ctypes.byref(ctx)))
+        self._finish(ctx, p)
 
 
 def _check_mg(status, mg):

@@ -1,5 +1,5 @@
-"""Builds libhx.so for gfx950 in-tree: one translation unit per polynomial degree plus the host
-runtime, compiled in parallel with hipcc and linked into paper_2408_12479_amd/libhx.so."""
+"""Builds libhx.so for gfx950 in-tree: one translation unit per polynomial degree and mesh topology
+plus the host runtime, compiled in parallel with hipcc and linked into paper_2408_12479_amd/libhx.so."""
 import concurrent.futures as cf
 import os
 import shutil
@@ -13,6 +13,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhx.so")
 DEGREES = range(1, 7)
+# mesh topologies: lattice of trilinear cells, lattice with stored geometry, general mesh
+TOPOLOGIES = range(3)
 
 ARCH = "gfx950"
 FLAGS = [
@@ -44,14 +46,18 @@ def build(jobs=None, verbose=False):
     hipcc = _hipcc()
     units = []
     for p in DEGREES:
-        units.append(([hipcc] + FLAGS + [f"-DHX_DEGREE={p}", "-c", os.path.join(CSRC, "hx_degree.hip"),
-                       "-o", os.path.join(BUILD, f"hx_p{p}.o")], f"p{p}"))
+        for t in TOPOLOGIES:
+            units.append(([hipcc] + FLAGS + [f"-DHX_DEGREE={p}", f"-DHX_TOPO={t}", "-c",
+                                            os.path.join(CSRC, "hx_degree.hip"),
+                           "-o", os.path.join(BUILD, f"hx_p{p}_t{t}.o")], f"p{p}/t{t}"))
     units.append(([hipcc] + FLAGS + ["-c", os.path.join(CSRC, "hx_api.hip"),
                    "-o", os.path.join(BUILD, "hx_api.o")], "api"))
     units.append(([hipcc] + FLAGS + ["-c", os.path.join(CSRC, "hx_solver.hip"),
                    "-o", os.path.join(BUILD, "hx_solver.o")], "solver"))
     units.append(([hipcc] + FLAGS + ["-c", os.path.join(CSRC, "hx_stability.hip"),
                    "-o", os.path.join(BUILD, "hx_stability.o")], "stability"))
+    units.append(([hipcc] + FLAGS + ["-c", os.path.join(CSRC, "hx_mesh.hip"),
+                   "-o", os.path.join(BUILD, "hx_mesh.o")], "mesh"))
     jobs = jobs or min(len(units), max(1, os.cpu_count() or 1), 16)
     with cf.ThreadPoolExecutor(jobs) as ex:
         futs = {ex.submit(_run, cmd): name for cmd, name in units}
@@ -61,8 +67,8 @@ def build(jobs=None, verbose=False):
                 print(f"[build] {futs[f]} done", flush=True)
                 if out.strip():
                     print(out)
-    objs = [os.path.join(BUILD, f"hx_p{p}.o") for p in DEGREES] + [
-        os.path.join(BUILD, n) for n in ("hx_api.o", "hx_solver.o", "hx_stability.o")]
+    objs = [os.path.join(BUILD, f"hx_p{p}_t{t}.o") for p in DEGREES for t in TOPOLOGIES] + [
+        os.path.join(BUILD, n) for n in ("hx_api.o", "hx_solver.o", "hx_stability.o", "hx_mesh.o")]
     tmp = LIB + ".tmp"
     _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + ["-lrocsolver", "-lrocblas"])
     os.replace(tmp, LIB)

@@ -153,15 +153,27 @@ hx_status hip_fail(hx_ctx ctx, hipError_t e, const char* what) {
 }  // namespace
 
 hipError_t hx::dispatch(int p, const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok) {
+#define HX_CASE(d)                                                       \
+  case d:                                                                \
+    switch (h.topo) {                                                    \
+      case kTopoLattice: return dispatch_p##d##_t0(op, h, s, ok);        \
+      case kTopoLatticeG: return dispatch_p##d##_t1(op, h, s, ok);       \
+      case kTopoMap: return dispatch_p##d##_t2(op, h, s, ok);            \
+      default: break;                                                    \
+    }                                                                    \
+    break;
   switch (p) {
-    case 1: return dispatch_p1(op, h, s, ok);
-    case 2: return dispatch_p2(op, h, s, ok);
-    case 3: return dispatch_p3(op, h, s, ok);
-    case 4: return dispatch_p4(op, h, s, ok);
-    case 5: return dispatch_p5(op, h, s, ok);
-    case 6: return dispatch_p6(op, h, s, ok);
-    default: *ok = false; return hipSuccess;
+    HX_CASE(1)
+    HX_CASE(2)
+    HX_CASE(3)
+    HX_CASE(4)
+    HX_CASE(5)
+    HX_CASE(6)
+    default: break;
   }
+#undef HX_CASE
+  *ok = false;
+  return hipSuccess;
 }
 
 int hx::cells_per_block(int p) {
@@ -190,7 +202,11 @@ hipError_t write_consts(int p, const HostArgs& h) {
   }
 }
 
-bool is_constrained(const Lattice& L, int64_t node) {
+}  // namespace
+
+bool hx::host_constrained(const hx_ctx_s* c, int64_t node) {
+  if (c->topo == kTopoMap) return c->cons_host[static_cast<size_t>(node)] != 0;
+  const Lattice& L = c->L;
   const int I = static_cast<int>(node % L.Nx);
   const int J = static_cast<int>((node / L.Nx) % L.Ny);
   const int K = static_cast<int>(node / (static_cast<int64_t>(L.Nx) * L.Ny));
@@ -198,6 +214,8 @@ bool is_constrained(const Lattice& L, int64_t node) {
   return ((f & 1u) && I == 0) || ((f & 2u) && I == L.Nx - 1) || ((f & 4u) && J == 0) ||
          ((f & 8u) && J == L.Ny - 1) || ((f & 16u) && K == 0) || ((f & 32u) && K == L.Nz - 1);
 }
+
+namespace {
 
 // vertex v = a + 2b + 4c of cell (ex, ey, ez)
 const double* cell_vertex(const hx_ctx_s* c, int ex, int ey, int ez, int v) {
@@ -295,6 +313,13 @@ HostArgs hx::args_for(const hx_ctx_s* c) {
   h.cblk32 = c->cblk32;
   h.fib64 = c->fib64;
   h.fib32 = c->fib32;
+  h.topo = c->topo;
+  h.map = c->map;
+  h.nptr = c->nptr;
+  h.nslot = c->nslot;
+  h.cmask = c->cmask;
+  h.geo64 = c->geo64;
+  h.geo32 = c->geo32;
   return h;
 }
 
@@ -413,30 +438,113 @@ hx_status hx_fiber_structure(double a, double b, double phi, const double* E, do
   return HX_OK;
 }
 
-hx_status hx_setup(const hx_mesh* mesh, int32_t p, const hx_material* mat, const hx_options* opt,
-                   hx_ctx* out) {
-  if (!out) return fail(nullptr, HX_E_ARG, "hx_setup: out is NULL");
-  *out = nullptr;
-  if (!mesh || !mat || !mesh->vertices) return fail(nullptr, HX_E_ARG, "hx_setup: NULL mesh, vertices or material");
-  if (p < 1 || p > kMaxDegree) return fail(nullptr, HX_E_UNSUPPORTED, "hx_setup: degree must be in [1, 6]");
-  if (mesh->nx < 1 || mesh->ny < 1 || mesh->nz < 1) return fail(nullptr, HX_E_ARG, "hx_setup: empty lattice");
-  if (mat->law != HX_LAW_CNH && mat->law != HX_LAW_INH && mat->law != HX_LAW_FIBER)
-    return fail(nullptr, HX_E_ARG, "hx_setup: unknown law");
-  if (opt) {
-    for (int i = 0; i < 7; ++i)
-      if (opt->reserved[i]) return fail(nullptr, HX_E_ARG, "hx_setup: reserved option fields must be zero");
-    if (opt->jpow_newton_iters < 0 || opt->jpow_newton_iters > 16)
-      return fail(nullptr, HX_E_ARG, "hx_setup: jpow_newton_iters out of [0, 16]");
+}  // extern "C"
+
+// Setup steps shared by the lattice and the general meshes: basis tables, device buffers, fibre
+// frames, constants, stored geometry (curved or general meshes) and the static buffer's address.
+// On failure the context is destroyed.
+hx_status hx::finish_setup(hx_ctx_s* c, const hx_material* mat, const hx_options* opt, const double* frames,
+                           hx_ctx* out) {
+  const int p = c->p;
+  HostArgs& h = c->base;
+  std::memset(&h, 0, sizeof(h));
+  h.L = c->L;
+  h.topo = c->topo;
+  basis_tables(p, h, c->gll);
+  h.mat = *mat;
+  h.jpow_iters = opt ? opt->jpow_newton_iters : 0;
+  const int64_t cells = c->L.n_cells;
+  const int64_t q = static_cast<int64_t>(p + 1) * (p + 1) * (p + 1);
+  const int64_t eb = cells_per_block(p);
+  const int64_t padded = (cells + eb - 1) / eb * eb;
+  hipError_t e;
+  if ((e = hipMalloc(&c->flag, sizeof(int))) != hipSuccess ||
+      (e = hipMalloc(&c->ework, 3 * padded * q * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc(&c->cblk64, kConstBlockBytes)) != hipSuccess ||
+      (e = hipMalloc(&c->cblk32, kConstBlockBytes)) != hipSuccess) {
+    hx_destroy(c);
+    return hip_fail(nullptr, e, "hx_setup: allocation");
   }
-  if (mesh->dirichlet_faces >> 6) return fail(nullptr, HX_E_ARG, "hx_setup: dirichlet_faces has bits above 5");
+  if ((e = hipMemset(c->flag, 0, sizeof(int))) != hipSuccess) {
+    hx_destroy(c);
+    return hip_fail(nullptr, e, "hx_setup: clear");
+  }
+  if (mat->law == HX_LAW_FIBER && frames) {
+    std::vector<double> fib;
+    if (!cell_fibers(frames, cells, *mat, fib)) {
+      hx_destroy(c);
+      return fail(nullptr, HX_E_ARG, "hx_setup: a cell frame is not orthonormal and right-handed");
+    }
+    std::vector<float> fib32(fib.begin(), fib.end());
+    if ((e = hipMalloc(&c->fib64, fib.size() * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&c->fib32, fib.size() * sizeof(float))) != hipSuccess ||
+        (e = hipMemcpy(c->fib64, fib.data(), fib.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(c->fib32, fib32.data(), fib.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) {
+      hx_destroy(c);
+      return hip_fail(nullptr, e, "hx_setup: cell frames");
+    }
+  }
+  if (c->topo != kTopoLattice) {
+    const hx_status st = build_stored_geometry(c);
+    if (st != HX_OK) {
+      const std::string msg = c->err;
+      hx_destroy(c);
+      return fail(nullptr, st, msg);
+    }
+  }
+  HostArgs ha = args_for(c);
+  if ((e = write_consts(p, ha)) != hipSuccess) {
+    hx_destroy(c);
+    return hip_fail(nullptr, e, "hx_setup: constants");
+  }
+  *out = c;
+  return HX_OK;
+}
+
+hx_status hx::setup_fail(hx_status s, const std::string& msg) { return fail(nullptr, s, msg); }
+
+bool hx::check_options(const hx_options* opt, const char* who) {
+  if (!opt) return true;
+  for (int i = 0; i < 6; ++i)
+    if (opt->reserved[i]) {
+      fail(nullptr, HX_E_ARG, std::string(who) + ": reserved option fields must be zero");
+      return false;
+    }
+  if (opt->jpow_newton_iters < 0 || opt->jpow_newton_iters > 16) {
+    fail(nullptr, HX_E_ARG, std::string(who) + ": jpow_newton_iters out of [0, 16]");
+    return false;
+  }
+  return true;
+}
+
+extern "C" {
+
+hx_status hx_setup_lattice(const hx_lattice* mesh, int32_t p, const hx_material* mat, const hx_options* opt,
+                           hx_ctx* out) {
+  if (!out) return fail(nullptr, HX_E_ARG, "hx_setup_lattice: out is NULL");
+  *out = nullptr;
+  if (!mesh || !mat) return fail(nullptr, HX_E_ARG, "hx_setup_lattice: NULL mesh or material");
+  const bool curved = mesh->geom_nodes != nullptr;
+  if (!curved && !mesh->vertices) return fail(nullptr, HX_E_ARG, "hx_setup_lattice: NULL vertices (and no geometry points)");
+  if (p < 1 || p > kMaxDegree) return fail(nullptr, HX_E_UNSUPPORTED, "hx_setup_lattice: degree must be in [1, 6]");
+  if (mesh->nx < 1 || mesh->ny < 1 || mesh->nz < 1) return fail(nullptr, HX_E_ARG, "hx_setup_lattice: empty lattice");
+  if (mat->law != HX_LAW_CNH && mat->law != HX_LAW_INH && mat->law != HX_LAW_FIBER)
+    return fail(nullptr, HX_E_ARG, "hx_setup_lattice: unknown law");
+  if (!check_options(opt, "hx_setup_lattice")) return HX_E_ARG;
+  if (mesh->dirichlet_faces >> 6) return fail(nullptr, HX_E_ARG, "hx_setup_lattice: dirichlet_faces has bits above 5");
+  if (curved && (mesh->geom_degree < 1 || mesh->geom_degree > kMaxGeomDegree))
+    return fail(nullptr, HX_E_ARG, "hx_setup_lattice: geom_degree out of [1, 8]");
+  if (!curved && mesh->geom_degree > 1)
+    return fail(nullptr, HX_E_ARG, "hx_setup_lattice: geom_degree > 1 needs geom_nodes");
 
   hx_ctx_s* c = new (std::nothrow) hx_ctx_s();
-  if (!c) return fail(nullptr, HX_E_NOMEM, "hx_setup: host allocation failed");
+  if (!c) return fail(nullptr, HX_E_NOMEM, "hx_setup_lattice: host allocation failed");
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
-    return fail(nullptr, HX_E_HIP, "hx_setup: no HIP device");
+    return fail(nullptr, HX_E_HIP, "hx_setup_lattice: no HIP device");
   }
   c->p = p;
+  c->topo = curved ? kTopoLatticeG : kTopoLattice;
   Lattice& L = c->L;
   L.nx = mesh->nx;
   L.ny = mesh->ny;
@@ -452,9 +560,10 @@ hx_status hx_setup(const hx_mesh* mesh, int32_t p, const hx_material* mat, const
   const int64_t Nz = static_cast<int64_t>(L.nz) * p + ((per & 4) ? 0 : 1);
   const int64_t nodes = Nx * Ny * Nz;
   const int64_t q = static_cast<int64_t>(p + 1) * (p + 1) * (p + 1);
-  if (cells * q > (int64_t(1) << 31) - 1 || Nx > (1 << 30) || Ny > (1 << 30) || Nz > (1 << 30)) {
+  const int64_t eb = cells_per_block(p);
+  if ((cells + eb) * q > (int64_t(1) << 31) - 1 || Nx > (1 << 30) || Ny > (1 << 30) || Nz > (1 << 30)) {
     delete c;
-    return fail(nullptr, HX_E_ARG, "hx_setup: mesh too large (cells * (p+1)^3 must fit in int32)");
+    return fail(nullptr, HX_E_ARG, "hx_setup_lattice: mesh too large (cells * (p+1)^3 must fit in int32)");
   }
   L.Nx = static_cast<int32_t>(Nx);
   L.Ny = static_cast<int32_t>(Ny);
@@ -467,62 +576,40 @@ hx_status hx_setup(const hx_mesh* mesh, int32_t p, const hx_material* mat, const
   if (per & 4) faces &= ~48u;
   L.dir_faces = faces;
 
-  HostArgs& h = c->base;
-  std::memset(&h, 0, sizeof(h));
-  h.L = L;
-  basis_tables(p, h, c->gll);
-  h.mat = *mat;
-  h.jpow_iters = opt ? opt->jpow_newton_iters : 0;
-
-  const int64_t nv = static_cast<int64_t>(L.Vx) * L.Vy * L.Vz;
-  c->vert_host.assign(mesh->vertices, mesh->vertices + 3 * nv);
-  for (double v : c->vert_host)
-    if (!std::isfinite(v)) {
+  if (curved) {
+    const int g = mesh->geom_degree;
+    c->geom_degree = g;
+    const size_t m3 = static_cast<size_t>(g + 1) * (g + 1) * (g + 1);
+    c->geom_host.assign(mesh->geom_nodes, mesh->geom_nodes + 3 * m3 * cells);
+    for (double v : c->geom_host)
+      if (!std::isfinite(v)) {
+        delete c;
+        return fail(nullptr, HX_E_ARG, "hx_setup_lattice: non-finite geometry point");
+      }
+  } else {
+    const int64_t nv = static_cast<int64_t>(L.Vx) * L.Vy * L.Vz;
+    c->vert_host.assign(mesh->vertices, mesh->vertices + 3 * nv);
+    for (double v : c->vert_host)
+      if (!std::isfinite(v)) {
+        delete c;
+        return fail(nullptr, HX_E_ARG, "hx_setup_lattice: non-finite vertex coordinate");
+      }
+    HostArgs tmp{};  // the Gauss points for the check (finish_setup fills the context's tables)
+    basis_tables(p, tmp, c->gll);
+    std::memcpy(c->base.x, tmp.x, sizeof(tmp.x));
+    if (!(min_detJ0(c) > 0.0)) {
       delete c;
-      return fail(nullptr, HX_E_ARG, "hx_setup: non-finite vertex coordinate");
+      return fail(nullptr, HX_E_INVERTED, "hx_setup_lattice: det J0 <= 0 at a Gauss point of some cell");
     }
-  if (!(min_detJ0(c) > 0.0)) {
-    delete c;
-    return fail(nullptr, HX_E_INVERTED, "hx_setup: det J0 <= 0 at a Gauss point of some cell");
-  }
-
-  hipError_t e;
-  if ((e = hipMalloc(&c->vert64, 3 * nv * sizeof(double))) != hipSuccess ||
-      (e = hipMalloc(&c->flag, sizeof(int))) != hipSuccess ||
-      (e = hipMalloc(&c->ework, 3 * cells * static_cast<int64_t>((p + 1) * (p + 1) * (p + 1)) * sizeof(double))) !=
-          hipSuccess ||
-      (e = hipMalloc(&c->cblk64, kConstBlockBytes)) != hipSuccess ||
-      (e = hipMalloc(&c->cblk32, kConstBlockBytes)) != hipSuccess) {
-    hx_destroy(c);
-    return hip_fail(nullptr, e, "hx_setup: allocation");
-  }
-  if ((e = hipMemcpy(c->vert64, c->vert_host.data(), 3 * nv * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemset(c->flag, 0, sizeof(int))) != hipSuccess) {
-    hx_destroy(c);
-    return hip_fail(nullptr, e, "hx_setup: copy");
-  }
-  if (mat->law == HX_LAW_FIBER && mesh->frames) {
-    std::vector<double> fib;
-    if (!cell_fibers(mesh->frames, cells, *mat, fib)) {
+    hipError_t e;
+    if ((e = hipMalloc(&c->vert64, 3 * nv * sizeof(double))) != hipSuccess ||
+        (e = hipMemcpy(c->vert64, c->vert_host.data(), 3 * nv * sizeof(double), hipMemcpyHostToDevice)) !=
+            hipSuccess) {
       hx_destroy(c);
-      return fail(nullptr, HX_E_ARG, "hx_setup: a cell frame is not orthonormal and right-handed");
-    }
-    std::vector<float> fib32(fib.begin(), fib.end());
-    if ((e = hipMalloc(&c->fib64, fib.size() * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc(&c->fib32, fib.size() * sizeof(float))) != hipSuccess ||
-        (e = hipMemcpy(c->fib64, fib.data(), fib.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(c->fib32, fib32.data(), fib.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) {
-      hx_destroy(c);
-      return hip_fail(nullptr, e, "hx_setup: cell frames");
+      return hip_fail(nullptr, e, "hx_setup_lattice: vertices");
     }
   }
-  HostArgs ha = args_for(c);
-  if ((e = write_consts(p, ha)) != hipSuccess) {
-    hx_destroy(c);
-    return hip_fail(nullptr, e, "hx_setup: constants");
-  }
-  *out = c;
-  return HX_OK;
+  return finish_setup(c, mat, opt, mesh->frames, out);
 }
 
 hx_status hx_destroy(hx_ctx ctx) {
@@ -538,6 +625,12 @@ hx_status hx_destroy(hx_ctx ctx) {
   if (ctx->cblk32) (void)hipFree(ctx->cblk32);
   if (ctx->fib64) (void)hipFree(ctx->fib64);
   if (ctx->fib32) (void)hipFree(ctx->fib32);
+  if (ctx->geo64) (void)hipFree(ctx->geo64);
+  if (ctx->geo32) (void)hipFree(ctx->geo32);
+  if (ctx->map) (void)hipFree(ctx->map);
+  if (ctx->nptr) (void)hipFree(ctx->nptr);
+  if (ctx->nslot) (void)hipFree(ctx->nslot);
+  if (ctx->cmask) (void)hipFree(ctx->cmask);
   (void)hipSetDevice(cur);
   delete ctx;
   return HX_OK;
@@ -551,6 +644,20 @@ hx_status hx_node_coords(hx_ctx ctx, double* xyz) {
   if (!ctx || !xyz) return fail(ctx, HX_E_ARG, "hx_node_coords: NULL argument");
   const Lattice& L = ctx->L;
   const int p = ctx->p;
+  if (ctx->topo == kTopoMap) {
+    // the map of the cell where the node is first met (cells in order, local nodes x fastest)
+    const int n = p + 1, Q = n * n * n;
+    std::vector<uint8_t> seen(static_cast<size_t>(L.n_nodes), 0);
+    for (int64_t e = 0; e < L.n_cells; ++e)
+      for (int a = 0; a < Q; ++a) {
+        const int64_t node = ctx->cell_nodes[static_cast<size_t>(e) * Q + a];
+        if (seen[node]) continue;
+        seen[node] = 1;
+        const double xi[3] = {ctx->gll[a % n], ctx->gll[(a / n) % n], ctx->gll[a / (n * n)]};
+        host_map(ctx, e, xi, xyz + 3 * node, nullptr);
+      }
+    return HX_OK;
+  }
   for (int64_t node = 0; node < L.n_nodes; ++node) {
     const int lat[3] = {static_cast<int>(node % L.Nx), static_cast<int>((node / L.Nx) % L.Ny),
                         static_cast<int>(node / (static_cast<int64_t>(L.Nx) * L.Ny))};
@@ -561,14 +668,18 @@ hx_status hx_node_coords(hx_ctx ctx, double* xyz) {
       cell[d] = std::min(lat[d] / p, nc[d] - 1);
       loc[d] = ctx->gll[lat[d] - cell[d] * p];
     }
-    trilinear(ctx, cell[0], cell[1], cell[2], loc[0], loc[1], loc[2], xyz + 3 * node);
+    if (ctx->topo == kTopoLattice)
+      trilinear(ctx, cell[0], cell[1], cell[2], loc[0], loc[1], loc[2], xyz + 3 * node);
+    else
+      host_map(ctx, cell[0] + static_cast<int64_t>(L.nx) * (cell[1] + static_cast<int64_t>(L.ny) * cell[2]), loc,
+               xyz + 3 * node, nullptr);
   }
   return HX_OK;
 }
 
 hx_status hx_constrained_mask(hx_ctx ctx, uint8_t* mask) {
   if (!ctx || !mask) return fail(ctx, HX_E_ARG, "hx_constrained_mask: NULL argument");
-  for (int64_t node = 0; node < ctx->L.n_nodes; ++node) mask[node] = is_constrained(ctx->L, node) ? 1 : 0;
+  for (int64_t node = 0; node < ctx->L.n_nodes; ++node) mask[node] = host_constrained(ctx, node) ? 1 : 0;
   return HX_OK;
 }
 
@@ -678,15 +789,23 @@ hx_status hx_update_linearization(hx_ctx ctx, const double* u, hx_storage mode, 
   return HX_OK;
 }
 
-hx_status hx_apply_tangent(hx_ctx ctx, const void* du, void* dst, hx_precision prec, void* stream) {
-  if (!ctx || !du || !dst) return fail(ctx, HX_E_ARG, "hx_apply_tangent: NULL argument");
-  if (du == dst) return fail(ctx, HX_E_ARG, "hx_apply_tangent: du and dst alias");
-  if (store_of(prec) < 0) return fail(ctx, HX_E_ARG, "hx_apply_tangent: unknown precision");
+}  // extern "C"
+
+namespace {
+
+// The apply with a given element-vector buffer (the context's, or the static one).
+// (messages are formed only on failure: the successful path allocates nothing, host or device)
+hx_status apply_with(hx_ctx ctx, const void* du, void* dst, hx_precision prec, void* stream, void* ework,
+                     const char* who) {
+  if (!ctx || !du || !dst) return fail(ctx, HX_E_ARG, std::string(who) + ": NULL argument");
+  if (du == dst) return fail(ctx, HX_E_ARG, std::string(who) + ": du and dst alias");
+  if (store_of(prec) < 0) return fail(ctx, HX_E_ARG, std::string(who) + ": unknown precision");
   const bool fp32 = prec != HX_FP64;
   const Slot& sl = ctx->slot[fp32 ? 1 : 0];
-  if (!sl.valid) return fail(ctx, HX_E_STATE, "hx_apply_tangent: no linearisation stored for this precision");
+  if (!sl.valid) return fail(ctx, HX_E_STATE, std::string(who) + ": no linearisation stored for this precision");
   hipStream_t s = static_cast<hipStream_t>(stream);
   HostArgs h = args_for(ctx);
+  h.ework = ework;
   h.in0 = du;
   h.in1 = sl.uk;
   h.out = dst;
@@ -699,9 +818,17 @@ hx_status hx_apply_tangent(hx_ctx ctx, const void* du, void* dst, hx_precision p
   HostOp op{OpKind::Apply, ctx->base.mat.law, sl.mode, sl.store, fp32};
   bool ok = false;
   const hipError_t e = dispatch(ctx->p, op, h, s, &ok);
-  if (!ok) return fail(ctx, HX_E_UNSUPPORTED, "hx_apply_tangent: combination not built");
-  if (e != hipSuccess) return hip_fail(ctx, e, "hx_apply_tangent: launch");
+  if (!ok) return fail(ctx, HX_E_UNSUPPORTED, std::string(who) + ": combination not built");
+  if (e != hipSuccess) return hip_fail(ctx, e, (std::string(who) + ": launch").c_str());
   return HX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hx_status hx_apply_tangent(hx_ctx ctx, const void* du, void* dst, hx_precision prec, void* stream) {
+  return apply_with(ctx, du, dst, prec, stream, ctx ? ctx->ework : nullptr, "hx_apply_tangent");
 }
 
 hx_status hx_autotune_storage(hx_ctx ctx, const double* u, hx_precision prec, int32_t reps,

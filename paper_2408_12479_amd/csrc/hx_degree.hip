@@ -1,5 +1,7 @@
-// Kernel instantiations and launch dispatch for one polynomial degree (HX_DEGREE, set by the
-// build). Each degree is its own translation unit so degrees compile in parallel.
+// Kernel instantiations and launch dispatch for one polynomial degree (HX_DEGREE) and one kind of
+// mesh topology (HX_TOPO: 0 lattice of trilinear cells, 1 lattice with stored geometry, 2 general
+// mesh), both set by the build. Each (degree, topology) pair is its own translation unit so that
+// they compile in parallel.
 #include <type_traits>
 
 #include "hx_kernels.hpp"
@@ -7,14 +9,20 @@
 #ifndef HX_DEGREE
 #error "HX_DEGREE must be defined"
 #endif
+#ifndef HX_TOPO
+#error "HX_TOPO must be defined"
+#endif
 
 #define HX_CAT2(a, b) a##b
 #define HX_CAT(a, b) HX_CAT2(a, b)
+#define HX_CAT4(a, b, c, d) HX_CAT(HX_CAT(a, b), HX_CAT(c, d))
+#define HX_DISPATCH_NAME(t) HX_CAT4(dispatch_p, HX_DEGREE, _t, t)
 
 namespace hx {
 namespace {
 
 constexpr int N = HX_DEGREE + 1;
+constexpr int TOPO = HX_TOPO;
 
 // Cells per workgroup: the workgroup holds EB * N^3 q-threads; chosen so that the thread count
 // is close to a multiple of the 64-wide wavefront. Q3 and Q4 take 4 cells: their pencil phases
@@ -70,6 +78,11 @@ KernelArgs<N, R> make_args(const HostArgs& h) {
     a.fib = h.fib32;
   }
   a.vert = h.vert64;
+  a.map = h.map;
+  if constexpr (std::is_same<R, double>::value)
+    a.geo = h.geo64;
+  else
+    a.geo = h.geo32;
   a.in0 = static_cast<const R*>(h.in0);
   a.in1 = static_cast<const R*>(h.in1);
   a.out = static_cast<R*>(h.out);
@@ -94,18 +107,24 @@ hipError_t launch(const HostArgs& h, hipStream_t s) {
     // stored data larger than the last-level cache: non-temporal loads (a separate instantiation,
     // since a run-time choice between the two loads is merged into one by the compiler)
     if (h.stream_qdata)
-      element_kernel<N, EB, R, KIND, MODE, LAW, S, true><<<dim3(nblk), dim3(EB * N * N * N), 0, s>>>(a);
+      element_kernel<N, EB, R, KIND, MODE, LAW, S, true, TOPO><<<dim3(nblk), dim3(EB * N * N * N), 0, s>>>(a);
     else
-      element_kernel<N, EB, R, KIND, MODE, LAW, S><<<dim3(nblk), dim3(EB * N * N * N), 0, s>>>(a);
+      element_kernel<N, EB, R, KIND, MODE, LAW, S, false, TOPO><<<dim3(nblk), dim3(EB * N * N * N), 0, s>>>(a);
   } else {
-    element_kernel<N, EB, R, KIND, MODE, LAW, S><<<dim3(nblk), dim3(EB * N * N * N), 0, s>>>(a);
+    element_kernel<N, EB, R, KIND, MODE, LAW, S, false, TOPO><<<dim3(nblk), dim3(EB * N * N * N), 0, s>>>(a);
   }
   if constexpr (KIND == 0 || KIND == 1) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // rows of the nodes on cell faces: sum of the cells' bricks; constrained rows du (apply) or 0
-    assemble_kernel<N, R><<<dim3(static_cast<unsigned>((h.L.n_nodes + 255) / 256)), dim3(256), 0, s>>>(
-        h.L, a.ework, KIND == 0 ? a.in0 : nullptr, a.out);
+    // every row: sum of the element vectors at the node; constrained rows du (apply) or 0
+    const dim3 grid(static_cast<unsigned>((h.L.n_nodes + 255) / 256));
+    if constexpr (TOPO == kTopoMap) {
+      const int64_t ES = static_cast<int64_t>(nblk) * EB * N * N * N;
+      assemble_map_kernel<R><<<grid, dim3(256), 0, s>>>(h.L.n_nodes, h.nptr, h.nslot, h.cmask, ES, a.ework,
+                                                         KIND == 0 ? a.in0 : nullptr, a.out);
+    } else {
+      assemble_kernel<N, R><<<grid, dim3(256), 0, s>>>(h.L, a.ework, KIND == 0 ? a.in0 : nullptr, a.out);
+    }
   }
   return hipGetLastError();
 }
@@ -149,6 +168,7 @@ hipError_t by_law(const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok) 
         if (op.fp32 && op.store == kStoreF32)
           return launch<float, 0, HX_STORE_FINV_J, LAW, kStoreF32>(h, s);
       }
+#if HX_TOPO != 1
       if (op.mode == HX_STORE_SPATIAL) {
         // the stored words carry the frames: one apply kernel per law family
         constexpr int AL = LAW == kFIBERC ? kFIBER : LAW;
@@ -157,6 +177,7 @@ hipError_t by_law(const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok) 
         if (op.fp32 && op.store == kStoreF32)
           return launch<float, 0, HX_STORE_SPATIAL, AL, kStoreF32>(h, s);
       }
+#endif
       break;
   }
   *ok = false;
@@ -173,6 +194,10 @@ hipError_t launch_diag(const HostArgs& h, hipStream_t s) {
   return hipGetLastError();
 }
 
+// The diagonal (multigrid on lattices) and the apply modes that never read the geometry are
+// built in the translation unit of the lattice of trilinear cells; the lattice with stored
+// geometry forwards them there (see the dispatch below), general meshes have no diagonal.
+#if HX_TOPO == 0
 hipError_t diagonal(const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok) {
   *ok = true;
   if (op.mode == HX_STORE_TANGENT) {
@@ -189,7 +214,9 @@ hipError_t diagonal(const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok
   *ok = false;
   return hipSuccess;
 }
+#endif
 
+#if HX_TOPO != 1
 // The stored-tangent apply does not depend on the law.
 hipError_t apply_tangent_mode(const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok) {
   *ok = true;
@@ -206,9 +233,11 @@ hipError_t apply_tangent_mode(const HostOp& op, const HostArgs& h, hipStream_t s
   *ok = false;
   return hipSuccess;
 }
+#endif
 
 }  // namespace
 
+#if HX_TOPO == 0
 // Cells per workgroup: the stored q-point data is laid out in blocks of this many cells.
 int HX_CAT(cells_per_block_p, HX_DEGREE)() { return Blocking<N>::EB; }
 
@@ -220,11 +249,29 @@ hipError_t HX_CAT(consts_p, HX_DEGREE)(const HostArgs& h) {
   if (e != hipSuccess) return e;
   return hipMemcpy(h.cblk32, &c32, sizeof(c32), hipMemcpyHostToDevice);
 }
+#endif
 
-hipError_t HX_CAT(dispatch_p, HX_DEGREE)(const HostOp& op, const HostArgs& h, hipStream_t s,
-                                          bool* ok) {
+hipError_t HX_DISPATCH_NAME(HX_TOPO)(const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok) {
+#if HX_TOPO == 1
+  // a lattice with stored geometry: the operations that never read the geometry are those of the
+  // lattice of trilinear cells
+  if (op.kind == OpKind::Diagonal ||
+      (op.kind == OpKind::Apply && (op.mode == HX_STORE_TANGENT || op.mode == HX_STORE_SPATIAL)))
+    return HX_DISPATCH_NAME(0)(op, h, s, ok);
+#endif
+#if HX_TOPO == 2
+  // the diagonal kernel addresses lattices only (general meshes have no multigrid)
+  if (op.kind == OpKind::Diagonal) {
+    *ok = false;
+    return hipSuccess;
+  }
+#endif
+#if HX_TOPO == 0
   if (op.kind == OpKind::Diagonal) return diagonal(op, h, s, ok);
+#endif
+#if HX_TOPO != 1
   if (op.kind == OpKind::Apply && op.mode == HX_STORE_TANGENT) return apply_tangent_mode(op, h, s, ok);
+#endif
   switch (op.law) {
     case HX_LAW_CNH: return by_law<kCNH>(op, h, s, ok);
     case HX_LAW_INH: return by_law<kINH>(op, h, s, ok);

@@ -52,12 +52,42 @@ struct Consts {
 
 constexpr size_t kConstBlockBytes = 4096;
 
+// How a context addresses its nodes and finds its geometry (a template parameter of the kernels):
+//   kTopoLattice  structured lattice, geometry = trilinear map of the 8 cell vertices, evaluated
+//                 at every q-point from the vertex lattice
+//   kTopoLatticeG structured lattice, geometry stored per q-point (curved cells)
+//   kTopoMap      general mesh: node of every gather slot from an int32 map, geometry stored per
+//                 q-point, element vectors summed per node through a node -> slot list
+enum Topo : int { kTopoLattice = 0, kTopoLatticeG = 1, kTopoMap = 2 };
+
+// Words of stored geometry per q-point: K = J0^-1 (9, row-major K[3 d + J] = dxi_d / dX_J) and
+// w_q det J0.
+constexpr int kGeoWords = 10;
+
+// Gather/store slot of thread t of a workgroup of EB cells of n^3 points: the cell le of the block
+// and the local node q. With several cells of odd n per workgroup, the cells are interleaved along
+// x (t: i = t mod n, then the cell, then j and k) so that consecutive lanes walk a whole x-row of
+// the block; otherwise t = le n^3 + q.
+__host__ __device__ inline void slot_of_thread(int n, int EB, int t, int& le, int& q) {
+  if (EB > 1 && (n & 1)) {
+    const int i = t % n;
+    const int r = t / n;
+    le = r % EB;
+    q = i + n * (r / EB);
+  } else {
+    le = t / (n * n * n);
+    q = t - le * n * n * n;
+  }
+}
+
 // Everything a kernel needs, passed by value.
 template <int N, typename R>
 struct KernelArgs {
   Lattice L;
   const Consts<N, R>* __restrict__ c;
   const double* vert;   // vertices [Vz][Vy][Vx][3] (FP64 in every arithmetic)
+  const int32_t* map;   // general meshes: node of gather slot [block][EB n^3] (~node if constrained)
+  const R* geo;         // stored geometry planes [block][kGeoWords][EB n^3] (curved or general meshes)
   const R* in0;         // gathered vector (du, or u for residual/update)
   const R* in1;         // linearisation point u_k (recompute mode)
   R* out;               // output vector (apply, residual)
@@ -93,6 +123,13 @@ struct HostOp {
 
 struct HostArgs {
   Lattice L;
+  int topo;             // Topo of the context
+  const int32_t* map;   // kTopoMap: gather slot -> node (device)
+  const int32_t* nptr;  // kTopoMap: node -> first entry of its slot list [n_nodes + 1] (device)
+  const int32_t* nslot; // kTopoMap: slot lists, increasing within a node (device)
+  const uint8_t* cmask; // kTopoMap: constrained nodes [n_nodes] (device)
+  const double* geo64;  // stored geometry planes, FP64 (kTopoLatticeG, kTopoMap)
+  const float* geo32;   // the same rounded to FP32
   double B[64], D[64], w[8], x[8];   // 1D tables, row-major N x N
   hx_material mat;
   int32_t jpow_iters;
@@ -142,11 +179,16 @@ hipError_t consts_p3(const HostArgs&);
 hipError_t consts_p4(const HostArgs&);
 hipError_t consts_p5(const HostArgs&);
 hipError_t consts_p6(const HostArgs&);
-hipError_t dispatch_p1(const HostOp&, const HostArgs&, hipStream_t, bool*);
-hipError_t dispatch_p2(const HostOp&, const HostArgs&, hipStream_t, bool*);
-hipError_t dispatch_p3(const HostOp&, const HostArgs&, hipStream_t, bool*);
-hipError_t dispatch_p4(const HostOp&, const HostArgs&, hipStream_t, bool*);
-hipError_t dispatch_p5(const HostOp&, const HostArgs&, hipStream_t, bool*);
-hipError_t dispatch_p6(const HostOp&, const HostArgs&, hipStream_t, bool*);
+#define HX_DECLARE_DISPATCH(p)                                                  \
+  hipError_t dispatch_p##p##_t0(const HostOp&, const HostArgs&, hipStream_t, bool*); \
+  hipError_t dispatch_p##p##_t1(const HostOp&, const HostArgs&, hipStream_t, bool*); \
+  hipError_t dispatch_p##p##_t2(const HostOp&, const HostArgs&, hipStream_t, bool*);
+HX_DECLARE_DISPATCH(1)
+HX_DECLARE_DISPATCH(2)
+HX_DECLARE_DISPATCH(3)
+HX_DECLARE_DISPATCH(4)
+HX_DECLARE_DISPATCH(5)
+HX_DECLARE_DISPATCH(6)
+#undef HX_DECLARE_DISPATCH
 
 }  // namespace hx

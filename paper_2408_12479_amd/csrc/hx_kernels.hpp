@@ -652,17 +652,19 @@ __device__ __forceinline__ void pencil_jobs(Fn&& fn) {
 // Used for odd N only: with N even the per-cell LDS stride (9 N^3 words) is a multiple of the
 // bank count, the cells' rows fall on the same banks and the interleaved LDS writes conflict
 // (measured slower at Q3); with N odd they are spread over the banks (Q4: +5 %).
+// (The host builds the general meshes' gather map in the same order, with slot_of_thread.)
 template <int N, int EB>
 __device__ __forceinline__ void interleaved_slot(int t, int& le, int& q) {
-  if constexpr (EB > 1 && N % 2 == 1) {
-    const int i = t % N;
-    const int r = t / N;
-    le = r % EB;
-    q = i + N * (r / EB);
-  } else {
-    le = t / (N * N * N);
-    q = t - le * N * N * N;
-  }
+  slot_of_thread(N, EB, t, le, q);
+}
+
+// Node and constraint flag of gather slot t of block blk of a general mesh (map entry ~node marks
+// a constrained node).
+template <int N, int EB>
+__device__ __forceinline__ int64_t map_node(const int32_t* map, int blk, int t, bool& cons) {
+  const int32_t v = map[static_cast<int64_t>(blk) * (EB * N * N * N) + t];
+  cons = v < 0;
+  return cons ? static_cast<int64_t>(~v) : static_cast<int64_t>(v);
 }
 
 // LDS per cell: 9 fields of N^3 values. Forward: values (then d/dx in place) in c, d/dz in
@@ -671,7 +673,7 @@ constexpr int kBuffers = 9;
 
 // Forward pass for one 3-component vector V: writes the 9 reference derivatives at this
 // thread's q-point into g[c*3 + d].
-template <int N, int EB, bool MASK, typename R>
+template <int N, int EB, bool MASK, int TOPO, typename R>
 __device__ __forceinline__ void forward_vector(const KernelArgs<N, R>& a, R* sb, const R* V,
                                                int e0, const CellPos& c0, int le_me, int q_me,
                                                R* g) {
@@ -687,10 +689,15 @@ __device__ __forceinline__ void forward_vector(const KernelArgs<N, R>& a, R* sb,
     interleaved_slot<N, EB>(le_me * Q + q_me, lg, qg);
     R* cb = sb + lg * CB;
     if (e0 + lg < L.n_cells) {
-      const int i = qg % N, j = (qg / N) % N, k = qg / (N * N);
-      const CellPos cp = cell_advance(L, c0, lg);
       bool cons;
-      const int64_t node = node_of(L, cp, i, j, k, cons);
+      int64_t node;
+      if constexpr (TOPO == kTopoMap) {
+        node = map_node<N, EB>(a.map, e0 / EB, le_me * Q + q_me, cons);
+      } else {
+        const int i = qg % N, j = (qg / N) % N, k = qg / (N * N);
+        const CellPos cp = cell_advance(L, c0, lg);
+        node = node_of(L, cp, i, j, k, cons);
+      }
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const R v = V[c * L.n_nodes + node];
@@ -783,7 +790,7 @@ __device__ __forceinline__ void forward_vector(const KernelArgs<N, R>& a, R* sb,
 // at each node and writes every row of the output once, in whole cache lines. (Device-scope
 // FP64 atomics on the shared nodes cost about a third of the apply on MI355X; storing the
 // cell-interior rows directly from here, interleaved with the other kernel's rows, was slower.)
-template <int N, int EB, typename R>
+template <int N, int EB, int TOPO, typename R>
 __device__ __forceinline__ void backward_scatter(const KernelArgs<N, R>& a, R* sb, int e0,
                                                  const CellPos& c0, int le_me, int q_me,
                                                  const R* t) {
@@ -861,7 +868,21 @@ __device__ __forceinline__ void backward_scatter(const KernelArgs<N, R>& a, R* s
     int lg, qg;
     interleaved_slot<N, EB>(le_me * Q + q_me, lg, qg);
     const int e = e0 + lg;
-    if (e < L.n_cells) {
+    if constexpr (TOPO == kTopoMap) {
+      // general mesh: the brick of a cell is its workgroup's slots, in the gather's order, so
+      // that the store is one contiguous run per workgroup; the node kernel finds each node's
+      // slots through its slot list
+      if (e < L.n_cells) {
+        bool cons;
+        (void)map_node<N, EB>(a.map, e0 / EB, le_me * Q + q_me, cons);
+        if (!cons) {
+          const int64_t ES = static_cast<int64_t>(gridDim.x) * (EB * Q);
+          const int64_t pos = static_cast<int64_t>(e0 / EB) * (EB * Q) + le_me * Q + q_me;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) a.ework[c * ES + pos] = sb[lg * CB + (3 * c) * Lds<N>::FS + lds_q<N>(qg)];
+        }
+      }
+    } else if (e < L.n_cells) {
       const int i = qg % N, j = (qg / N) % N, k = qg / (N * N);
       const CellPos cp = cell_advance(L, c0, lg);
       bool cons;
@@ -973,6 +994,32 @@ __global__ void __launch_bounds__(256) assemble_kernel(Lattice L, const R* __res
   out[node] = s0;
   out[n + node] = s1;
   out[2 * n + node] = s2;
+}
+
+// General meshes: one thread per node sums the element-vector slots of its list (increasing slot
+// order, so repeated applies are bit-identical); constrained rows receive cons_src or zero.
+template <typename R>
+__global__ void __launch_bounds__(256) assemble_map_kernel(int64_t n, const int32_t* __restrict__ nptr,
+                                                           const int32_t* __restrict__ nslot,
+                                                           const uint8_t* __restrict__ cmask, int64_t ES,
+                                                           const R* __restrict__ E, const R* __restrict__ cons_src,
+                                                           R* __restrict__ out) {
+  const int64_t node = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (node >= n) return;
+  if (cmask[node]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[c * n + node] = cons_src ? cons_src[c * n + node] : R(0);
+    return;
+  }
+  const int s0 = nptr[node], s1 = nptr[node + 1];
+  R s[3] = {R(0), R(0), R(0)};
+  for (int k = s0; k < s1; ++k) {
+    const int64_t sl = nslot[k];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s[c] += E[c * ES + sl];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) out[c * n + node] = s[c];
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1217,7 +1264,8 @@ __device__ __forceinline__ int xcd_block(int b, int g) {
 // The apply and residual kernels are held to at most 128 VGPRs (4 waves per SIMD; forcing 8
 // waves spills and is slower); the update runs once per Newton step and may use the whole
 // register file.
-template <int N, int EB, typename R, int KIND, int MODE, int LAW, int S, bool NT = false>
+template <int N, int EB, typename R, int KIND, int MODE, int LAW, int S, bool NT = false,
+          int TOPO = kTopoLattice>
 __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
     element_kernel(KernelArgs<N, R> a) {
   constexpr int Q = N * N * N;
@@ -1259,7 +1307,26 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
   }
 
   constexpr bool kGeom = !(KIND == 0 && (MODE == HX_STORE_TANGENT || MODE == HX_STORE_SPATIAL));
-  if constexpr (kGeom) load_vertices<N, EB>(a, sv, e0, c0);
+  // stored geometry of this thread's q-point (curved or general meshes), requested early like the
+  // stored data; the lattice of trilinear cells forms it from the vertices instead
+  constexpr bool kGeoStored = kGeom && TOPO != kTopoLattice;
+  R gq[kGeoStored ? kGeoWords : 1];
+  if constexpr (kGeoStored) {
+    const R* gp = a.geo + static_cast<int64_t>(blk) * kGeoWords * EBQ;
+#pragma unroll
+    for (int w = 0; w < kGeoWords; ++w) gq[w] = valid ? gp[w * EBQ + qi] : R(0);
+  }
+  if constexpr (kGeom && TOPO == kTopoLattice) load_vertices<N, EB>(a, sv, e0, c0);
+  // K = J0^-1 and w det J0 at this thread's q-point
+  auto geometry = [&](R* K) -> R {
+    if constexpr (!kGeoStored) {
+      return valid ? qpoint_geometry<N>(sv + le * 24, q, K) : R(0);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) K[i] = gq[i];
+      return gq[9];
+    }
+  };
   if constexpr (KIND == 2 && S == kStoreF16) {
     if (q == 0) sred[le] = 0.0f;
   }
@@ -1267,13 +1334,13 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
   R g0[9], g1[9], t[9];
   if constexpr (KIND == 0 && MODE == HX_STORE_NONE) {
     // linearisation point first (not masked), then the direction (masked)
-    forward_vector<N, EB, false>(a, sb, a.in1, e0, c0, le, q, g1);
+    forward_vector<N, EB, false, TOPO>(a, sb, a.in1, e0, c0, le, q, g1);
     __syncthreads();
-    forward_vector<N, EB, true>(a, sb, a.in0, e0, c0, le, q, g0);
+    forward_vector<N, EB, true, TOPO>(a, sb, a.in0, e0, c0, le, q, g0);
   } else if constexpr (KIND == 0) {
-    forward_vector<N, EB, true>(a, sb, a.in0, e0, c0, le, q, g0);
+    forward_vector<N, EB, true, TOPO>(a, sb, a.in0, e0, c0, le, q, g0);
   } else {
-    forward_vector<N, EB, false>(a, sb, a.in0, e0, c0, le, q, g0);
+    forward_vector<N, EB, false, TOPO>(a, sb, a.in0, e0, c0, le, q, g0);
   }
 
   const MaterialK<R>& m = a.c->m;
@@ -1320,7 +1387,7 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
     spatial_action<LAW>(d, m, g0, t);
   } else if constexpr (KIND == 0) {
     R K[9];
-    const R wdet = valid ? qpoint_geometry<N>(sv + le * 24, q, K) : R(0);
+    const R wdet = geometry(K);
     QState<R> st;
     if constexpr (kIsFiber<LAW>) {
       if (a.act && valid) st.forced = a.act[static_cast<int64_t>(blk) * EBQ + qi];
@@ -1348,7 +1415,7 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
     to_reference(Pd, K, wdet, t);
   } else if constexpr (KIND == 1) {
     R K[9], H[9], E[9], P[9];
-    const R wdet = valid ? qpoint_geometry<N>(sv + le * 24, q, K) : R(0);
+    const R wdet = geometry(K);
     to_physical(g0, K, H);
     QState<R> st;
     state_from_H<LAW>(H, m, fb, st, E);
@@ -1357,7 +1424,7 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
   } else {
     // linearisation update (always FP64 arithmetic)
     R K[9], H[9], E[9];
-    const R wdet = valid ? qpoint_geometry<N>(sv + le * 24, q, K) : R(0);
+    const R wdet = geometry(K);
     to_physical(g0, K, H);
     QState<R> st;
     const bool ok = state_from_H<LAW>(H, m, fb, st, E);
@@ -1426,7 +1493,16 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
       }
     } else if constexpr (MODE == HX_STORE_SPATIAL) {
       R J0[9], dw[W];
-      qpoint_jacobian<N>(sv + le * 24, q, J0);
+      if constexpr (TOPO == kTopoLattice) {
+        qpoint_jacobian<N>(sv + le * 24, q, J0);
+      } else {
+        // J0 = K^-1 from the stored inverse
+        R A[9];
+        adj3(K, A);
+        const R inv = R(1) / (K[0] * A[0] + K[1] * A[3] + K[2] * A[6]);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) J0[i] = A[i] * inv;
+      }
       spatial_words_at<LAW>(H, st, m, fb, J0, g0, wdet, dw);
       R chk = R(0);
 #pragma unroll
@@ -1448,7 +1524,7 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
 #pragma unroll
       for (int i = 0; i < 9; ++i) t[i] = R(0);
     }
-    backward_scatter<N, EB>(a, sb, e0, c0, le, q, t);
+    backward_scatter<N, EB, TOPO>(a, sb, e0, c0, le, q, t);
   }
 }
 

@@ -824,6 +824,8 @@ hx_status hx_mg_create(const hx_ctx* levels, int32_t n_levels, const hx_mg_optio
   if (!levels || n_levels < 1) return HX_E_ARG;
   for (int l = 0; l < n_levels; ++l) {
     if (!levels[l]) return HX_E_ARG;
+    // transfers, the diagonal and the coarse assembly address lattices
+    if (levels[l]->topo == kTopoMap) return HX_E_UNSUPPORTED;
     if (l > 0) {
       const Lattice& a = levels[l - 1]->L;
       const Lattice& b = levels[l]->L;
@@ -1218,92 +1220,6 @@ hx_status hx_newton_solve(hx_mg mg, double* u, const double* f_ext, const hx_new
   if (status == HX_E_HIP) return mg_fail(mg, status, "hx_newton_solve: HIP error");
   if (status == HX_E_NOT_CONVERGED) return mg_fail(mg, status, "hx_newton_solve: Newton did not converge");
   return status;
-}
-
-// Dead-load pressure on one boundary face (Section 2 residual, Neumann term):
-// f_(c,a) = -p * int_face phi_a N_c dA, N the outward unit normal of the reference body.
-hx_status hx_surface_load(hx_ctx ctx, int32_t face, double pressure, double* f) {
-  if (!ctx || !f || face < 0 || face > 5) return HX_E_ARG;
-  const Lattice& L = ctx->L;
-  const int d = face / 2, side = face % 2;
-  const int per = (L.Nx == L.nx * L.p ? 1 : 0) | (L.Ny == L.ny * L.p ? 2 : 0) | (L.Nz == L.nz * L.p ? 4 : 0);
-  if (per & (1 << d)) return set_error(ctx, HX_E_ARG, "hx_surface_load: face of a periodic direction");
-  const int n = ctx->p + 1;
-  const int64_t nn = L.n_nodes;
-  std::memset(f, 0, 3 * nn * sizeof(double));
-  const double* xq = ctx->base.x;
-  const double* wq = ctx->base.w;
-  const int da = (d + 1) % 3, db = (d + 2) % 3;  // tangential reference directions (cyclic)
-  const int nc[3] = {L.nx, L.ny, L.nz};
-  const int cd = side ? nc[d] - 1 : 0;
-  std::vector<double> la(n * n);  // la[q*n + i] = l_i(x_q) on the GLL nodes
-  for (int qq = 0; qq < n; ++qq)
-    for (int i = 0; i < n; ++i) {
-      double v = 1.0;
-      for (int m = 0; m < n; ++m)
-        if (m != i) v *= (xq[qq] - ctx->gll[m]) / (ctx->gll[i] - ctx->gll[m]);
-      la[qq * n + i] = v;
-    }
-  int cell[3];
-  for (int c2 = 0; c2 < nc[db]; ++c2)
-    for (int c1 = 0; c1 < nc[da]; ++c1) {
-      cell[d] = cd;
-      cell[da] = c1;
-      cell[db] = c2;
-      const int e = cell[0] + L.nx * (cell[1] + L.ny * cell[2]);
-      (void)e;
-      double X8[8][3];
-      for (int v = 0; v < 8; ++v) {
-        int vx = cell[0] + (v & 1), vy = cell[1] + ((v >> 1) & 1), vz = cell[2] + (v >> 2);
-        vx = vx >= L.Vx ? vx - L.Vx : vx;
-        vy = vy >= L.Vy ? vy - L.Vy : vy;
-        vz = vz >= L.Vz ? vz - L.Vz : vz;
-        const double* P = &ctx->vert_host[3 * (vx + static_cast<int64_t>(L.Vx) * (vy + static_cast<int64_t>(L.Vy) * vz))];
-        for (int k = 0; k < 3; ++k) X8[v][k] = P[k];
-      }
-      for (int q2 = 0; q2 < n; ++q2)
-        for (int q1 = 0; q1 < n; ++q1) {
-          double xi[3];
-          xi[d] = side ? 1.0 : 0.0;
-          xi[da] = xq[q1];
-          xi[db] = xq[q2];
-          // tangent vectors dX/dxi_da, dX/dxi_db of the trilinear map
-          double ta[3] = {0, 0, 0}, tb[3] = {0, 0, 0};
-          for (int v = 0; v < 8; ++v) {
-            const int bit[3] = {v & 1, (v >> 1) & 1, v >> 2};
-            double phi[3], dphi[3];
-            for (int k = 0; k < 3; ++k) {
-              phi[k] = bit[k] ? xi[k] : 1.0 - xi[k];
-              dphi[k] = bit[k] ? 1.0 : -1.0;
-            }
-            const double ga = dphi[da] * phi[db] * phi[d];
-            const double gb = phi[da] * dphi[db] * phi[d];
-            for (int k = 0; k < 3; ++k) {
-              ta[k] += ga * X8[v][k];
-              tb[k] += gb * X8[v][k];
-            }
-          }
-          // ta x tb points along +xi_d for a positively oriented map: outward on the max side
-          double nda[3] = {ta[1] * tb[2] - ta[2] * tb[1], ta[2] * tb[0] - ta[0] * tb[2], ta[0] * tb[1] - ta[1] * tb[0]};
-          const double sgn = side ? 1.0 : -1.0;
-          const double w = wq[q1] * wq[q2];
-          for (int j2 = 0; j2 < n; ++j2)
-            for (int j1 = 0; j1 < n; ++j1) {
-              int loc[3];
-              loc[d] = side ? n - 1 : 0;
-              loc[da] = j1;
-              loc[db] = j2;
-              int I[3] = {cell[0] * L.p + loc[0], cell[1] * L.p + loc[1], cell[2] * L.p + loc[2]};
-              I[0] = I[0] >= L.Nx ? I[0] - L.Nx : I[0];
-              I[1] = I[1] >= L.Ny ? I[1] - L.Ny : I[1];
-              I[2] = I[2] >= L.Nz ? I[2] - L.Nz : I[2];
-              const int64_t node = I[0] + static_cast<int64_t>(L.Nx) * (I[1] + static_cast<int64_t>(L.Ny) * I[2]);
-              const double phi = la[q1 * n + j1] * la[q2 * n + j2];
-              for (int k = 0; k < 3; ++k) f[k * nn + node] += -pressure * sgn * nda[k] * w * phi;
-            }
-        }
-    }
-  return HX_OK;
 }
 
 }  // extern "C"

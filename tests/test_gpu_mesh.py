@@ -1,0 +1,168 @@
+"""GPU parity of the general-mesh and curved-cell paths against the FP64 oracle, through the C ABI.
+
+* General meshes (hx_setup): a perturbed lattice written as connectivity with renumbered vertices,
+  shuffled cells and every cell turned by a rotation of the cube, and a genuinely unstructured
+  O-grid of a cylinder (valence-3 vertices) with curved cells of degree 2; node numbering, node
+  coordinates, constraint masks, residual and every storage mode of the tangent apply, FP64 within
+  1e-12 and FP32 within 1e-5 (relative 2-norm), against the oracle's own first-touch numbering.
+* Curved lattices (hx_setup_lattice with geometry points): the tube with isoparametric cells.
+* Pressure loads by boundary id and on curved lattice faces; error paths of hx_setup; no
+  multigrid on general meshes.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2408_12479_amd as hx
+import workloads
+from oracle import fem, fiber, mesh as omesh
+from tests.gpu_helpers import rel, to_dev, to_host
+from tests.helpers import make_material
+
+pytestmark = pytest.mark.gpu
+
+
+def _matkw(mat):
+    return dict(law=mat.law, mu=mat.mu, lam=mat.lam, kappa=mat.kappa, k1=mat.k1, k2=mat.k2, H4=mat.H4, H6=mat.H6,
+                M4=mat.M4, M6=mat.M6)
+
+
+def _scrambled_lattice(p, law, seed=7):
+    nx, ny, nz = 3, 2, 2
+    V = workloads.box_vertices(nx, ny, nz, perturb=0.2, seed=4)
+    Vh, C, F = workloads.lattice_as_hex(nx, ny, nz, V, faces=(0, 3))
+    Vh, C, F, _, _, _ = workloads.scramble_hex(Vh, C, F, seed=seed)
+    mat = make_material(law)
+    m = omesh.HexMesh(Vh, C, p, face_bid=F, dirichlet_bids=(1, 4))
+    op = hx.HexOperator(Vh, C, p, face_bid=F, dirichlet_bids=(1, 4), **_matkw(mat))
+    return op, fem.Problem(m, mat)
+
+
+def _ogrid(p, law, g=2, seed=3):
+    V, C, F, G = workloads.ogrid_cylinder(2, 2, g=g)
+    V, C, F, G, _, _ = workloads.scramble_hex(V, C, F, G, geom_degree=g, seed=seed)
+    mat = make_material(law)
+    m = omesh.HexMesh(V, C, p, face_bid=F, dirichlet_bids=(1,), geom_degree=g, geom_nodes=G)
+    op = hx.HexOperator(V, C, p, face_bid=F, dirichlet_bids=(1,), geom_degree=g, geom_nodes=G, **_matkw(mat))
+    return op, fem.Problem(m, mat)
+
+
+def _fields(pb, scale=0.05, seed=1):
+    # a smooth field that vanishes on the constrained faces (x = 0 and y = 1 of the box, the bottom
+    # z = 0 of the cylinder and of the tube's clamped end), so that zeroing it there leaves it smooth
+    X = pb.mesh.node_coords
+    if isinstance(pb.mesh, omesh.HexMesh) and pb.mesh.dirichlet_bids == (1, 4):
+        damp = X[:, 0] * (1.0 - X[:, 1])
+    else:
+        damp = X[:, 2]
+    u = scale * damp * np.stack([np.sin(X[:, 0] + 2 * X[:, 1]), np.cos(X[:, 2] - X[:, 0]),
+                                 np.sin(3 * X[:, 1] * X[:, 2])])
+    u[:, pb.mesh.constrained] = 0.0
+    du = workloads.random_direction(pb.mesh.n_nodes, seed, pb.mesh.constrained)
+    return u, du
+
+
+def _check(op, pb, modes=("none", "finv_j", "tangent", "spatial"), precisions=("fp64", "fp32")):
+    n = pb.mesh.n_nodes
+    assert op.num_nodes == n
+    np.testing.assert_allclose(op.node_coords(), pb.mesh.node_coords, rtol=0, atol=1e-13)
+    np.testing.assert_array_equal(op.constrained_mask(), pb.mesh.constrained)
+    u, du = _fields(pb)
+    ud = to_dev(u)
+    rr = pb.residual(u)
+    assert rel(to_host(op.residual(ud), n), rr) < 1e-12
+    ref = pb.apply_tangent(u, du)
+    for prec in precisions:
+        dt = "float64" if prec == "fp64" else "float32"
+        for mode in modes:
+            op.update_linearization(ud, mode=mode, precision=prec)
+            y = to_host(op.apply_tangent(to_dev(du, dt), precision=prec), n)
+            err = rel(y, ref)
+            assert err < (1e-12 if prec == "fp64" else 1e-5), (prec, mode, err)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
+def test_scrambled_lattice_as_general_mesh(device, p):
+    op, pb = _scrambled_lattice(p, "inh")
+    _check(op, pb)
+    op.close()
+
+
+@pytest.mark.parametrize("law", ["cnh", "fiber"])
+@pytest.mark.parametrize("p", [2, 4])
+def test_curved_ogrid(device, p, law):
+    op, pb = _ogrid(p, law)
+    _check(op, pb)
+    op.close()
+
+
+def test_general_mesh_repeats_bit_identically(device):
+    op, pb = _ogrid(3, "cnh")
+    u, du = _fields(pb)
+    op.update_linearization(to_dev(u), mode="spatial")
+    d = to_dev(du)
+    y0 = op.apply_tangent(d).cpu().numpy()
+    for _ in range(3):
+        assert np.array_equal(op.apply_tangent(d).cpu().numpy(), y0)
+    op.close()
+
+
+def _tube_pair(p, g, law="fiber", cells=(4, 2, 3)):
+    tube = dict(length=1.0, bend=0.3)
+    G = workloads.tube_geometry_nodes(*cells, g, **tube)
+    frames = workloads.tube_frames(*cells, **tube)
+    mat = make_material(law)
+    cf = None
+    if law == "fiber":
+        cf = fiber.cell_structure_tensors(frames, np.deg2rad(45.0), *fiber.dispersion_coefficients(3.62, 34.3))
+    V = workloads.tube_vertices(*cells, **tube)
+    m = omesh.BoxMesh(*cells, V, p, dirichlet_faces=(4,), periodic=(True, False, False), geom_degree=g, geom_nodes=G)
+    op = hx.Operator(*cells, None, p, dirichlet_faces=(4,), periodic=(True, False, False), frames=frames,
+                     geom_degree=g, geom_nodes=G, **_matkw(mat))
+    return op, fem.Problem(m, mat, cell_fibers=cf)
+
+
+@pytest.mark.parametrize("p", [2, 3, 4, 6])
+def test_isoparametric_tube_lattice(device, p):
+    op, pb = _tube_pair(p, p)
+    _check(op, pb)
+    # the curved tube's volume differs from the polygonal (trilinear) one
+    op.close()
+
+
+def test_surface_loads(device):
+    op, pb = _ogrid(3, "cnh")
+    for bid in (1, 2, 3):
+        assert rel(op.surface_load(bid, 0.4), fem.surface_load_bid(pb, bid, 0.4)) < 1e-13
+    with pytest.raises(hx.HxError):
+        op.surface_load(0, 0.4)
+    op.close()
+    op, pb = _tube_pair(3, 3)
+    assert rel(op.surface_load(2, 0.1), fem.surface_load(pb, 2, 0.1)) < 1e-13
+    op.close()
+
+
+def test_general_mesh_errors(device):
+    V, C, F, G = workloads.ogrid_cylinder(1, 1, g=1)
+    mat = dict(law="cnh", mu=1.0, lam=10.0)
+    bad = C.copy()
+    bad[0, 1] = bad[0, 0]
+    with pytest.raises(hx.HxError) as err:
+        hx.HexOperator(V, bad, 2, **mat)
+    assert err.value.name == "HX_E_ARG"
+    bad = C.copy()
+    bad[0, 0] = len(V)
+    with pytest.raises(hx.HxError) as err:
+        hx.HexOperator(V, bad, 2, **mat)
+    assert err.value.name == "HX_E_ARG"
+    # a mirrored cell (corners a and a + 1 swapped along x) is inverted
+    bad = C.copy()
+    bad[0, [0, 1, 2, 3, 4, 5, 6, 7]] = bad[0, [1, 0, 3, 2, 5, 4, 7, 6]]
+    with pytest.raises(hx.HxError) as err:
+        hx.HexOperator(V, bad, 2, **mat)
+    assert err.value.name == "HX_E_INVERTED"
+    op = hx.HexOperator(V, C, 1, face_bid=F, dirichlet_bids=(1,), **mat)
+    with pytest.raises(hx.HxError) as err:
+        hx.Multigrid([op], precision="fp64")
+    assert err.value.name == "HX_E_UNSUPPORTED"
+    op.close()
