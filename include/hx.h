@@ -251,6 +251,18 @@ hx_status hx_update_linearization(hx_ctx ctx, const double* u, hx_storage mode,
 hx_status hx_apply_tangent(hx_ctx ctx, const void* du, void* dst, hx_precision prec,
                            void* stream);
 
+/* The same operator as hx_apply_tangent, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the element
+ * vectors go to a static device buffer of the library (64 MiB per GPU, held until the process
+ * ends) instead of the context's buffer, and the call allocates nothing, host or device. Limit:
+ * 3 * n_cells * (p+1)^3 values of the apply's type (8 bytes for HX_FP64, 4 for the FP32 values;
+ * n_cells rounded up to whole workgroups of cells) must fit in 64 MiB, else HX_E_ARG with a
+ * message. The buffer is shared by every context on the
+ * GPU and keeps the last call's contents (no part of it needs to start at zero): calls of this
+ * entry point that overlap in time on one GPU (different streams, or host threads) race. */
+hx_status hx_apply_tangent_noalloc(hx_ctx ctx, const void* du, void* dst, hx_precision prec,
+                                   void* stream);
+
 /* Autotuner of the storage strategy (Section 7.2: which strategy is fastest depends on the
  * hardware, degree and law and has to be measured). For each of NONE, FINV_J, TANGENT and SPATIAL:
  * updates the slot of prec (HX_FP64 or HX_FP32) at u, applies once to warm up, then times `reps`

@@ -99,6 +99,7 @@ def _load():
         "hx_residual": (ctypes.c_int, [vp, vp, vp, vp]),
         "hx_update_linearization": (ctypes.c_int, [vp, vp, ctypes.c_int, ctypes.c_int, vp]),
         "hx_apply_tangent": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, vp]),
+        "hx_apply_tangent_noalloc": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, vp]),
         "hx_linearization_bytes": (i64, [vp, ctypes.c_int]),
         "hx_autotune_storage": (ctypes.c_int, [vp, vp, ctypes.c_int, ctypes.c_int32, ctypes.POINTER(ctypes.c_int),
                                                ctypes.POINTER(ctypes.c_double), vp]),
@@ -281,6 +282,15 @@ class _Context:
         dst = torch.empty_like(du) if dst is None else dst
         _check(lib.hx_apply_tangent(self.ctx, self._vec(du, dt, "du"), self._vec(dst, dt, "dst"),
                                     PRECISIONS[precision], _stream_handle(stream)), self.ctx)
+        return dst
+
+    def apply_tangent_noalloc(self, du, dst, precision="fp64", stream=None):
+        """hx_apply_tangent_noalloc: the apply with the library's static element-vector buffer
+        (dst must be given; nothing is allocated)."""
+        import torch
+        dt = torch.float64 if precision == "fp64" else torch.float32
+        _check(lib.hx_apply_tangent_noalloc(self.ctx, self._vec(du, dt, "du"), self._vec(dst, dt, "dst"),
+                                            PRECISIONS[precision], _stream_handle(stream)), self.ctx)
         return dst
 
     def linearization_bytes(self, precision="fp64"):

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -132,6 +133,32 @@ using namespace hx;
 namespace {
 
 thread_local std::string g_setup_error;
+
+// Element-vector buffer of hx_apply_tangent_noalloc: a file-scope device array (each GPU the
+// library runs on holds its own copy until the process ends). Host code never passes the array's
+// name to a kernel: it is a host-side stand-in, not a device address. The device address of each
+// GPU's copy is looked up once, with that device current, by the setup calls.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on the current device (looked up on the first call per device)
+hipError_t scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
 
 }  // namespace
 
@@ -497,6 +524,11 @@ hx_status hx::finish_setup(hx_ctx_s* c, const hx_material* mat, const hx_options
     hx_destroy(c);
     return hip_fail(nullptr, e, "hx_setup: constants");
   }
+  void* sp = nullptr;
+  if ((e = scratch_address(c->device, &sp)) != hipSuccess) {
+    hx_destroy(c);
+    return hip_fail(nullptr, e, "hx_setup: address of the static element-vector buffer");
+  }
   *out = c;
   return HX_OK;
 }
@@ -829,6 +861,23 @@ extern "C" {
 
 hx_status hx_apply_tangent(hx_ctx ctx, const void* du, void* dst, hx_precision prec, void* stream) {
   return apply_with(ctx, du, dst, prec, stream, ctx ? ctx->ework : nullptr, "hx_apply_tangent");
+}
+
+hx_status hx_apply_tangent_noalloc(hx_ctx ctx, const void* du, void* dst, hx_precision prec, void* stream) {
+  if (!ctx) return fail(ctx, HX_E_ARG, "hx_apply_tangent_noalloc: NULL context");
+  // the element vectors of every cell: 3 components x cells (whole workgroups) x (p+1)^3 values of
+  // the apply's type
+  const int64_t q = static_cast<int64_t>(ctx->p + 1) * (ctx->p + 1) * (ctx->p + 1);
+  const int64_t eb = cells_per_block(ctx->p);
+  const int64_t padded = (static_cast<int64_t>(ctx->L.n_cells) + eb - 1) / eb * eb;
+  const size_t need = static_cast<size_t>(3 * padded * q) * (prec == HX_FP64 ? sizeof(double) : sizeof(float));
+  if (need > kScratchBytes)
+    return fail(ctx, HX_E_ARG, "hx_apply_tangent_noalloc: the element vectors need " + std::to_string(need) +
+                                   " bytes, more than the static buffer's " + std::to_string(kScratchBytes));
+  void* sp = nullptr;
+  const hipError_t e = scratch_address(ctx->device, &sp);  // set at hx_setup: a table read
+  if (e != hipSuccess) return hip_fail(ctx, e, "hx_apply_tangent_noalloc: static buffer");
+  return apply_with(ctx, du, dst, prec, stream, sp, "hx_apply_tangent_noalloc");
 }
 
 hx_status hx_autotune_storage(hx_ctx ctx, const double* u, hx_precision prec, int32_t reps,
