@@ -361,9 +361,19 @@ def main():
         samples[p] = (nodes, rows)
         print(f"[bench] p={p}: " + ", ".join(f"{m_} {res[m_]['gdofs']:.2f} GDoF/s" for m_ in modes),
               file=sys.stderr, flush=True)
+        # the configuration autotuner: every storage mode x cells-per-workgroup variant x load
+        # policy of the stored data; its choice per mode is kept by the context
+        best_cfg, configs = op.autotune(ud, "fp64", reps=max(10, args.steps // 2))
+        res["autotune"] = {"best": best_cfg, "configurations": configs}
+        print(f"[bench] p={p}: autotuner picks {best_cfg['mode']} with {best_cfg['cells_per_workgroup']} cells "
+              f"per workgroup, non-temporal {best_cfg['nontemporal']} ({best_cfg['ms']:.4f} ms)",
+              file=sys.stderr, flush=True)
         if p == args.p:
-            mode = args.mode if args.mode != "auto" else max(modes, key=lambda m_: res[m_]["gdofs"])
+            mode = args.mode if args.mode != "auto" else best_cfg["mode"]
+            # the update uses the configuration the autotuner recorded for the mode
             op.update_linearization(ud, mode=mode, precision="fp64")
+            cfg = next(c for c in configs if c["mode"] == mode and c["ms"] == min(
+                x["ms"] for x in configs if x["mode"] == mode))
             for _ in range(args.warmup):
                 op.apply_tangent(dud, dst)
             torch.cuda.synchronize()
@@ -376,7 +386,7 @@ def main():
             ms = e0.elapsed_time(e1) / args.steps
             b, f = algorithmic(p, mode, op.num_cells, op.num_dofs)
             head = dict(p=p, mode=mode, ms=ms, dofs=op.num_dofs, cells=op.num_cells, bytes=b, flops=f,
-                        dst=dst.cpu().numpy())
+                        dst=dst.cpu().numpy(), cfg=cfg)
         op.close()
         del ud, dud, dst, r
         torch.cuda.empty_cache()
@@ -436,7 +446,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"perturbed cube {args.cells}^3 cells, Q{head['p']}, cNH mu=1 lambda=100, "
                                f"stretch 1.3, storage mode {head['mode']}",
-                   "dofs": head["dofs"], "cells": head["cells"], "p": head["p"], "storage": head["mode"]},
+                   "dofs": head["dofs"], "cells": head["cells"], "p": head["p"], "storage": head["mode"],
+                   "cells_per_workgroup": head["cfg"]["cells_per_workgroup"],
+                   "nontemporal_loads": head["cfg"]["nontemporal"]},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

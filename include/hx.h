@@ -105,15 +105,19 @@ typedef enum {
                            c2 and (2 mu / 3) J^-2/3 b; fibre per family F H_i F^T and
                            2 c3 (2 k2 E_i^2 + 1)): 16 / 23 / 37 words for cNH / iNH / fibre;
                            FP64 or FP32 data */
+  HX_STORE_SPATIAL_RECOMPUTE = 4, /* the spatial-configuration operator with nothing stored: every
+                                     apply re-interpolates u_k and forms the SPATIAL mode's data
+                                     on the fly (the paper's "recompute all" variant over Omega_t);
+                                     the library keeps a copy of u_k */
   HX_STORE_AUTO = 255 /* only where a field says so: the mode is chosen by hx_autotune_storage */
 } hx_storage;
 
 /* Arithmetic of hx_apply_tangent and the type of its stored data.
  *   FP64             double vectors, double compute, double data
  *   FP32             float vectors, float compute, float data
- *   FP32_BF16DATA    float vectors and compute, bfloat16 data (TANGENT only)
+ *   FP32_BF16DATA    float vectors and compute, bfloat16 data (FINV_J, TANGENT, SPATIAL)
  *   FP32_FP16DATA    float vectors and compute, binary16 data scaled per cell by a power of
- *                    two (TANGENT only)
+ *                    two (TANGENT only: its words share one magnitude per cell)
  * The linearisation data itself is always computed in FP64 and rounded once when stored. */
 typedef enum {
   HX_FP64 = 0,
@@ -230,8 +234,15 @@ hx_status hx_constrained_mask(hx_ctx ctx, uint8_t* host_mask);
  * [3][n_nodes]; constrained rows are 0. u and r must not alias. */
 hx_status hx_residual(hx_ctx ctx, const double* u, double* r, void* stream);
 
+/* r = r~(u) evaluated over the spatial configuration (Section 2, the residual written with the
+ * Kirchhoff stress and the spatial gradient: r_a = int_Omega0 tau : grad phi_a, grad = Grad F^-1,
+ * with the Jacobian J_t = J0 + du/dxi of the deformed map). Equal to hx_residual in exact
+ * arithmetic; same arguments and errors. */
+hx_status hx_residual_spatial(hx_ctx ctx, const double* u, double* r, void* stream);
+
 /* Linearisation update at u (Algorithm 1, "update quadrature point data"): stores the data of
- * the requested mode in the requested storage precision. The FP64 class (prec == HX_FP64) and
+ * the requested mode in the requested storage precision, in the configuration hx_autotune or
+ * hx_set_tuning recorded for that mode and precision class (else the default one). The FP64 class (prec == HX_FP64) and
  * the FP32 class (the three FP32 values) are separate slots, so one context can hold an FP64
  * operator and an FP32 operator at once. For the fibre law in the FP32 NONE and FINV_J modes the
  * tension switches (I*_i > 1) are decided here in FP64 and kept (one byte per q-point), so that
@@ -263,15 +274,50 @@ hx_status hx_apply_tangent(hx_ctx ctx, const void* du, void* dst, hx_precision p
 hx_status hx_apply_tangent_noalloc(hx_ctx ctx, const void* du, void* dst, hx_precision prec,
                                    void* stream);
 
-/* Autotuner of the storage strategy (Section 7.2: which strategy is fastest depends on the
- * hardware, degree and law and has to be measured). For each of NONE, FINV_J, TANGENT and SPATIAL:
- * updates the slot of prec (HX_FP64 or HX_FP32) at u, applies once to warm up, then times `reps`
- * applies (1..1000) of a fixed direction with HIP events on the stream. Leaves the slot
- * linearised in the fastest mode, written to *best; ms_per_apply (HOST [4] or NULL) receives the
- * mean time per apply of each mode in that order. Allocates two temporary device vectors and
- * waits for the stream. Errors of the updates (HX_E_INVERTED, ...) are returned as they come. */
+/* Autotuner of the storage strategy alone (Section 7.2: which strategy is fastest depends on the
+ * hardware, degree and law and has to be measured), in the default configuration (the one the
+ * multigrid levels use). For each of NONE, FINV_J, TANGENT and SPATIAL: updates the slot of prec
+ * (HX_FP64, HX_FP32 or HX_FP32_BF16DATA) at u, applies once to warm up, then times `reps` applies (1..1000) of a
+ * fixed direction with HIP events on the stream. Leaves the slot linearised in the fastest mode,
+ * written to *best; ms_per_apply (HOST [4] or NULL) receives the mean time per apply of each mode
+ * in that order. Allocates two temporary device vectors and waits for the stream. Errors of the
+ * updates (HX_E_INVERTED, ...) are returned as they come. */
 hx_status hx_autotune_storage(hx_ctx ctx, const double* u, hx_precision prec, int32_t reps,
                               hx_storage* best, double* ms_per_apply, void* stream);
+
+/* One configuration timed by hx_autotune. */
+typedef struct {
+  hx_storage mode;
+  int32_t variant;              /* cells-per-workgroup variant (0 default, 1 alternative) */
+  int32_t cells_per_workgroup;  /* cells each workgroup of the variant processes */
+  int32_t nontemporal;          /* 1: the stored data is loaded with the non-temporal hint */
+  double ms;                    /* mean time per apply */
+} hx_tune_entry;
+
+/* Cells per workgroup of variant v (0 default, 1 alternative) of degree p, or -1. */
+int32_t hx_cells_per_workgroup(int32_t p, int32_t variant);
+
+/* Autotuner of the apply's configuration (Section 7.2: the fastest evaluation depends on the
+ * hardware, degree and law and has to be measured): for each storage mode (NONE, FINV_J,
+ * TANGENT, SPATIAL, SPATIAL_RECOMPUTE), each cells-per-workgroup variant (two on a lattice of trilinear cells, the
+ * default elsewhere; the stored data is laid out per variant) and, for the modes with stored
+ * data, both load policies of that data (plain or non-temporal), updates the slot of prec
+ * (HX_FP64 or HX_FP32) at u, applies once to warm up and times `reps` applies (1..1000) of a fixed
+ * direction with HIP events on the stream (SPATIAL_RECOMPUTE is timed like NONE). Records the
+ * fastest configuration of every mode as the
+ * context's choice, which later hx_update_linearization calls of that mode and precision class use,
+ * and leaves the slot linearised in the overall fastest one (*best). table (HOST, max_entries) or
+ * NULL receives every timed configuration, *n_entries (or NULL) their number (at most 16).
+ * Allocates two temporary device vectors and waits for the stream. */
+hx_status hx_autotune(hx_ctx ctx, const double* u, hx_precision prec, int32_t reps,
+                      hx_tune_entry* table, int32_t max_entries, int32_t* n_entries,
+                      hx_tune_entry* best, void* stream);
+
+/* Records a configuration for later updates of (precision class of prec, mode) without timing
+ * (for a choice read back from a stored table): variant 0 or 1 (1 only on a lattice of trilinear
+ * cells), nontemporal -1 (by the data size, the default), 0 or 1. HX_E_ARG otherwise. */
+hx_status hx_set_tuning(hx_ctx ctx, hx_precision prec, hx_storage mode, int32_t variant,
+                        int32_t nontemporal);
 
 /* Bytes of per-q-point data held by a slot (0 before its first update). */
 int64_t hx_linearization_bytes(hx_ctx ctx, hx_precision prec);
@@ -301,17 +347,20 @@ typedef struct {
                               eigenvalues of D^-1 A (default 20) */
   double eig_safety;       /* the estimate is multiplied by this factor (default 1.2) */
   hx_precision precision;  /* HX_FP32: levels apply in FP32 with FP32 stored data (the
-                              mixed-precision preconditioner); HX_FP32_BF16DATA / _FP16DATA: FP32
-                              vectors and arithmetic with 16-bit stored tangents on all levels
-                              but the coarsest (FP32); HX_FP64: everything in FP64 */
+                              mixed-precision preconditioner); HX_FP32_BF16DATA: FP32 vectors and
+                              arithmetic with bfloat16 stored data of the level mode on all levels
+                              but the coarsest (FP32); HX_FP32_FP16DATA: the same with binary16
+                              stored tangents (the level mode is then TANGENT); HX_FP64:
+                              everything in FP64 */
   int32_t use_graph;       /* 1: one V-cycle is captured into a HIP graph per update */
   hx_storage level_mode;   /* storage mode of the level operators inside the V-cycle: NONE,
-                              FINV_J, TANGENT (default), SPATIAL or AUTO (hx_autotune_storage on each
+                              FINV_J, TANGENT (default), SPATIAL, SPATIAL_RECOMPUTE or AUTO
+                              (hx_autotune_storage on each
                               level at the first update; the choice is kept). The inverse
                               diagonal always comes from a TANGENT update of the level. */
   int32_t coarse_solver;   /* coarsest level: 0 = dense if it has at most 8192 DoFs, else
                               Chebyshev (default); 1 = Chebyshev of coarse_degree; 2 = dense
-                              (HX_E_UNSUPPORTED above 8192 DoFs). Dense: the level operator is
+                              (HX_E_UNSUPPORTED above 32768 DoFs; 20 n^2 bytes of device memory). Dense: the level operator is
                               assembled by probing with 3 k_x k_y k_z coloured vectors (k_d >=
                               2p + 1 colours along direction d for a coarsest degree p, so that
                               no two coupled nodes share a colour), factored by Cholesky
@@ -371,8 +420,9 @@ typedef struct {
   int32_t max_krylov;
   int32_t load_steps;     /* the external load is applied in this many equal increments */
   hx_storage outer_mode;  /* storage mode of the FP64 outer operator with an FP32 hierarchy:
-                             NONE, FINV_J, TANGENT, SPATIAL or AUTO (hx_autotune_storage at the first
-                             linearisation, kept for the solve). An FP64 hierarchy shares the
+                             NONE, FINV_J, TANGENT, SPATIAL or AUTO (hx_autotune at the first
+                             linearisation: mode and configuration kept for the solve). An FP64
+                             hierarchy shares the
                              finest level's data with the outer operator and ignores it. */
   int32_t verbose;        /* 1: one progress line per Newton iteration on stderr */
 } hx_newton_opts;

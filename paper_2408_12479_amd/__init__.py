@@ -21,8 +21,9 @@ HX_OK = 0
 STATUS = {0: "HX_OK", 1: "HX_E_ARG", 2: "HX_E_HIP", 3: "HX_E_NOMEM", 4: "HX_E_STATE", 5: "HX_E_INVERTED",
           6: "HX_E_NONFINITE", 7: "HX_E_NOT_CONVERGED", 8: "HX_E_UNSUPPORTED"}
 LAWS = {"cnh": 0, "inh": 1, "fiber": 2}
-MODES = {"none": 0, "finv_j": 1, "tangent": 2, "spatial": 3, "auto": 255}
-MODE_NAMES = {0: "none", 1: "finv_j", 2: "tangent", 3: "spatial", 255: "auto"}
+MODES = {"none": 0, "finv_j": 1, "tangent": 2, "spatial": 3, "spatial_recompute": 4, "auto": 255}
+MODE_NAMES = {0: "none", 1: "finv_j", 2: "tangent", 3: "spatial", 4: "spatial_recompute", 255: "auto"}
+STORAGE_MODES = ("none", "finv_j", "tangent", "spatial", "spatial_recompute")
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_bf16": 2, "fp32_fp16": 3}
 
 
@@ -45,6 +46,16 @@ class _Mesh(ctypes.Structure):
                 ("vertices", ctypes.POINTER(ctypes.c_double)), ("cells", ctypes.POINTER(ctypes.c_int64)),
                 ("face_bid", ctypes.POINTER(ctypes.c_uint8)), ("geom_degree", ctypes.c_int32),
                 ("geom_nodes", ctypes.POINTER(ctypes.c_double)), ("frames", ctypes.POINTER(ctypes.c_double))]
+
+
+class _TuneEntry(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("variant", ctypes.c_int32), ("cells_per_workgroup", ctypes.c_int32),
+                ("nontemporal", ctypes.c_int32), ("ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"mode": MODE_NAMES[self.mode], "variant": int(self.variant),
+                "cells_per_workgroup": int(self.cells_per_workgroup), "nontemporal": int(self.nontemporal),
+                "ms": float(self.ms)}
 
 
 class _Material(ctypes.Structure):
@@ -97,12 +108,18 @@ def _load():
         "hx_node_coords": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double)]),
         "hx_constrained_mask": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_uint8)]),
         "hx_residual": (ctypes.c_int, [vp, vp, vp, vp]),
+        "hx_residual_spatial": (ctypes.c_int, [vp, vp, vp, vp]),
         "hx_update_linearization": (ctypes.c_int, [vp, vp, ctypes.c_int, ctypes.c_int, vp]),
         "hx_apply_tangent": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, vp]),
         "hx_apply_tangent_noalloc": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, vp]),
         "hx_linearization_bytes": (i64, [vp, ctypes.c_int]),
         "hx_autotune_storage": (ctypes.c_int, [vp, vp, ctypes.c_int, ctypes.c_int32, ctypes.POINTER(ctypes.c_int),
                                                ctypes.POINTER(ctypes.c_double), vp]),
+        "hx_autotune": (ctypes.c_int, [vp, vp, ctypes.c_int, ctypes.c_int32, ctypes.POINTER(_TuneEntry),
+                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_TuneEntry),
+                                       vp]),
+        "hx_set_tuning": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int32, ctypes.c_int32]),
+        "hx_cells_per_workgroup": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32]),
         "hx_mg_default_options": (ctypes.c_int, [ctypes.POINTER(_MgOptions)]),
         "hx_mg_level_mode": (ctypes.c_int32, [vp, ctypes.c_int32]),
         "hx_fiber_structure": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double]
@@ -264,11 +281,14 @@ class _Context:
             raise ValueError(f"{name} must be contiguous with {self.num_dofs} entries ([3][n_nodes])")
         return ctypes.c_void_p(t.data_ptr())
 
-    def residual(self, u, r=None, stream=None):
+    def residual(self, u, r=None, stream=None, form="material"):
+        """r~(u), integrated over the material (hx_residual) or the spatial configuration
+        (hx_residual_spatial)."""
         import torch
         r = torch.empty_like(u) if r is None else r
-        _check(lib.hx_residual(self.ctx, self._vec(u, torch.float64, "u"), self._vec(r, torch.float64, "r"),
-                               _stream_handle(stream)), self.ctx)
+        fn = {"material": lib.hx_residual, "spatial": lib.hx_residual_spatial}[form]
+        _check(fn(self.ctx, self._vec(u, torch.float64, "u"), self._vec(r, torch.float64, "r"), _stream_handle(stream)),
+               self.ctx)
         return r
 
     def update_linearization(self, u, mode="tangent", precision="fp64", stream=None):
@@ -304,6 +324,23 @@ class _Context:
         _check(lib.hx_autotune_storage(self.ctx, self._vec(u, torch.float64, "u"), PRECISIONS[precision], int(reps),
                                        ctypes.byref(best), _dptr(ms), _stream_handle(stream)), self.ctx)
         return MODE_NAMES[best.value], {"none": ms[0], "finv_j": ms[1], "tangent": ms[2], "spatial": ms[3]}
+
+    def autotune(self, u, precision="fp64", reps=20, stream=None):
+        """hx_autotune at u: (best configuration, every timed configuration) as dicts with mode,
+        variant, cells_per_workgroup, nontemporal and ms per apply. The choice per mode is kept by
+        the context for its later updates."""
+        import torch
+        table = (_TuneEntry * 16)()
+        n = ctypes.c_int32()
+        best = _TuneEntry()
+        _check(lib.hx_autotune(self.ctx, self._vec(u, torch.float64, "u"), PRECISIONS[precision], int(reps),
+                               table, 16, ctypes.byref(n), ctypes.byref(best), _stream_handle(stream)), self.ctx)
+        return best.as_dict(), [table[i].as_dict() for i in range(n.value)]
+
+    def set_tuning(self, mode, precision="fp64", variant=0, nontemporal=-1):
+        """hx_set_tuning: the configuration later updates of (precision class, mode) use."""
+        _check(lib.hx_set_tuning(self.ctx, PRECISIONS[precision], MODES[mode], int(variant), int(nontemporal)),
+               self.ctx)
 
     def surface_load(self, face, pressure):
         """Dead-load pressure vector on a lattice boundary face (0..5) or, on a general mesh, on the
@@ -477,3 +514,55 @@ class Multigrid:
         if check:
             _check_mg(st, self.mg)
         return out
+
+
+def cells_per_workgroup(p, variant=0):
+    """Cells per workgroup of a degree's variant (hx_cells_per_workgroup), -1 if none."""
+    return int(lib.hx_cells_per_workgroup(int(p), int(variant)))
+
+
+def tuning_key(p, law, precision, mode, mesh="lattice"):
+    """Key of a stored autotuner choice: degree, law, precision class, storage mode, mesh kind."""
+    return f"p{int(p)}/{law}/{'fp64' if precision == 'fp64' else 'fp32'}/{mode}/{mesh}"
+
+
+def load_tuning(path):
+    """The autotuner table stored at path (JSON {key: {variant, nontemporal, ms, ...}}), or {}."""
+    import json
+    if not path or not os.path.exists(path):
+        return {}
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def store_tuning(path, table):
+    """Writes the autotuner table (see load_tuning) to path as JSON."""
+    import json
+    tmp = path + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(table, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def autotune_with_table(op, u, law, precision="fp64", reps=20, path=None, mesh="lattice"):
+    """Tunes op at u, or, where the table at path holds the choice of every storage mode for this
+    (degree, law, precision, mesh kind), sets those choices without timing and updates the slot in
+    the stored best mode. Returns (best mode, table entries used) and stores new measurements."""
+    table = load_tuning(path)
+    keys = {m: tuning_key(op.p, law, precision, m, mesh) for m in STORAGE_MODES}
+    if all(k in table for k in keys.values()):
+        for m, k in keys.items():
+            op.set_tuning(m, precision, table[k]["variant"], table[k]["nontemporal"])
+        best = min(keys, key=lambda m: table[keys[m]]["ms"])
+        op.update_linearization(u, mode=best, precision=precision)
+        return best, {m: table[k] for m, k in keys.items()}
+    best, entries = op.autotune(u, precision, reps)
+    chosen = {}
+    for e in entries:
+        k = keys[e["mode"]]
+        if k not in chosen or e["ms"] < chosen[k]["ms"]:
+            chosen[k] = e
+    table.update(chosen)
+    if path:
+        store_tuning(path, table)
+    return best["mode"], {m: chosen[k] for m, k in keys.items()}

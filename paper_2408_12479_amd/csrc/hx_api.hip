@@ -203,14 +203,14 @@ hipError_t hx::dispatch(int p, const HostOp& op, const HostArgs& h, hipStream_t 
   return hipSuccess;
 }
 
-int hx::cells_per_block(int p) {
+int hx::cells_per_block(int p, int variant) {
   switch (p) {
-    case 1: return cells_per_block_p1();
-    case 2: return cells_per_block_p2();
-    case 3: return cells_per_block_p3();
-    case 4: return cells_per_block_p4();
-    case 5: return cells_per_block_p5();
-    case 6: return cells_per_block_p6();
+    case 1: return cells_per_block_p1(variant);
+    case 2: return cells_per_block_p2(variant);
+    case 3: return cells_per_block_p3(variant);
+    case 4: return cells_per_block_p4(variant);
+    case 5: return cells_per_block_p5(variant);
+    case 6: return cells_per_block_p6(variant);
     default: return 1;
   }
 }
@@ -730,21 +730,59 @@ hx_status hx_residual(hx_ctx ctx, const double* u, double* r, void* stream) {
   return HX_OK;
 }
 
+hx_status hx_residual_spatial(hx_ctx ctx, const double* u, double* r, void* stream) {
+  if (!ctx || !u || !r) return fail(ctx, HX_E_ARG, "hx_residual_spatial: NULL argument");
+  if (static_cast<const void*>(u) == static_cast<const void*>(r))
+    return fail(ctx, HX_E_ARG, "hx_residual_spatial: u and r alias");
+  HostArgs h = args_for(ctx);
+  h.in0 = u;
+  h.out = r;
+  HostOp op{OpKind::Residual, ctx->base.mat.law, HX_STORE_SPATIAL, kStoreF64, false};
+  bool ok = false;
+  const hipError_t e = dispatch(ctx->p, op, h, static_cast<hipStream_t>(stream), &ok);
+  if (!ok) return fail(ctx, HX_E_UNSUPPORTED, "hx_residual_spatial: not built");
+  if (e != hipSuccess) return hip_fail(ctx, e, "hx_residual_spatial: launch");
+  return HX_OK;
+}
+
 hx_status hx_update_linearization(hx_ctx ctx, const double* u, hx_storage mode, hx_precision prec,
                                   void* stream) {
   if (!ctx || !u) return fail(ctx, HX_E_ARG, "hx_update_linearization: NULL argument");
-  if (mode != HX_STORE_NONE && mode != HX_STORE_FINV_J && mode != HX_STORE_TANGENT && mode != HX_STORE_SPATIAL)
+  int variant = 0, nt = -1;
+  if (mode >= HX_STORE_NONE && mode < kModes && store_of(prec) >= 0) {
+    const Tuning& t = ctx->tuned[prec == HX_FP64 ? 0 : 1][mode];
+    if (t.set) {
+      variant = t.variant;
+      nt = t.nt;
+    }
+  }
+  return hx::update_linearization(ctx, u, mode, prec, stream, variant, nt);
+}
+
+}  // extern "C"
+
+hx_status hx::update_linearization(hx_ctx_s* ctx, const double* u, hx_storage mode, hx_precision prec,
+                                   void* stream, int variant, int nt) {
+  if (!ctx || !u) return fail(ctx, HX_E_ARG, "hx_update_linearization: NULL argument");
+  if (variant < 0 || variant >= kVariants || (variant != 0 && ctx->topo != kTopoLattice))
+    return fail(ctx, HX_E_ARG, "hx_update_linearization: cells-per-workgroup variant not available for this mesh");
+  if (mode != HX_STORE_NONE && mode != HX_STORE_FINV_J && mode != HX_STORE_TANGENT && mode != HX_STORE_SPATIAL &&
+      mode != HX_STORE_SPATIAL_RECOMPUTE)
     return fail(ctx, HX_E_ARG, "hx_update_linearization: unknown storage mode");
+  // the modes that re-interpolate the linearisation point at every apply keep a copy of it
+  const bool keeps_uk = mode == HX_STORE_NONE || mode == HX_STORE_SPATIAL_RECOMPUTE;
   const int st = store_of(prec);
   if (st < 0) return fail(ctx, HX_E_ARG, "hx_update_linearization: unknown precision");
-  if ((st == kStoreBF16 || st == kStoreF16) && mode != HX_STORE_TANGENT)
-    return fail(ctx, HX_E_UNSUPPORTED, "hx_update_linearization: 16-bit data only for the stored tangent");
+  // bfloat16 data (FP32 range) for every mode that stores data; binary16 (range limited, scaled per
+  // cell by a power of two) for the stored tangent only; the modes that store nothing run as FP32
+  if (st == kStoreF16 && (mode == HX_STORE_FINV_J || mode == HX_STORE_SPATIAL))
+    return fail(ctx, HX_E_UNSUPPORTED, "hx_update_linearization: binary16 data only for the stored tangent");
   hipStream_t s = static_cast<hipStream_t>(stream);
   Slot& sl = ctx->slot[prec == HX_FP64 ? 0 : 1];
   const Lattice& L = ctx->L;
   const int64_t Q = static_cast<int64_t>(ctx->p + 1) * (ctx->p + 1) * (ctx->p + 1);
   // whole workgroup blocks of cells (the last one may be partly unused)
-  const int64_t eb = cells_per_block(ctx->p);
+  const int64_t eb = cells_per_block(ctx->p, variant);
   const int64_t padded_cells = (L.n_cells + eb - 1) / eb * eb;
   const size_t need = static_cast<size_t>(mode_words(mode, ctx->base.mat.law)) * padded_cells * Q * store_bytes(st);
   hipError_t e = hipStreamSynchronize(s);  // the slot's buffers may still be in use
@@ -769,7 +807,7 @@ hx_status hx_update_linearization(hx_ctx ctx, const double* u, hx_storage mode, 
     }
   }
   const int64_t n = 3 * L.n_nodes;
-  if (mode == HX_STORE_NONE) {
+  if (keeps_uk) {
     const size_t ub = n * (prec == HX_FP64 ? sizeof(double) : sizeof(float));
     if (!sl.uk) {
       if ((e = hipMalloc(&sl.uk, ub)) != hipSuccess) {
@@ -784,7 +822,7 @@ hx_status hx_update_linearization(hx_ctx ctx, const double* u, hx_storage mode, 
   // FP32 recompute and F^-1+J modes of the fibre law: the tension switches are decided here in
   // FP64 and kept, so that the FP32 apply cannot flip them by rounding
   const bool keep_act = ctx->base.mat.law == HX_LAW_FIBER && prec != HX_FP64 &&
-                        (mode == HX_STORE_NONE || mode == HX_STORE_FINV_J);
+                        (keeps_uk || mode == HX_STORE_FINV_J);
   if (keep_act) {
     const size_t ab = static_cast<size_t>(padded_cells) * Q;
     if (sl.act_bytes < ab) {
@@ -804,6 +842,7 @@ hx_status hx_update_linearization(hx_ctx ctx, const double* u, hx_storage mode, 
   h.qdata_w = sl.qdata;
   h.cscale_w = sl.cscale;
   h.act_w = keep_act ? sl.act : nullptr;
+  h.variant = variant;
   HostOp op{OpKind::Update, ctx->base.mat.law, mode, st, false};
   bool ok = false;
   e = dispatch(ctx->p, op, h, s, &ok);
@@ -816,10 +855,14 @@ hx_status hx_update_linearization(hx_ctx ctx, const double* u, hx_storage mode, 
   sl.valid = true;
   sl.mode = mode;
   sl.store = st;
+  sl.variant = variant;
+  sl.nt = nt;
   if (flag & kFlagInverted) return fail(ctx, HX_E_INVERTED, "hx_update_linearization: J <= 0 at a q-point");
   if (flag & kFlagNonFinite) return fail(ctx, HX_E_NONFINITE, "hx_update_linearization: non-finite data");
   return HX_OK;
 }
+
+extern "C" {
 
 }  // extern "C"
 
@@ -843,8 +886,9 @@ hx_status apply_with(hx_ctx ctx, const void* du, void* dst, hx_precision prec, v
   h.out = dst;
   h.qdata = sl.qdata;
   // stored data larger than the last-level cache is streamed (non-temporal loads); smaller data
-  // may stay cached between applies
-  h.stream_qdata = sl.qbytes > (size_t(128) << 20) ? 1 : 0;
+  // may stay cached between applies (unless the autotuner chose otherwise)
+  h.stream_qdata = sl.nt >= 0 ? sl.nt : (sl.qbytes > (size_t(128) << 20) ? 1 : 0);
+  h.variant = sl.variant;
   h.cscale = sl.cscale;
   h.act = sl.keep_act ? sl.act : nullptr;
   HostOp op{OpKind::Apply, ctx->base.mat.law, sl.mode, sl.store, fp32};
@@ -880,64 +924,139 @@ hx_status hx_apply_tangent_noalloc(hx_ctx ctx, const void* du, void* dst, hx_pre
   return apply_with(ctx, du, dst, prec, stream, sp, "hx_apply_tangent_noalloc");
 }
 
-hx_status hx_autotune_storage(hx_ctx ctx, const double* u, hx_precision prec, int32_t reps,
-                              hx_storage* best, double* ms_per_apply, void* stream) {
-  if (!ctx || !u || !best) return fail(ctx, HX_E_ARG, "hx_autotune_storage: NULL argument");
-  if (prec != HX_FP64 && prec != HX_FP32)
-    return fail(ctx, HX_E_ARG, "hx_autotune_storage: precision must be HX_FP64 or HX_FP32");
-  if (reps < 1 || reps > 1000) return fail(ctx, HX_E_ARG, "hx_autotune_storage: reps out of [1, 1000]");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const int64_t n = 3 * ctx->L.n_nodes;
-  const size_t vb = n * (prec == HX_FP64 ? sizeof(double) : sizeof(float));
+}  // extern "C"
+
+namespace {
+
+// Timing buffers of the autotuners: a fixed direction, an output and two events.
+struct TuneBench {
+  hx_ctx ctx;
+  hx_precision prec;
+  hipStream_t s;
   void* du = nullptr;
   void* dst = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  hipError_t e = hipMalloc(&du, vb);
-  if (e == hipSuccess) e = hipMalloc(&dst, vb);
-  if (e == hipSuccess) e = hipEventCreate(&e0);
-  if (e == hipSuccess) e = hipEventCreate(&e1);
-  auto cleanup = [&]() {
+  ~TuneBench() {
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     if (du) (void)hipFree(du);
     if (dst) (void)hipFree(dst);
-  };
-  if (e != hipSuccess) {
-    cleanup();
-    return hip_fail(ctx, e, "hx_autotune_storage: allocation");
   }
-  if (prec == HX_FP64)
-    fill_timing_direction<double><<<grid_for(n), 256, 0, s>>>(static_cast<double*>(du), n);
-  else
-    fill_timing_direction<float><<<grid_for(n), 256, 0, s>>>(static_cast<float*>(du), n);
-  const hx_storage modes[4] = {HX_STORE_NONE, HX_STORE_FINV_J, HX_STORE_TANGENT, HX_STORE_SPATIAL};
-  double t[4] = {0.0, 0.0, 0.0, 0.0};
-  int arg = 3;
-  for (int k = 0; k < 4; ++k) {
-    hx_status st = hx_update_linearization(ctx, u, modes[k], prec, stream);
-    if (st == HX_OK) st = hx_apply_tangent(ctx, du, dst, prec, stream);  // warm-up
-    if (st != HX_OK) {
-      cleanup();
-      return st;
-    }
-    e = hipEventRecord(e0, s);
-    for (int r = 0; r < reps && st == HX_OK; ++r) st = hx_apply_tangent(ctx, du, dst, prec, stream);
+  hipError_t init() {
+    const int64_t n = 3 * ctx->L.n_nodes;
+    const size_t vb = n * (prec == HX_FP64 ? sizeof(double) : sizeof(float));
+    hipError_t e = hipMalloc(&du, vb);
+    if (e == hipSuccess) e = hipMalloc(&dst, vb);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) return e;
+    if (prec == HX_FP64)
+      fill_timing_direction<double><<<grid_for(n), 256, 0, s>>>(static_cast<double*>(du), n);
+    else
+      fill_timing_direction<float><<<grid_for(n), 256, 0, s>>>(static_cast<float*>(du), n);
+    return hipGetLastError();
+  }
+  // updates the slot in (mode, variant, nt), applies once to warm up, then times reps applies
+  hx_status time(const double* u, hx_storage mode, int variant, int nt, int reps, double* ms_out) {
+    hx_status st = hx::update_linearization(ctx, u, mode, prec, s, variant, nt);
+    if (st == HX_OK) st = hx_apply_tangent(ctx, du, dst, prec, s);
+    if (st != HX_OK) return st;
+    hipError_t e = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && st == HX_OK; ++r) st = hx_apply_tangent(ctx, du, dst, prec, s);
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.0f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    if (st != HX_OK || e != hipSuccess) {
-      cleanup();
-      return st != HX_OK ? st : hip_fail(ctx, e, "hx_autotune_storage: timing");
-    }
-    t[k] = ms / reps;
-    if (t[k] < t[arg] || k == 0) arg = k;
+    if (st != HX_OK) return st;
+    if (e != hipSuccess) return hip_fail(ctx, e, "autotuner: timing");
+    *ms_out = ms / reps;
+    return HX_OK;
   }
-  cleanup();
+};
+
+const hx_storage kTuneModes[5] = {HX_STORE_NONE, HX_STORE_FINV_J, HX_STORE_TANGENT, HX_STORE_SPATIAL,
+                                  HX_STORE_SPATIAL_RECOMPUTE};
+
+}  // namespace
+
+extern "C" {
+
+hx_status hx_autotune_storage(hx_ctx ctx, const double* u, hx_precision prec, int32_t reps,
+                              hx_storage* best, double* ms_per_apply, void* stream) {
+  if (!ctx || !u || !best) return fail(ctx, HX_E_ARG, "hx_autotune_storage: NULL argument");
+  if (prec != HX_FP64 && prec != HX_FP32 && prec != HX_FP32_BF16DATA)
+    return fail(ctx, HX_E_ARG, "hx_autotune_storage: precision must be HX_FP64, HX_FP32 or HX_FP32_BF16DATA");
+  if (reps < 1 || reps > 1000) return fail(ctx, HX_E_ARG, "hx_autotune_storage: reps out of [1, 1000]");
+  TuneBench tb{ctx, prec, static_cast<hipStream_t>(stream)};
+  const hipError_t e = tb.init();
+  if (e != hipSuccess) return hip_fail(ctx, e, "hx_autotune_storage: allocation");
+  double t[4] = {0.0, 0.0, 0.0, 0.0};
+  int arg = 0;
+  for (int k = 0; k < 4; ++k) {
+    // the default configuration (the multigrid's levels rely on it for their diagonal)
+    const hx_status st = tb.time(u, kTuneModes[k], 0, -1, reps, &t[k]);
+    if (st != HX_OK) return st;
+    if (t[k] < t[arg]) arg = k;
+  }
   if (ms_per_apply)
     for (int k = 0; k < 4; ++k) ms_per_apply[k] = t[k];
-  *best = modes[arg];
-  if (arg != 3) return hx_update_linearization(ctx, u, modes[arg], prec, stream);
+  *best = kTuneModes[arg];
+  if (arg != 3) return hx::update_linearization(ctx, u, kTuneModes[arg], prec, stream, 0, -1);
+  return HX_OK;
+}
+
+int32_t hx_cells_per_workgroup(int32_t p, int32_t variant) {
+  if (p < 1 || p > kMaxDegree || variant < 0 || variant >= kVariants) return -1;
+  return cells_per_block(p, variant);
+}
+
+hx_status hx_autotune(hx_ctx ctx, const double* u, hx_precision prec, int32_t reps, hx_tune_entry* table,
+                      int32_t max_entries, int32_t* n_entries, hx_tune_entry* best, void* stream) {
+  if (!ctx || !u || !best) return fail(ctx, HX_E_ARG, "hx_autotune: NULL argument");
+  if (prec != HX_FP64 && prec != HX_FP32) return fail(ctx, HX_E_ARG, "hx_autotune: precision must be HX_FP64 or HX_FP32");
+  if (reps < 1 || reps > 1000) return fail(ctx, HX_E_ARG, "hx_autotune: reps out of [1, 1000]");
+  if (table && max_entries < 0) return fail(ctx, HX_E_ARG, "hx_autotune: max_entries < 0");
+  TuneBench tb{ctx, prec, static_cast<hipStream_t>(stream)};
+  const hipError_t e = tb.init();
+  if (e != hipSuccess) return hip_fail(ctx, e, "hx_autotune: allocation");
+  const int cls = prec == HX_FP64 ? 0 : 1;
+  const int nvar = ctx->topo == kTopoLattice ? kVariants : 1;
+  int count = 0;
+  hx_tune_entry overall{};
+  overall.ms = -1.0;
+  for (int k = 0; k < 5; ++k) {
+    const hx_storage mode = kTuneModes[k];
+    const bool stored = mode != HX_STORE_NONE && mode != HX_STORE_SPATIAL_RECOMPUTE;
+    hx_tune_entry mode_best{};
+    mode_best.ms = -1.0;
+    for (int v = 0; v < nvar; ++v)
+      for (int nt = 0; nt < 2; ++nt) {
+        if (!stored && nt == 1) continue;  // no stored data to stream
+        double ms = 0.0;
+        const hx_status st = tb.time(u, mode, v, nt, reps, &ms);
+        if (st != HX_OK) return st;
+        hx_tune_entry en{mode, v, cells_per_block(ctx->p, v), nt, ms};
+        if (table && count < max_entries) table[count] = en;
+        ++count;
+        if (mode_best.ms < 0.0 || ms < mode_best.ms) mode_best = en;
+      }
+    ctx->tuned[cls][mode] = Tuning{true, mode_best.variant, mode_best.nontemporal};
+    if (overall.ms < 0.0 || mode_best.ms < overall.ms) overall = mode_best;
+  }
+  if (n_entries) *n_entries = count;
+  *best = overall;
+  return hx::update_linearization(ctx, u, overall.mode, prec, stream, overall.variant, overall.nontemporal);
+}
+
+hx_status hx_set_tuning(hx_ctx ctx, hx_precision prec, hx_storage mode, int32_t variant, int32_t nontemporal) {
+  if (!ctx) return HX_E_ARG;
+  if (prec != HX_FP64 && prec != HX_FP32 && prec != HX_FP32_BF16DATA && prec != HX_FP32_FP16DATA)
+    return fail(ctx, HX_E_ARG, "hx_set_tuning: unknown precision");
+  if (mode < HX_STORE_NONE || mode >= kModes) return fail(ctx, HX_E_ARG, "hx_set_tuning: unknown storage mode");
+  if (variant < 0 || variant >= kVariants || (variant != 0 && ctx->topo != kTopoLattice))
+    return fail(ctx, HX_E_ARG, "hx_set_tuning: variant not available for this mesh");
+  if (nontemporal < -1 || nontemporal > 1) return fail(ctx, HX_E_ARG, "hx_set_tuning: nontemporal out of [-1, 1]");
+  ctx->tuned[prec == HX_FP64 ? 0 : 1][mode] = Tuning{true, variant, nontemporal};
   return HX_OK;
 }
 

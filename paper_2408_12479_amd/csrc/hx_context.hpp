@@ -21,9 +21,21 @@ struct Slot {
   uint8_t* act = nullptr;  // fibre switches per q-point (FP32 slot, recompute and F^-1+J modes)
   size_t act_bytes = 0;
   bool keep_act = false;   // the apply reads act
+  int variant = 0;         // cells-per-workgroup variant the data is laid out for
+  int nt = -1;             // stored data loaded non-temporally: -1 by size, 0 no, 1 yes
 };
 
-int cells_per_block(int p);
+// Storage modes NONE .. SPATIAL_RECOMPUTE (the hx_storage values 0 .. kModes - 1).
+constexpr int kModes = 5;
+
+// A configuration the autotuner chose (or the caller set) for one storage mode of one slot.
+struct Tuning {
+  bool set = false;
+  int variant = 0;
+  int nt = -1;
+};
+
+int cells_per_block(int p, int variant = 0);
 hipError_t dispatch(int p, const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok);
 
 }  // namespace hx
@@ -59,6 +71,7 @@ struct hx_ctx_s {
   double* fib64 = nullptr;  // per-cell fibre tensors (frames given), else NULL
   float* fib32 = nullptr;
   hx::Slot slot[2];  // 0: FP64 class, 1: FP32 class
+  hx::Tuning tuned[2][hx::kModes];  // per slot and storage mode (hx_storage value)
   std::string err;
 };
 
@@ -75,6 +88,10 @@ hx_status finish_setup(hx_ctx_s* c, const hx_material* mat, const hx_options* op
 // error of a failed setup (read by hx_last_error(NULL))
 hx_status setup_fail(hx_status s, const std::string& msg);
 bool check_options(const hx_options* opt, const char* who);
+// the linearisation update in a given configuration (variant, non-temporal policy); the public
+// update uses the configuration recorded for the mode, the multigrid the default one
+hx_status update_linearization(hx_ctx_s* ctx, const double* u, hx_storage mode, hx_precision prec,
+                               void* stream, int variant, int nt);
 // stored geometry planes (K = J0^-1, w det J0 per q-point, FP64 and FP32) from c->geom_host;
 // HX_E_INVERTED if det J0 <= 0 at some Gauss point (message in c->err)
 hx_status build_stored_geometry(hx_ctx_s* c);

@@ -27,14 +27,22 @@ constexpr int TOPO = HX_TOPO;
 // Cells per workgroup: the workgroup holds EB * N^3 q-threads; chosen so that the thread count
 // is close to a multiple of the 64-wide wavefront. Q3 and Q4 take 4 cells: their pencil phases
 // (3 N^2 jobs per cell) then fill whole wavefronts better than with 2, which measured faster in
-// the stored-data modes; Q6 stays at one cell (two were slower).
-template <int n> struct Blocking { static constexpr int EB = 1; };
+// the stored-data modes; Q6 stays at one cell (two were slower). Variant 1 is the alternative the
+// autotuner times against the default on the lattice of trilinear cells (other meshes lay their
+// stored geometry and gather map out for the default).
+template <int n, int V = 0> struct Blocking { static constexpr int EB = 1; };
 template <> struct Blocking<2> { static constexpr int EB = 8; };   //  64 threads
 template <> struct Blocking<3> { static constexpr int EB = 7; };   // 189 of 192
 template <> struct Blocking<4> { static constexpr int EB = 4; };   // 256
 template <> struct Blocking<5> { static constexpr int EB = 4; };   // 500 of 512
 template <> struct Blocking<6> { static constexpr int EB = 1; };   // 216 of 256
 template <> struct Blocking<7> { static constexpr int EB = 1; };   // 343 of 384
+template <> struct Blocking<2, 1> { static constexpr int EB = 16; };  // 128
+template <> struct Blocking<3, 1> { static constexpr int EB = 9; };   // 243 of 256
+template <> struct Blocking<4, 1> { static constexpr int EB = 2; };   // 128
+template <> struct Blocking<5, 1> { static constexpr int EB = 2; };   // 250 of 256
+template <> struct Blocking<6, 1> { static constexpr int EB = 2; };   // 432 of 448
+template <> struct Blocking<7, 1> { static constexpr int EB = 2; };   // 686 of 704
 
 template <typename R>
 Consts<N, R> make_consts(const HostArgs& h) {
@@ -97,13 +105,13 @@ KernelArgs<N, R> make_args(const HostArgs& h) {
   return a;
 }
 
-template <typename R, int KIND, int MODE, int LAW, int S>
-hipError_t launch(const HostArgs& h, hipStream_t s) {
-  constexpr int EB = Blocking<N>::EB;
+template <typename R, int KIND, int MODE, int LAW, int S, int V = 0>
+hipError_t launch_v(const HostArgs& h, hipStream_t s) {
+  constexpr int EB = Blocking<N, V>::EB;
   const KernelArgs<N, R> a = make_args<R>(h);
   const int nblk = (h.L.n_cells + EB - 1) / EB;
   if (nblk == 0) return hipSuccess;
-  if constexpr (KIND == 0 && MODE != HX_STORE_NONE) {
+  if constexpr (KIND == 0 && MODE != HX_STORE_NONE && MODE != HX_STORE_SPATIAL_RECOMPUTE) {
     // stored data larger than the last-level cache: non-temporal loads (a separate instantiation,
     // since a run-time choice between the two loads is merged into one by the compiler)
     if (h.stream_qdata)
@@ -129,21 +137,38 @@ hipError_t launch(const HostArgs& h, hipStream_t s) {
   return hipGetLastError();
 }
 
+// the apply and the update of the lattice of trilinear cells come in two cells-per-workgroup variants
+template <typename R, int KIND, int MODE, int LAW, int S>
+hipError_t launch(const HostArgs& h, hipStream_t s) {
+#if HX_TOPO == 0
+  if constexpr (KIND == 0 || KIND == 2) {
+    if (h.variant == 1) return launch_v<R, KIND, MODE, LAW, S, 1>(h, s);
+  }
+#endif
+  return launch_v<R, KIND, MODE, LAW, S, 0>(h, s);
+}
+
 template <int LAW>
 hipError_t by_law(const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok) {
   *ok = true;
   switch (op.kind) {
     case OpKind::Residual:
+      // material form, or (mode SPATIAL) the spatial form
+      if (op.mode == HX_STORE_SPATIAL) return launch<double, 1, HX_STORE_SPATIAL, LAW, kStoreF64>(h, s);
       return launch<double, 1, HX_STORE_NONE, LAW, kStoreF64>(h, s);
     case OpKind::Update:
-      if (op.mode == HX_STORE_NONE) return launch<double, 2, HX_STORE_NONE, LAW, kStoreF64>(h, s);
+      // nothing stored: the update checks the state (and decides the fibre switches of FP32 applies)
+      if (op.mode == HX_STORE_NONE || op.mode == HX_STORE_SPATIAL_RECOMPUTE)
+        return launch<double, 2, HX_STORE_NONE, LAW, kStoreF64>(h, s);
       if (op.mode == HX_STORE_FINV_J) {
         if (op.store == kStoreF64) return launch<double, 2, HX_STORE_FINV_J, LAW, kStoreF64>(h, s);
         if (op.store == kStoreF32) return launch<double, 2, HX_STORE_FINV_J, LAW, kStoreF32>(h, s);
+        if (op.store == kStoreBF16) return launch<double, 2, HX_STORE_FINV_J, LAW, kStoreBF16>(h, s);
       }
       if (op.mode == HX_STORE_SPATIAL) {
         if (op.store == kStoreF64) return launch<double, 2, HX_STORE_SPATIAL, LAW, kStoreF64>(h, s);
         if (op.store == kStoreF32) return launch<double, 2, HX_STORE_SPATIAL, LAW, kStoreF32>(h, s);
+        if (op.store == kStoreBF16) return launch<double, 2, HX_STORE_SPATIAL, LAW, kStoreBF16>(h, s);
       }
       if (op.mode == HX_STORE_TANGENT) {
         switch (op.store) {
@@ -162,11 +187,17 @@ hipError_t by_law(const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok) 
         return op.fp32 ? launch<float, 0, HX_STORE_NONE, LAW, kStoreF32>(h, s)
                        : launch<double, 0, HX_STORE_NONE, LAW, kStoreF64>(h, s);
       }
+      if (op.mode == HX_STORE_SPATIAL_RECOMPUTE) {
+        return op.fp32 ? launch<float, 0, HX_STORE_SPATIAL_RECOMPUTE, LAW, kStoreF32>(h, s)
+                       : launch<double, 0, HX_STORE_SPATIAL_RECOMPUTE, LAW, kStoreF64>(h, s);
+      }
       if (op.mode == HX_STORE_FINV_J) {
         if (!op.fp32 && op.store == kStoreF64)
           return launch<double, 0, HX_STORE_FINV_J, LAW, kStoreF64>(h, s);
         if (op.fp32 && op.store == kStoreF32)
           return launch<float, 0, HX_STORE_FINV_J, LAW, kStoreF32>(h, s);
+        if (op.fp32 && op.store == kStoreBF16)
+          return launch<float, 0, HX_STORE_FINV_J, LAW, kStoreBF16>(h, s);
       }
 #if HX_TOPO != 1
       if (op.mode == HX_STORE_SPATIAL) {
@@ -176,6 +207,8 @@ hipError_t by_law(const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok) 
           return launch<double, 0, HX_STORE_SPATIAL, AL, kStoreF64>(h, s);
         if (op.fp32 && op.store == kStoreF32)
           return launch<float, 0, HX_STORE_SPATIAL, AL, kStoreF32>(h, s);
+        if (op.fp32 && op.store == kStoreBF16)
+          return launch<float, 0, HX_STORE_SPATIAL, AL, kStoreBF16>(h, s);
       }
 #endif
       break;
@@ -239,7 +272,9 @@ hipError_t apply_tangent_mode(const HostOp& op, const HostArgs& h, hipStream_t s
 
 #if HX_TOPO == 0
 // Cells per workgroup: the stored q-point data is laid out in blocks of this many cells.
-int HX_CAT(cells_per_block_p, HX_DEGREE)() { return Blocking<N>::EB; }
+int HX_CAT(cells_per_block_p, HX_DEGREE)(int variant) {
+  return variant == 1 ? Blocking<N, 1>::EB : Blocking<N>::EB;
+}
 
 // Writes the constant blocks of a context (synchronous; called once at setup).
 hipError_t HX_CAT(consts_p, HX_DEGREE)(const HostArgs& h) {
@@ -252,6 +287,11 @@ hipError_t HX_CAT(consts_p, HX_DEGREE)(const HostArgs& h) {
 #endif
 
 hipError_t HX_DISPATCH_NAME(HX_TOPO)(const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok) {
+  if (h.variant != 0 && (HX_TOPO != 0 || h.variant >= kVariants ||
+                         (op.kind != OpKind::Apply && op.kind != OpKind::Update))) {
+    *ok = false;
+    return hipSuccess;
+  }
 #if HX_TOPO == 1
   // a lattice with stored geometry: the operations that never read the geometry are those of the
   // lattice of trilinear cells

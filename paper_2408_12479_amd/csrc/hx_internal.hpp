@@ -121,9 +121,15 @@ struct HostOp {
   bool fp32;         // apply arithmetic and vector type (Apply only)
 };
 
+// Number of cells-per-workgroup variants of the lattice of trilinear cells.
+constexpr int kVariants = 2;
+
 struct HostArgs {
   Lattice L;
   int topo;             // Topo of the context
+  int variant;          // cells-per-workgroup variant of an apply or update (0 default, 1 the
+                        // alternative; lattices of trilinear cells only): the stored data is laid
+                        // out in blocks of that many cells
   const int32_t* map;   // kTopoMap: gather slot -> node (device)
   const int32_t* nptr;  // kTopoMap: node -> first entry of its slot list [n_nodes + 1] (device)
   const int32_t* nslot; // kTopoMap: slot lists, increasing within a node (device)
@@ -167,12 +173,12 @@ inline int mode_words(hx_storage m, hx_law law) {
 }
 
 // One per degree, defined in hx_degree.hip compiled with HX_DEGREE = p.
-int cells_per_block_p1();
-int cells_per_block_p2();
-int cells_per_block_p3();
-int cells_per_block_p4();
-int cells_per_block_p5();
-int cells_per_block_p6();
+int cells_per_block_p1(int variant);
+int cells_per_block_p2(int variant);
+int cells_per_block_p3(int variant);
+int cells_per_block_p4(int variant);
+int cells_per_block_p5(int variant);
+int cells_per_block_p6(int variant);
 hipError_t consts_p1(const HostArgs&);
 hipError_t consts_p2(const HostArgs&);
 hipError_t consts_p3(const HostArgs&);

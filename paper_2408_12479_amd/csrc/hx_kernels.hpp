@@ -1327,12 +1327,26 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
       return gq[9];
     }
   };
+  // J0 itself (the spatial data): from the vertices, or as the inverse of the stored J0^-1
+  auto jacobian_at = [&](const R* K, R* J0) {
+    if constexpr (!kGeoStored) {
+      qpoint_jacobian<N>(sv + le * 24, q, J0);
+    } else {
+      R A[9];
+      adj3(K, A);
+      const R inv = R(1) / (K[0] * A[0] + K[1] * A[3] + K[2] * A[6]);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) J0[i] = A[i] * inv;
+    }
+  };
   if constexpr (KIND == 2 && S == kStoreF16) {
     if (q == 0) sred[le] = 0.0f;
   }
 
   R g0[9], g1[9], t[9];
-  if constexpr (KIND == 0 && MODE == HX_STORE_NONE) {
+  // the apply modes that interpolate the linearisation point u_k at every apply
+  constexpr bool kRecompute = MODE == HX_STORE_NONE || MODE == HX_STORE_SPATIAL_RECOMPUTE;
+  if constexpr (KIND == 0 && kRecompute) {
     // linearisation point first (not masked), then the direction (masked)
     forward_vector<N, EB, false, TOPO>(a, sb, a.in1, e0, c0, le, q, g1);
     __syncthreads();
@@ -1385,6 +1399,26 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
 #pragma unroll
     for (int w = 0; w < W; ++w) d[w] = valid ? static_cast<R>(as_val(qv[w])) : R(0);
     spatial_action<LAW>(d, m, g0, t);
+  } else if constexpr (KIND == 0 && MODE == HX_STORE_SPATIAL_RECOMPUTE) {
+    // the spatial data formed from u_k at this apply, then the spatial action
+    R K[9], H[9], E[9];
+    const R wdet = geometry(K);
+    to_physical(g1, K, H);
+    QState<R> st;
+    if constexpr (kIsFiber<LAW>) {
+      if (a.act && valid) st.forced = a.act[static_cast<int64_t>(blk) * EBQ + qi];
+    }
+    state_from_H<LAW>(H, m, fb, st, E);
+    R J0[9];
+    jacobian_at(K, J0);
+    constexpr int WS = kSpatialWords<LAW>;
+    R d[WS];
+    spatial_words_at<LAW>(H, st, m, fb, J0, g1, wdet, d);
+    if (!valid) {
+#pragma unroll
+      for (int w = 0; w < WS; ++w) d[w] = R(0);
+    }
+    spatial_action<LAW>(d, m, g0, t);
   } else if constexpr (KIND == 0) {
     R K[9];
     const R wdet = geometry(K);
@@ -1414,13 +1448,26 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
     action<LAW>(st, m, fb, G, Pd);
     to_reference(Pd, K, wdet, t);
   } else if constexpr (KIND == 1) {
-    R K[9], H[9], E[9], P[9];
+    R K[9], H[9], E[9];
     const R wdet = geometry(K);
     to_physical(g0, K, H);
     QState<R> st;
     state_from_H<LAW>(H, m, fb, st, E);
-    stress_P<LAW>(st, E, m, fb, P);
-    to_reference(P, K, wdet, t);
+    if constexpr (MODE == HX_STORE_SPATIAL) {
+      // over the spatial configuration: t = w det J0 tau J_t^-T; the spatial data carries
+      // sqrt(w det J0) J_t^-1 and tau
+      R J0[9];
+      jacobian_at(K, J0);
+      constexpr int WS = kSpatialWords<LAW>;
+      R d[WS], tau[9];
+      spatial_words_at<LAW>(H, st, m, fb, J0, g0, wdet, d);
+      sym_to_full(d + 9, tau);
+      to_reference(tau, d, sqrt(wdet), t);
+    } else {
+      R P[9];
+      stress_P<LAW>(st, E, m, fb, P);
+      to_reference(P, K, wdet, t);
+    }
   } else {
     // linearisation update (always FP64 arithmetic)
     R K[9], H[9], E[9];
@@ -1493,16 +1540,7 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
       }
     } else if constexpr (MODE == HX_STORE_SPATIAL) {
       R J0[9], dw[W];
-      if constexpr (TOPO == kTopoLattice) {
-        qpoint_jacobian<N>(sv + le * 24, q, J0);
-      } else {
-        // J0 = K^-1 from the stored inverse
-        R A[9];
-        adj3(K, A);
-        const R inv = R(1) / (K[0] * A[0] + K[1] * A[3] + K[2] * A[6]);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) J0[i] = A[i] * inv;
-      }
+      jacobian_at(K, J0);
       spatial_words_at<LAW>(H, st, m, fb, J0, g0, wdet, dw);
       R chk = R(0);
 #pragma unroll

@@ -553,7 +553,10 @@ namespace {
 enum { B_B = 0, B_X, B_T, B_D, B_DINV, B_U, B_COUNT };
 
 // largest coarsest level (DoFs) that the dense coarse solve accepts
-constexpr int64_t kDenseCoarseMax = 8192;
+// the automatic choice takes the dense solve up to 8192 DoFs; asked for explicitly, up to 32768
+// (the factor, the identity/inverse and the FP32 or FP64 inverse take 20 n^2 bytes at most: 21 GB)
+constexpr int64_t kDenseCoarseAuto = 8192;
+constexpr int64_t kDenseCoarseMax = 32768;
 
 hx_status mg_fail(hx_mg mg, hx_status s, const std::string& m) {
   if (mg) mg->err = m;
@@ -800,6 +803,7 @@ hipError_t level_diagonal(hx_mg mg, int l) {
   T* dinv = mg->buf[l][B_DINV].as<T>();
   k_fill<T><<<grid_for(n), 256, 0, mg->stream>>>(dinv, T(0), n);
   const Slot& sl = c->slot[mg->fp32 ? 1 : 0];
+  if (sl.variant != 0) return hipErrorInvalidValue;  // the diagonal reads the default layout
   HostArgs h = args_for(c);
   h.out = dinv;
   h.qdata = sl.qdata;
@@ -851,7 +855,7 @@ hx_status hx_mg_create(const hx_ctx* levels, int32_t n_levels, const hx_mg_optio
     o = *opt;
     const bool mode_ok = o.level_mode == HX_STORE_NONE || o.level_mode == HX_STORE_FINV_J ||
                          o.level_mode == HX_STORE_TANGENT || o.level_mode == HX_STORE_SPATIAL ||
-                         o.level_mode == HX_STORE_AUTO;
+                         o.level_mode == HX_STORE_SPATIAL_RECOMPUTE || o.level_mode == HX_STORE_AUTO;
     if (o.smoother_degree < 1 || o.coarse_degree < 1 || o.eig_iters < 1 || !(o.smoothing_range > 1.0) ||
         !(o.eig_safety >= 1.0) ||
         (o.precision != HX_FP32 && o.precision != HX_FP64 && o.precision != HX_FP32_BF16DATA &&
@@ -869,7 +873,7 @@ hx_status hx_mg_create(const hx_ctx* levels, int32_t n_levels, const hx_mg_optio
     delete mg;
     return HX_E_UNSUPPORTED;
   }
-  mg->dense = o.coarse_solver == 2 || (o.coarse_solver == 0 && n_coarse <= kDenseCoarseMax);
+  mg->dense = o.coarse_solver == 2 || (o.coarse_solver == 0 && n_coarse <= kDenseCoarseAuto);
   // periodic flags: recovered from the lattice (periodic direction has N = n p)
   const Lattice& L0 = levels[0]->L;
   mg->periodic = (L0.Nx == L0.nx * L0.p ? 1 : 0) | (L0.Ny == L0.ny * L0.p ? 2 : 0) | (L0.Nz == L0.nz * L0.p ? 4 : 0);
@@ -954,15 +958,16 @@ hx_status hx_mg_update(hx_mg mg, const double* u, void* stream) {
   }
   for (int l = 0; l < L; ++l) {
     const hx_precision lp = level_prec(mg, l);
-    const hx_status st = hx_update_linearization(mg->lv[l], mg->buf[l][B_U].as<double>(), HX_STORE_TANGENT,
-                                                 lp, mg->stream);
+    // the default configuration: the diagonal kernel reads the tangent in its block layout
+    const hx_status st = hx::update_linearization(mg->lv[l], mg->buf[l][B_U].as<double>(), HX_STORE_TANGENT,
+                                                  lp, mg->stream, 0, -1);
     if (st != HX_OK) return mg_fail(mg, st, std::string("hx_mg_update: level update: ") + hx_last_error(mg->lv[l]));
     e = mg->fp32 ? level_diagonal<float>(mg, l) : level_diagonal<double>(mg, l);
     if (e != hipSuccess) return mg_fail(mg, HX_E_HIP, "hx_mg_update: diagonal");
-    // the level operator's own storage mode (the diagonal above needed the tangent)
-    // (16-bit data exists for the stored tangent only)
+    // the level operator's own storage mode (the diagonal above needed the tangent); binary16
+    // data exists for the stored tangent only
     hx_status sm = HX_OK;
-    if (sixteen_bit(lp)) {
+    if (lp == HX_FP32_FP16DATA) {
       mg->mode[l] = HX_STORE_TANGENT;
     } else if (mg->mode[l] < 0 && mg->opt.level_mode == HX_STORE_AUTO) {
       hx_storage best = HX_STORE_TANGENT;
@@ -971,8 +976,8 @@ hx_status hx_mg_update(hx_mg mg, const double* u, void* stream) {
     } else {
       if (mg->mode[l] < 0) mg->mode[l] = mg->opt.level_mode;
       if (mg->mode[l] != HX_STORE_TANGENT)
-        sm = hx_update_linearization(mg->lv[l], mg->buf[l][B_U].as<double>(), static_cast<hx_storage>(mg->mode[l]),
-                                     lp, mg->stream);
+        sm = hx::update_linearization(mg->lv[l], mg->buf[l][B_U].as<double>(), static_cast<hx_storage>(mg->mode[l]),
+                                      lp, mg->stream, 0, -1);
     }
     if (sm != HX_OK) return mg_fail(mg, sm, std::string("hx_mg_update: level mode: ") + hx_last_error(mg->lv[l]));
     double lm = 1.0, ln = 1.0;
@@ -1131,7 +1136,7 @@ hx_status hx_newton_solve(hx_mg mg, double* u, const double* f_ext, const hx_new
   hx_status status = HX_OK;
   const bool mode_ok = opt->outer_mode == HX_STORE_NONE || opt->outer_mode == HX_STORE_FINV_J ||
                        opt->outer_mode == HX_STORE_TANGENT || opt->outer_mode == HX_STORE_SPATIAL ||
-                       opt->outer_mode == HX_STORE_AUTO;
+                       opt->outer_mode == HX_STORE_SPATIAL_RECOMPUTE || opt->outer_mode == HX_STORE_AUTO;
   if (!mode_ok) return mg_fail(mg, HX_E_ARG, "hx_newton_solve: unknown outer_mode");
   int outer = opt->outer_mode == HX_STORE_AUTO ? -1 : opt->outer_mode;
   for (int step = 1; step <= opt->load_steps && status == HX_OK; ++step) {
@@ -1147,9 +1152,11 @@ hx_status hx_newton_solve(hx_mg mg, double* u, const double* f_ext, const hx_new
       // linearisation of the outer FP64 operator and of every multigrid level
       if (mg->fp32) {
         if (outer < 0) {
-          hx_storage best = HX_STORE_TANGENT;
-          status = hx_autotune_storage(fine, u, HX_FP64, 5, &best, nullptr, mg->stream);
-          outer = best;
+          // storage mode and configuration of the outer operator by the autotuner (recorded in the
+          // context, so that the following updates of that mode use the same configuration)
+          hx_tune_entry best{};
+          status = hx_autotune(fine, u, HX_FP64, 5, nullptr, 0, nullptr, &best, mg->stream);
+          outer = best.mode;
         } else {
           status = hx_update_linearization(fine, u, static_cast<hx_storage>(outer), HX_FP64, mg->stream);
         }

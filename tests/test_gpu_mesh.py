@@ -62,7 +62,8 @@ def _fields(pb, scale=0.05, seed=1):
     return u, du
 
 
-def _check(op, pb, modes=("none", "finv_j", "tangent", "spatial"), precisions=("fp64", "fp32")):
+def _check(op, pb, modes=("none", "finv_j", "tangent", "spatial", "spatial_recompute"),
+           precisions=("fp64", "fp32")):
     n = pb.mesh.n_nodes
     assert op.num_nodes == n
     np.testing.assert_allclose(op.node_coords(), pb.mesh.node_coords, rtol=0, atol=1e-13)
@@ -71,6 +72,7 @@ def _check(op, pb, modes=("none", "finv_j", "tangent", "spatial"), precisions=("
     ud = to_dev(u)
     rr = pb.residual(u)
     assert rel(to_host(op.residual(ud), n), rr) < 1e-12
+    assert rel(to_host(op.residual(ud, form="spatial"), n), rr) < 1e-12
     ref = pb.apply_tangent(u, du)
     for prec in precisions:
         dt = "float64" if prec == "fp64" else "float32"

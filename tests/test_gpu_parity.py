@@ -52,7 +52,8 @@ def test_config1_small_cube(device):
     ud, dud = to_dev(u), to_dev(du)
     r = to_host(op.residual(ud), op.num_nodes)
     assert rel(r, r_ref) < TOL64
-    for mode in ["none", "finv_j", "tangent", "spatial"]:
+    assert rel(to_host(op.residual(ud, form="spatial"), op.num_nodes), r_ref) < TOL64
+    for mode in ["none", "finv_j", "tangent", "spatial", "spatial_recompute"]:
         op.update_linearization(ud, mode=mode, precision="fp64")
         y = to_host(op.apply_tangent(dud, precision="fp64"), op.num_nodes)
         assert rel(y, Kdu_ref) < TOL64, mode
@@ -66,10 +67,13 @@ def test_fp64_all_modes(device, p, law):
     op, pb = make_pair((3, 2, 2), p, law, faces=(0, 5))
     u, du = _inputs(op, pb)
     ud, dud = to_dev(u), to_dev(du)
+    r_ref = pb.residual(u)
     r = to_host(op.residual(ud), op.num_nodes)
-    assert rel(r, pb.residual(u)) < TOL64
+    assert rel(r, r_ref) < TOL64
+    # the residual over the spatial configuration equals the material one (Section 2)
+    assert rel(to_host(op.residual(ud, form="spatial"), op.num_nodes), r_ref) < TOL64
     Kdu_ref = pb.apply_tangent(u, du)
-    for mode in ["none", "finv_j", "tangent", "spatial"]:
+    for mode in ["none", "finv_j", "tangent", "spatial", "spatial_recompute"]:
         op.update_linearization(ud, mode=mode, precision="fp64")
         y = to_host(op.apply_tangent(dud, precision="fp64"), op.num_nodes)
         assert rel(y, Kdu_ref) < TOL64, mode
@@ -84,8 +88,8 @@ def test_fp32_and_16bit_data(device, p, law):
     ud, du32 = to_dev(u), to_dev(du, "float32")
     Kdu_ref = pb.apply_tangent(u, du.astype(np.float32).astype(np.float64))
     bounds = {"fp32": TOL32, "fp32_bf16": 2e-2, "fp32_fp16": 3e-3}
-    for mode, precs in [("none", ["fp32"]), ("finv_j", ["fp32"]), ("spatial", ["fp32"]),
-                        ("tangent", ["fp32", "fp32_bf16", "fp32_fp16"])]:
+    for mode, precs in [("none", ["fp32"]), ("finv_j", ["fp32", "fp32_bf16"]), ("spatial", ["fp32", "fp32_bf16"]),
+                        ("spatial_recompute", ["fp32"]), ("tangent", ["fp32", "fp32_bf16", "fp32_fp16"])]:
         for prec in precs:
             op.update_linearization(ud, mode=mode, precision=prec)
             y = to_host(op.apply_tangent(du32, precision=prec), op.num_nodes)
@@ -133,9 +137,10 @@ def test_cell_frames_tube(device, p):
     u[:, pb.mesh.constrained] = 0.0
     ud, dud, du32 = to_dev(u), to_dev(du), to_dev(du, "float32")
     assert rel(to_host(op.residual(ud), op.num_nodes), pb.residual(u)) < TOL64
+    assert rel(to_host(op.residual(ud, form="spatial"), op.num_nodes), pb.residual(u)) < TOL64
     ref = pb.apply_tangent(u, du)
     ref32 = pb.apply_tangent(u, du.astype(np.float32).astype(np.float64))
-    for mode in ["none", "finv_j", "tangent", "spatial"]:
+    for mode in ["none", "finv_j", "tangent", "spatial", "spatial_recompute"]:
         op.update_linearization(ud, mode=mode, precision="fp64")
         assert rel(to_host(op.apply_tangent(dud), op.num_nodes), ref) < TOL64, mode
         op.update_linearization(ud, mode=mode, precision="fp32")
@@ -212,9 +217,11 @@ def test_error_paths(device):
     with pytest.raises(hx.HxError) as ei:
         op.update_linearization(to_dev(u), mode="tangent")
     assert ei.value.name == "HX_E_INVERTED"
-    with pytest.raises(hx.HxError) as ei:
-        op.update_linearization(to_dev(np.zeros_like(u)), mode="finv_j", precision="fp32_bf16")
-    assert ei.value.name == "HX_E_UNSUPPORTED"
+    # binary16 data exists for the stored tangent only (its words share one magnitude per cell)
+    for mode in ("finv_j", "spatial"):
+        with pytest.raises(hx.HxError) as ei:
+            op.update_linearization(to_dev(np.zeros_like(u)), mode=mode, precision="fp32_fp16")
+        assert ei.value.name == "HX_E_UNSUPPORTED"
     op.close()
     V = workloads.box_vertices(1, 1, 1)
     V[7] = [-1.0, -1.0, -1.0]
