@@ -366,6 +366,9 @@ typedef struct {
                               no two coupled nodes share a colour), factored by Cholesky
                               (rocSOLVER, FP64) at each update and applied as its explicit
                               inverse. */
+  int32_t fuse_smoother;   /* 1 (default): every Chebyshev step after the first, and the residual
+                              before the restriction, run in the node kernel of the level apply
+                              (no separate pass over the level vectors); 0: separate kernels */
 } hx_mg_options;
 
 /* Fills *opt with the defaults listed above. */
@@ -435,7 +438,11 @@ typedef struct {
 
 /* Solves r(u) = f_ext (Problem 2.1 with a dead load) by Newton's method with load stepping
  * (Algorithm 1), each step by flexible CG in FP64 on the finest FP64 operator preconditioned by
- * one V-cycle of mg. u: device FP64 [3][n_nodes], in/out (its constrained entries are the
+ * one V-cycle of mg. The CG scalars stay on the device: each iteration (apply, inner products,
+ * updates, V-cycle) is one graph launch when mg uses graphs, and the host reads the iteration
+ * count and stop flag every 4 iterations (iterations after the stopping one leave the iterate
+ * unchanged; report->vcycles counts the V-cycles run, report->krylov_iters the counted ones).
+ * u: device FP64 [3][n_nodes], in/out (its constrained entries are the
  * homogeneous Dirichlet data). f_ext: device FP64 [3][n_nodes] or NULL. Synchronous; returns
  * HX_E_NOT_CONVERGED if a load step does not reach its tolerance (u holds the last iterate). */
 hx_status hx_newton_solve(hx_mg mg, double* u, const double* f_ext, const hx_newton_opts* opt,

@@ -74,7 +74,7 @@ class _MgOptions(ctypes.Structure):
     _fields_ = [("smoother_degree", ctypes.c_int32), ("coarse_degree", ctypes.c_int32),
                 ("smoothing_range", ctypes.c_double), ("eig_iters", ctypes.c_int32),
                 ("eig_safety", ctypes.c_double), ("precision", ctypes.c_int), ("use_graph", ctypes.c_int32),
-                ("level_mode", ctypes.c_int), ("coarse_solver", ctypes.c_int32)]
+                ("level_mode", ctypes.c_int), ("coarse_solver", ctypes.c_int32), ("fuse_smoother", ctypes.c_int32)]
 
 
 class _NewtonOpts(ctypes.Structure):
@@ -432,14 +432,15 @@ class Multigrid:
     """p-multigrid V-cycle over operators on the same lattice with decreasing degrees."""
 
     def __init__(self, levels, smoother_degree=4, coarse_degree=30, smoothing_range=20.0, eig_iters=20,
-                 eig_safety=1.2, precision="fp32", use_graph=True, level_mode="tangent", coarse_solver="auto"):
+                 eig_safety=1.2, precision="fp32", use_graph=True, level_mode="tangent", coarse_solver="auto",
+                 fuse_smoother=True):
         """levels: Operators, finest first (see hx_mg_create for the allowed level pairs).
         coarse_solver: "auto" (dense up to 8192 DoFs), "chebyshev" or "dense"."""
         self.levels = list(levels)
         arr = (ctypes.c_void_p * len(self.levels))(*[op.ctx.value for op in self.levels])
         o = _MgOptions(int(smoother_degree), int(coarse_degree), float(smoothing_range), int(eig_iters),
                        float(eig_safety), PRECISIONS[precision], int(bool(use_graph)), MODES[level_mode],
-                       {"auto": 0, "chebyshev": 1, "dense": 2}[coarse_solver])
+                       {"auto": 0, "chebyshev": 1, "dense": 2}[coarse_solver], int(bool(fuse_smoother)))
         mg = ctypes.c_void_p()
         _check(lib.hx_mg_create(arr, len(self.levels), ctypes.byref(o), ctypes.byref(mg)))
         self.mg = mg

@@ -871,7 +871,7 @@ namespace {
 // The apply with a given element-vector buffer (the context's, or the static one).
 // (messages are formed only on failure: the successful path allocates nothing, host or device)
 hx_status apply_with(hx_ctx ctx, const void* du, void* dst, hx_precision prec, void* stream, void* ework,
-                     const char* who) {
+                     const char* who, const NodeEpilogue* epi = nullptr) {
   if (!ctx || !du || !dst) return fail(ctx, HX_E_ARG, std::string(who) + ": NULL argument");
   if (du == dst) return fail(ctx, HX_E_ARG, std::string(who) + ": du and dst alias");
   if (store_of(prec) < 0) return fail(ctx, HX_E_ARG, std::string(who) + ": unknown precision");
@@ -881,6 +881,7 @@ hx_status apply_with(hx_ctx ctx, const void* du, void* dst, hx_precision prec, v
   hipStream_t s = static_cast<hipStream_t>(stream);
   HostArgs h = args_for(ctx);
   h.ework = ework;
+  if (epi) h.epi = *epi;
   h.in0 = du;
   h.in1 = sl.uk;
   h.out = dst;
@@ -900,6 +901,11 @@ hx_status apply_with(hx_ctx ctx, const void* du, void* dst, hx_precision prec, v
 }
 
 }  // namespace
+
+hx_status hx::apply_with_epilogue(hx_ctx_s* ctx, const void* du, void* dst, hx_precision prec, void* stream,
+                                  const NodeEpilogue& epi) {
+  return apply_with(ctx, du, dst, prec, stream, ctx ? ctx->ework : nullptr, "level apply", &epi);
+}
 
 extern "C" {
 

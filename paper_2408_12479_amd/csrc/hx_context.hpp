@@ -88,6 +88,10 @@ hx_status finish_setup(hx_ctx_s* c, const hx_material* mat, const hx_options* op
 // error of a failed setup (read by hx_last_error(NULL))
 hx_status setup_fail(hx_status s, const std::string& msg);
 bool check_options(const hx_options* opt, const char* who);
+// the apply with a node-kernel epilogue (a Chebyshev step or the residual fused into the node
+// kernel; dst may be NULL for a Chebyshev step)
+hx_status apply_with_epilogue(hx_ctx_s* ctx, const void* du, void* dst, hx_precision prec, void* stream,
+                              const NodeEpilogue& epi);
 // the linearisation update in a given configuration (variant, non-temporal policy); the public
 // update uses the configuration recorded for the mode, the multigrid the default one
 hx_status update_linearization(hx_ctx_s* ctx, const double* u, hx_storage mode, hx_precision prec,

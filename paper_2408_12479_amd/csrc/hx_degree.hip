@@ -124,14 +124,20 @@ hipError_t launch_v(const HostArgs& h, hipStream_t s) {
   if constexpr (KIND == 0 || KIND == 1) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // every row: sum of the element vectors at the node; constrained rows du (apply) or 0
+    // every row: sum of the element vectors at the node; constrained rows du (apply) or 0; then the
+    // node epilogue of the apply (plain store, or a smoother step fused into the node kernel)
     const dim3 grid(static_cast<unsigned>((h.L.n_nodes + 255) / 256));
+    Epi<R> ep{};
+    if constexpr (KIND == 0) {
+      ep = Epi<R>{h.epi.kind, static_cast<const R*>(h.epi.b), static_cast<R*>(h.epi.x), static_cast<R*>(h.epi.d),
+                  static_cast<const R*>(h.epi.dinv), static_cast<R>(h.epi.c1), static_cast<R>(h.epi.c2)};
+    }
     if constexpr (TOPO == kTopoMap) {
       const int64_t ES = static_cast<int64_t>(nblk) * EB * N * N * N;
       assemble_map_kernel<R><<<grid, dim3(256), 0, s>>>(h.L.n_nodes, h.nptr, h.nslot, h.cmask, ES, a.ework,
-                                                         KIND == 0 ? a.in0 : nullptr, a.out);
+                                                         KIND == 0 ? a.in0 : nullptr, a.out, ep);
     } else {
-      assemble_kernel<N, R><<<grid, dim3(256), 0, s>>>(h.L, a.ework, KIND == 0 ? a.in0 : nullptr, a.out);
+      assemble_kernel<N, R><<<grid, dim3(256), 0, s>>>(h.L, a.ework, KIND == 0 ? a.in0 : nullptr, a.out, ep);
     }
   }
   return hipGetLastError();

@@ -124,8 +124,38 @@ struct HostOp {
 // Number of cells-per-workgroup variants of the lattice of trilinear cells.
 constexpr int kVariants = 2;
 
+// What the node kernel of an apply does with the assembled row t (the sum of the element vectors at
+// the node, or the input on constrained rows):
+//   kEpiStore      out = t
+//   kEpiChebyshev  d = c1 d + c2 dinv (b - t), x += d   (one Chebyshev step of the smoother, with x
+//                  the apply's input; out is not written)
+//   kEpiResidual   out = b - t                           (the residual of the smoothed iterate)
+//   kEpiChebyshevFirst  d = c2 dinv (b - t), x += d      (the first step from a nonzero iterate)
+enum EpiKind : int { kEpiStore = 0, kEpiChebyshev = 1, kEpiResidual = 2, kEpiChebyshevFirst = 3 };
+
+struct NodeEpilogue {
+  int kind;
+  const void* b;
+  void* x;
+  void* d;
+  const void* dinv;
+  double c1, c2;
+};
+
+// the same with the apply's arithmetic type, as the node kernel receives it
+template <typename R>
+struct Epi {
+  int kind;
+  const R* b;
+  R* x;
+  R* d;
+  const R* dinv;
+  R c1, c2;
+};
+
 struct HostArgs {
   Lattice L;
+  NodeEpilogue epi;     // node kernel of an apply (zero: plain store)
   int topo;             // Topo of the context
   int variant;          // cells-per-workgroup variant of an apply or update (0 default, 1 the
                         // alternative; lattices of trilinear cells only): the stored data is laid

@@ -933,9 +933,27 @@ __device__ __forceinline__ int cells_at(int Ig, int ncell, int Nn, int* cc, int*
 // the next row, so no lane idles at the end of a row). Every node gets the sum of the bricks of
 // the 1, 2, 4 or 8 cells that share it, in a fixed order (the apply is deterministic), or, on
 // constrained rows, cons_src (du of the apply: identity rows) or zero (residual).
+// the node kernel's last step on component row idx with assembled value t (see NodeEpilogue)
+template <typename R>
+__device__ __forceinline__ void node_epilogue(const Epi<R>& ep, int64_t idx, R t, R* __restrict__ out) {
+  if (ep.kind == kEpiChebyshev) {
+    const R di = ep.c1 * ep.d[idx] + ep.c2 * ep.dinv[idx] * (ep.b[idx] - t);
+    ep.d[idx] = di;
+    ep.x[idx] += di;
+  } else if (ep.kind == kEpiChebyshevFirst) {
+    const R di = ep.c2 * ep.dinv[idx] * (ep.b[idx] - t);
+    ep.d[idx] = di;
+    ep.x[idx] += di;
+  } else if (ep.kind == kEpiResidual) {
+    out[idx] = ep.b[idx] - t;
+  } else {
+    out[idx] = t;
+  }
+}
+
 template <int N, typename R>
 __global__ void __launch_bounds__(256) assemble_kernel(Lattice L, const R* __restrict__ E,
-                                                       const R* __restrict__ cons_src, R* __restrict__ out) {
+                                                       const R* cons_src, R* out, Epi<R> ep) {
   constexpr int P = N - 1;
   const int64_t n = L.n_nodes;
   // n_nodes < 2^31 (the setup bounds cells * (p+1)^3), so the index arithmetic is 32-bit
@@ -947,7 +965,7 @@ __global__ void __launch_bounds__(256) assemble_kernel(Lattice L, const R* __res
   const int K = static_cast<int>(row / static_cast<uint32_t>(L.Ny)), J = static_cast<int>(row) - K * L.Ny;
   if (cons_x(L, I) || cons_yz(L, J, K)) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) out[c * n + node] = cons_src ? cons_src[c * n + node] : R(0);
+    for (int c = 0; c < 3; ++c) node_epilogue(ep, c * n + node, cons_src ? cons_src[c * n + node] : R(0), out);
     return;
   }
   int cx[2], lx[2], cy[2], ly[2], cz[2], lz[2];
@@ -991,9 +1009,9 @@ __global__ void __launch_bounds__(256) assemble_kernel(Lattice L, const R* __res
       s2 += v[k][2][1];
     }
   }
-  out[node] = s0;
-  out[n + node] = s1;
-  out[2 * n + node] = s2;
+  node_epilogue(ep, node, s0, out);
+  node_epilogue(ep, n + node, s1, out);
+  node_epilogue(ep, 2 * n + node, s2, out);
 }
 
 // General meshes: one thread per node sums the element-vector slots of its list (increasing slot
@@ -1002,13 +1020,13 @@ template <typename R>
 __global__ void __launch_bounds__(256) assemble_map_kernel(int64_t n, const int32_t* __restrict__ nptr,
                                                            const int32_t* __restrict__ nslot,
                                                            const uint8_t* __restrict__ cmask, int64_t ES,
-                                                           const R* __restrict__ E, const R* __restrict__ cons_src,
-                                                           R* __restrict__ out) {
+                                                           const R* __restrict__ E, const R* cons_src,
+                                                           R* out, Epi<R> ep) {
   const int64_t node = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   if (node >= n) return;
   if (cmask[node]) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) out[c * n + node] = cons_src ? cons_src[c * n + node] : R(0);
+    for (int c = 0; c < 3; ++c) node_epilogue(ep, c * n + node, cons_src ? cons_src[c * n + node] : R(0), out);
     return;
   }
   const int s0 = nptr[node], s1 = nptr[node + 1];
@@ -1019,7 +1037,7 @@ __global__ void __launch_bounds__(256) assemble_map_kernel(int64_t n, const int3
     for (int c = 0; c < 3; ++c) s[c] += E[c * ES + sl];
   }
 #pragma unroll
-  for (int c = 0; c < 3; ++c) out[c * n + node] = s[c];
+  for (int c = 0; c < 3; ++c) node_epilogue(ep, c * n + node, s[c], out);
 }
 
 // ------------------------------------------------------------------------------------------

@@ -100,6 +100,50 @@ __global__ void k_dots(const T* a0, const T* b0, const T* a1, const T* b1, const
     for (int k = 0; k < npairs; ++k) unsafeAtomicAdd(out + k, red[k][0]);
 }
 
+// ---------------------------------------------------------------- PCG with device-side scalars
+// Scalars of the flexible PCG in device memory, so that an iteration needs no host round trip:
+// Scalars of the device-resident PCG: inner products of the running iteration, the stop flag
+// (1: loss of positive definiteness, the iterate is kept; 2: converged), the count of completed
+// iterations and the squared stopping threshold.
+enum { CG_RZ = 0, CG_PQ, CG_RR, CG_RZN, CG_RZO, CG_STOP, CG_ITERS, CG_TOL2, CG_COUNT };
+
+// x += alpha p, r -= alpha q with alpha = rz / pq; nothing moves once the iteration has stopped or
+// pq <= 0 (then the iterate is kept, as the host-driven loop does)
+__global__ void k_cg_alpha(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
+                           const double* __restrict__ q, const double* __restrict__ sc, int64_t n) {
+  const double pq = sc[CG_PQ];
+  if (sc[CG_STOP] != 0.0 || !(pq > 0.0)) return;
+  const double alpha = sc[CG_RZ] / pq;
+  HX_GRID_LOOP(i, n) {
+    x[i] += alpha * p[i];
+    r[i] -= alpha * q[i];
+  }
+}
+
+// p = z + beta p with the flexible (Polak-Ribiere) beta = (r.z - r.z_old) / rz
+__global__ void k_cg_beta(double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ sc,
+                          int64_t n) {
+  if (sc[CG_STOP] != 0.0 || !(sc[CG_PQ] > 0.0) || sc[CG_RZ] == 0.0) return;
+  const double beta = (sc[CG_RZN] - sc[CG_RZO]) / sc[CG_RZ];
+  HX_GRID_LOOP(i, n) p[i] = z[i] + beta * p[i];
+}
+
+// End of an iteration: count it, set the stop flag (pq <= 0, or ||r||^2 at or below the threshold),
+// rz <- r.z, and clear the accumulators of the next iteration's inner products.
+__global__ void k_cg_roll(double* sc) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (sc[CG_STOP] == 0.0) {
+    if (!(sc[CG_PQ] > 0.0)) {
+      sc[CG_STOP] = 1.0;
+    } else {
+      sc[CG_ITERS] += 1.0;
+      if (sc[CG_RR] <= sc[CG_TOL2]) sc[CG_STOP] = 2.0;
+      sc[CG_RZ] = sc[CG_RZN];
+    }
+  }
+  sc[CG_PQ] = sc[CG_RR] = sc[CG_RZN] = sc[CG_RZO] = 0.0;
+}
+
 __device__ __forceinline__ bool node_constrained(const Lattice& L, int64_t node) {
   const int I = static_cast<int>(node % L.Nx);
   const int J = static_cast<int>((node / L.Nx) % L.Ny);
@@ -541,6 +585,8 @@ struct hx_mg_s {
   std::string err;
   // Newton / Krylov work vectors (FP64, finest level)
   DevBuf r, x, p, q, z, zold, f;
+  DevBuf cg;                          // device scalars of the PCG (CG_*), with the ||r||^2 history
+  hipGraphExec_t cg_exec = nullptr;   // one PCG iteration, captured per linearisation
   // dense coarse solve: the coarsest operator is assembled by probing, factored by Cholesky and
   // kept as its explicit inverse (hierarchy precision)
   bool dense = false;
@@ -551,6 +597,9 @@ struct hx_mg_s {
 namespace {
 
 enum { B_B = 0, B_X, B_T, B_D, B_DINV, B_U, B_COUNT };
+
+// PCG iterations between two reads of the residual history by the host
+constexpr int kCgChunk = 4;
 
 // largest coarsest level (DoFs) that the dense coarse solve accepts
 // the automatic choice takes the dense solve up to 8192 DoFs; asked for explicitly, up to 32768
@@ -583,6 +632,16 @@ hipError_t level_apply(hx_mg mg, int l, const T* x, T* y) {
   return st == HX_OK ? hipSuccess : hipErrorLaunchFailure;
 }
 
+// The level apply followed, in its node kernel, by a smoother step or the residual (see
+// NodeEpilogue); y receives the residual (kEpiResidual) and is otherwise not written.
+template <typename T>
+hipError_t level_apply_epi(hx_mg mg, int l, T* x, T* y, int kind, const T* b, T* d, const T* dinv, double c1,
+                           double c2) {
+  const NodeEpilogue epi{kind, b, x, d, dinv, c1, c2};
+  const hx_status st = hx::apply_with_epilogue(mg->lv[l], x, y, level_prec(mg, l), mg->stream, epi);
+  return st == HX_OK ? hipSuccess : hipErrorLaunchFailure;
+}
+
 // Chebyshev-Jacobi on level l: x <- approximately A^-1 b, degree `deg`, starting from x (zero_init:
 // from 0). Eigenvalue interval [lmax / range, lmax] for smoothing; the coarse solve widens it down
 // to the smallest Ritz value (modes below the interval are still damped, never amplified).
@@ -603,17 +662,26 @@ hipError_t chebyshev(hx_mg mg, int l, int deg, bool zero_init) {
   const double sigma = theta / delta;
   double rho_old = 1.0 / sigma;
   hipError_t e;
+  const bool fuse = mg->opt.fuse_smoother != 0;
   if (zero_init) {
     k_cheb_first<T><<<grid_for(n), 256, 0, mg->stream>>>(x, d, b, nullptr, dinv, static_cast<T>(1.0 / theta), 1, n);
+  } else if (fuse) {
+    // the step in the apply's node kernel (no separate pass over the vectors)
+    if ((e = level_apply_epi<T>(mg, l, x, t, kEpiChebyshevFirst, b, d, dinv, 0.0, 1.0 / theta)) != hipSuccess)
+      return e;
   } else {
     if ((e = level_apply<T>(mg, l, x, t)) != hipSuccess) return e;
     k_cheb_first<T><<<grid_for(n), 256, 0, mg->stream>>>(x, d, b, t, dinv, static_cast<T>(1.0 / theta), 0, n);
   }
   for (int k = 1; k < deg; ++k) {
-    if ((e = level_apply<T>(mg, l, x, t)) != hipSuccess) return e;
     const double rho = 1.0 / (2.0 * sigma - rho_old);
-    k_cheb_step<T><<<grid_for(n), 256, 0, mg->stream>>>(x, d, b, t, dinv, static_cast<T>(rho * rho_old),
-                                                        static_cast<T>(2.0 * rho / delta), n);
+    const double c1 = rho * rho_old, c2 = 2.0 * rho / delta;
+    if (fuse) {
+      if ((e = level_apply_epi<T>(mg, l, x, t, kEpiChebyshev, b, d, dinv, c1, c2)) != hipSuccess) return e;
+    } else {
+      if ((e = level_apply<T>(mg, l, x, t)) != hipSuccess) return e;
+      k_cheb_step<T><<<grid_for(n), 256, 0, mg->stream>>>(x, d, b, t, dinv, static_cast<T>(c1), static_cast<T>(c2), n);
+    }
     rho_old = rho;
   }
   return hipGetLastError();
@@ -638,8 +706,14 @@ hipError_t vcycle_level(hx_mg mg, int l) {
   DevBuf* Bc = mg->buf[l + 1].get();
   const int64_t nf = 3 * cf->L.n_nodes, nc = 3 * cc->L.n_nodes;
   // t = b - A x (residual of the smoothed iterate)
-  if ((e = level_apply<T>(mg, l, Bf[B_X].as<T>(), Bf[B_T].as<T>())) != hipSuccess) return e;
-  k_axpby<T><<<grid_for(nf), 256, 0, mg->stream>>>(Bf[B_T].as<T>(), T(1), Bf[B_B].as<T>(), T(-1), nf);
+  if (mg->opt.fuse_smoother) {
+    if ((e = level_apply_epi<T>(mg, l, Bf[B_X].as<T>(), Bf[B_T].as<T>(), kEpiResidual, Bf[B_B].as<T>(), nullptr,
+                                nullptr, 0.0, 0.0)) != hipSuccess)
+      return e;
+  } else {
+    if ((e = level_apply<T>(mg, l, Bf[B_X].as<T>(), Bf[B_T].as<T>())) != hipSuccess) return e;
+    k_axpby<T><<<grid_for(nf), 256, 0, mg->stream>>>(Bf[B_T].as<T>(), T(1), Bf[B_B].as<T>(), T(-1), nf);
+  }
   k_fill<T><<<grid_for(nc), 256, 0, mg->stream>>>(Bc[B_B].as<T>(), T(0), nc);
   if ((e = transfer<T>(1, Bf[B_T].p, Bc[B_B].p, cf->L, cc->L, mg->periodic, mg->stream)) != hipSuccess) return e;
   if ((e = vcycle_level<T>(mg, l + 1)) != hipSuccess) return e;
@@ -861,7 +935,7 @@ hx_status hx_mg_create(const hx_ctx* levels, int32_t n_levels, const hx_mg_optio
         (o.precision != HX_FP32 && o.precision != HX_FP64 && o.precision != HX_FP32_BF16DATA &&
          o.precision != HX_FP32_FP16DATA) ||
         !mode_ok ||
-        o.coarse_solver < 0 || o.coarse_solver > 2) {
+        o.coarse_solver < 0 || o.coarse_solver > 2 || o.fuse_smoother < 0 || o.fuse_smoother > 1) {
       delete mg;
       return HX_E_ARG;
     }
@@ -919,6 +993,7 @@ hx_status hx_mg_default_options(hx_mg_options* o) {
   o->use_graph = 1;
   o->level_mode = HX_STORE_TANGENT;
   o->coarse_solver = 0;
+  o->fuse_smoother = 1;
   return HX_OK;
 }
 
@@ -932,6 +1007,7 @@ hx_status hx_mg_destroy(hx_mg mg) {
   if (mg->stream) (void)hipStreamSynchronize(mg->stream);
   if (mg->exec) (void)hipGraphExecDestroy(mg->exec);
   if (mg->graph) (void)hipGraphDestroy(mg->graph);
+  if (mg->cg_exec) (void)hipGraphExecDestroy(mg->cg_exec);
   if (mg->ev_in) (void)hipEventDestroy(mg->ev_in);
   if (mg->ev_out) (void)hipEventDestroy(mg->ev_out);
   if (mg->blas) (void)rocblas_destroy_handle(mg->blas);
@@ -1097,6 +1173,68 @@ static hx_status precondition(hx_mg mg, const double* r, double* z) {
   return hipGetLastError() == hipSuccess ? HX_OK : mg_fail(mg, HX_E_HIP, "precondition");
 }
 
+// The preconditioner's kernels enqueued directly (for the capture of a whole PCG iteration).
+static hx_status precondition_enqueue(hx_mg mg, const double* r, double* z) {
+  const int64_t n0 = 3 * mg->lv[0]->L.n_nodes;
+  DevBuf* B = mg->buf[0].get();
+  if (mg->fp32)
+    k_convert<double, float><<<grid_for(n0), 256, 0, mg->stream>>>(r, B[B_B].as<float>(), n0);
+  else
+    k_convert<double, double><<<grid_for(n0), 256, 0, mg->stream>>>(r, B[B_B].as<double>(), n0);
+  if (vcycle_enqueue(mg) != hipSuccess) return HX_E_HIP;
+  if (mg->fp32)
+    k_convert<float, double><<<grid_for(n0), 256, 0, mg->stream>>>(B[B_X].as<float>(), z, n0);
+  else
+    k_convert<double, double><<<grid_for(n0), 256, 0, mg->stream>>>(B[B_X].as<double>(), z, n0);
+  return hipGetLastError() == hipSuccess ? HX_OK : HX_E_HIP;
+}
+
+// One flexible PCG iteration (apply, inner products, updates, preconditioner) whose scalars live in
+// mg->cg: nothing in it waits for the host.
+static hx_status cg_iteration_enqueue(hx_mg mg, hx_ctx fine) {
+  const int64_t n = 3 * fine->L.n_nodes;
+  double* r = mg->r.as<double>();
+  double* x = mg->x.as<double>();
+  double* p = mg->p.as<double>();
+  double* q = mg->q.as<double>();
+  double* z = mg->z.as<double>();
+  double* zo = mg->zold.as<double>();
+  double* sc = mg->cg.as<double>();
+  const int dg = std::min(grid_for(n), 1024);
+  hx_status st = hx_apply_tangent(fine, p, q, HX_FP64, mg->stream);
+  if (st != HX_OK) return st;
+  k_dots<double><<<dg, 256, 0, mg->stream>>>(p, q, nullptr, nullptr, nullptr, nullptr, 1, sc + CG_PQ, n);
+  k_cg_alpha<<<grid_for(n), 256, 0, mg->stream>>>(x, r, p, q, sc, n);
+  k_dots<double><<<dg, 256, 0, mg->stream>>>(r, r, nullptr, nullptr, nullptr, nullptr, 1, sc + CG_RR, n);
+  k_convert<double, double><<<grid_for(n), 256, 0, mg->stream>>>(z, zo, n);
+  if ((st = precondition_enqueue(mg, r, z)) != HX_OK) return st;
+  k_dots<double><<<dg, 256, 0, mg->stream>>>(r, z, r, zo, nullptr, nullptr, 2, sc + CG_RZN, n);
+  k_cg_beta<<<grid_for(n), 256, 0, mg->stream>>>(p, z, sc, n);
+  k_cg_roll<<<1, 64, 0, mg->stream>>>(sc);
+  return hipGetLastError() == hipSuccess ? HX_OK : HX_E_HIP;
+}
+
+// Captures cg_iteration_enqueue into mg->cg_exec (the buffers of the current linearisation).
+static hx_status capture_cg_iteration(hx_mg mg, hx_ctx fine) {
+  if (mg->cg_exec) {
+    (void)hipGraphExecDestroy(mg->cg_exec);
+    mg->cg_exec = nullptr;
+  }
+  hipError_t e = hipStreamSynchronize(mg->stream);
+  if (e == hipSuccess) e = hipStreamBeginCapture(mg->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return HX_E_HIP;
+  const hx_status st = cg_iteration_enqueue(mg, fine);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(mg->stream, &g);
+  if (st != HX_OK || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return st != HX_OK ? st : HX_E_HIP;
+  }
+  e = hipGraphInstantiate(&mg->cg_exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  return e == hipSuccess ? HX_OK : HX_E_HIP;
+}
+
 hx_status hx_newton_solve(hx_mg mg, double* u, const double* f_ext, const hx_newton_opts* opt,
                           hx_newton_report* rep, void* stream) {
   if (!mg || !u || !opt) return HX_E_ARG;
@@ -1110,6 +1248,8 @@ hx_status hx_newton_solve(hx_mg mg, double* u, const double* f_ext, const hx_new
   DevBuf* W[] = {&mg->r, &mg->x, &mg->p, &mg->q, &mg->z, &mg->zold, &mg->f};
   for (DevBuf* b : W)
     if ((e = b->alloc(nb)) != hipSuccess) return mg_fail(mg, HX_E_NOMEM, "hx_newton_solve: work vectors");
+  if ((e = mg->cg.alloc(CG_COUNT * sizeof(double))) != hipSuccess)
+    return mg_fail(mg, HX_E_NOMEM, "hx_newton_solve: scalars");
   hipStream_t caller = static_cast<hipStream_t>(stream);
   if ((e = hipEventRecord(mg->ev_in, caller)) != hipSuccess || (e = hipStreamWaitEvent(mg->stream, mg->ev_in, 0)) != hipSuccess)
     return mg_fail(mg, HX_E_HIP, "hx_newton_solve: stream order");
@@ -1122,7 +1262,7 @@ hx_status hx_newton_solve(hx_mg mg, double* u, const double* f_ext, const hx_new
   double* f = mg->f.as<double>();
   hx_newton_report R{};
   const int vc0 = mg->vcycles;
-  double h[3];
+  double h[CG_COUNT];
   auto residual = [&](double scale) -> hx_status {
     hx_status st = hx_residual(fine, u, r, mg->stream);
     if (st != HX_OK) return st;
@@ -1163,36 +1303,48 @@ hx_status hx_newton_solve(hx_mg mg, double* u, const double* f_ext, const hx_new
         if (status != HX_OK) break;
       }
       if ((status = hx_mg_update(mg, u, mg->stream)) != HX_OK) break;
-      // flexible PCG on K dx = -r
+      // flexible PCG on K dx = -r; the scalars stay on the device, every iteration is one graph
+      // launch, and the host reads the residual history every kCgChunk iterations
       k_fill<double><<<grid_for(n), 256, 0, mg->stream>>>(x, 0.0, n);
       k_axpby<double><<<grid_for(n), 256, 0, mg->stream>>>(r, 0.0, r, -1.0, n);  // r <- -r (the right-hand side)
       if ((status = precondition(mg, r, z)) != HX_OK) break;
       k_convert<double, double><<<grid_for(n), 256, 0, mg->stream>>>(z, p, n);
-      if ((e = dots<double>(mg, n, 2, r, z, r, r, nullptr, nullptr, h)) != hipSuccess) { status = HX_E_HIP; break; }
-      double rz = h[0];
-      const double bn = std::sqrt(h[1]);
-      const double tol = opt->krylov_rel_tol * bn;
+      double* sc = mg->cg.as<double>();
+      k_fill<double><<<1, 64, 0, mg->stream>>>(sc, 0.0, CG_COUNT);
+      {
+        const int dg = std::min(grid_for(n), 1024);
+        k_dots<double><<<dg, 256, 0, mg->stream>>>(r, z, nullptr, nullptr, nullptr, nullptr, 1, sc + CG_RZ, n);
+        k_dots<double><<<dg, 256, 0, mg->stream>>>(r, r, nullptr, nullptr, nullptr, nullptr, 1, sc + CG_RR, n);
+      }
+      if ((e = hipMemcpyAsync(h, sc, CG_COUNT * sizeof(double), hipMemcpyDeviceToHost, mg->stream)) != hipSuccess ||
+          (e = hipStreamSynchronize(mg->stream)) != hipSuccess) {
+        status = HX_E_HIP;
+        break;
+      }
+      const double tol = opt->krylov_rel_tol * std::sqrt(h[CG_RR]);
+      k_fill<double><<<1, 64, 0, mg->stream>>>(sc + CG_RR, 0.0, 1);
+      k_fill<double><<<1, 64, 0, mg->stream>>>(sc + CG_TOL2, tol * tol, 1);
+      // the graph holds the buffers of this linearisation: captured again at every Newton step
+      if (mg->opt.use_graph && (status = capture_cg_iteration(mg, fine)) != HX_OK) break;
       int k = 0;
-      for (; k < opt->max_krylov; ++k) {
-        const hx_precision op = HX_FP64;
-        if ((status = hx_apply_tangent(fine, p, q, op, mg->stream)) != HX_OK) break;
-        if ((e = dots<double>(mg, n, 1, p, q, nullptr, nullptr, nullptr, nullptr, h)) != hipSuccess) { status = HX_E_HIP; break; }
-        const double pq = h[0];
-        if (!(pq > 0.0)) break;  // loss of positive definiteness: keep the current iterate
-        const double alpha = rz / pq;
-        k_axpby<double><<<grid_for(n), 256, 0, mg->stream>>>(x, alpha, p, 1.0, n);
-        k_axpby<double><<<grid_for(n), 256, 0, mg->stream>>>(r, -alpha, q, 1.0, n);
-        if ((e = dots<double>(mg, n, 1, r, r, nullptr, nullptr, nullptr, nullptr, h)) != hipSuccess) { status = HX_E_HIP; break; }
-        if (std::sqrt(h[0]) <= tol) {
-          ++k;
+      double stop = 0.0;
+      while (stop == 0.0 && k < opt->max_krylov) {
+        const int m = std::min(kCgChunk, opt->max_krylov - k);
+        for (int i = 0; i < m && status == HX_OK; ++i) {
+          if (mg->cg_exec && mg->opt.use_graph)
+            status = hipGraphLaunch(mg->cg_exec, mg->stream) == hipSuccess ? HX_OK : HX_E_HIP;
+          else
+            status = cg_iteration_enqueue(mg, fine);
+        }
+        mg->vcycles += m;
+        if (status != HX_OK) break;
+        if ((e = hipMemcpyAsync(h, sc, CG_COUNT * sizeof(double), hipMemcpyDeviceToHost, mg->stream)) != hipSuccess ||
+            (e = hipStreamSynchronize(mg->stream)) != hipSuccess) {
+          status = HX_E_HIP;
           break;
         }
-        k_convert<double, double><<<grid_for(n), 256, 0, mg->stream>>>(z, zo, n);
-        if ((status = precondition(mg, r, z)) != HX_OK) break;
-        if ((e = dots<double>(mg, n, 2, r, z, r, zo, nullptr, nullptr, h)) != hipSuccess) { status = HX_E_HIP; break; }
-        const double beta = (h[0] - h[1]) / rz;  // flexible (Polak-Ribiere) update
-        rz = h[0];
-        k_axpby<double><<<grid_for(n), 256, 0, mg->stream>>>(p, 1.0, z, beta, n);
+        k = static_cast<int>(h[CG_ITERS]);
+        stop = h[CG_STOP];
       }
       if (status != HX_OK) break;
       R.krylov_iters += k;
