@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--no-newton", action="store_true")
     ap.add_argument("--newton-cells", default="32,16,400")
     ap.add_argument("--newton-bf16", action="store_true", help="also solve with BF16-stored multigrid levels")
+    ap.add_argument("--mg-variants", default="graph,eager,graph_fp32_bf16,graph_unfused",
+                    help="V-cycle variants of the tube study (graph, eager, graph_fp32_bf16, graph_unfused)")
     return ap.parse_args()
 
 
@@ -406,7 +408,8 @@ def main():
     if not args.no_stability:
         study("forward_stability", lambda: stability_study(hx, workloads, torch))
     if not args.no_mg:
-        study("tube_vcycle_p6321", lambda: mg_study(hx, workloads, torch, dev, timer))
+        study("tube_vcycle_p6321", lambda: mg_study(hx, workloads, torch, dev, timer,
+                                                    variants=args.mg_variants.split(",")))
     if not args.no_newton:
         cells = tuple(int(c) for c in args.newton_cells.split(","))
         study("tube_newton_q4", lambda: newton_study(hx, workloads, torch, dev, cells=cells, bf16=args.newton_bf16))
@@ -594,10 +597,20 @@ def tube_twist(op, amp=0.05):
     return np.stack([c * dx - sn * y - dx, sn * dx + c * y - y, np.zeros_like(s)])
 
 
-def mg_study(hx, workloads, torch, dev, timer, cells=(16, 8, 200), degrees=(6, 3, 2, 1), reps=20):
-    """FP32 p-multigrid V-cycle on the tube: graph-captured vs eager time per V-cycle, the storage
-    mode the autotuner picked per level, and the measured convergence factor of the stationary
-    iteration x <- x + M (b - K x) with the FP64 fine operator."""
+MG_VARIANTS = {  # name: (graph capture, precision, Chebyshev steps fused into the node kernels)
+    "graph": (True, "fp32", True),
+    "eager": (False, "fp32", True),
+    "graph_fp32_bf16": (True, "fp32_bf16", True),
+    "graph_unfused": (True, "fp32", False),
+}
+
+
+def mg_study(hx, workloads, torch, dev, timer, cells=(16, 8, 200), degrees=(6, 3, 2, 1), reps=20,
+             variants=tuple(MG_VARIANTS)):
+    """FP32 p-multigrid V-cycle on the tube: graph-captured vs eager time per V-cycle, fused vs
+    separate smoother kernels, the storage mode the autotuner picked per level, and the measured
+    convergence factor of the stationary iteration x <- x + M (b - K x) with the FP64 fine
+    operator."""
     ops = tube_hierarchy(hx, workloads, cells, degrees)
     u = tube_twist(ops[0])
     ud = torch.tensor(u.reshape(-1), dtype=torch.float64, device=dev)
@@ -609,17 +622,17 @@ def mg_study(hx, workloads, torch, dev, timer, cells=(16, 8, 200), degrees=(6, 3
     bd = torch.tensor(b, dtype=torch.float64, device=dev)
     out = {"cells": list(cells), "levels": [[op.p, op.num_cells, op.num_dofs] for op in ops],
            "geometry": f"isoparametric: every level's cells map by the tube's map at degree {degrees[0]}"}
-    for use_graph, prec in ((True, "fp32"), (False, "fp32"), (True, "fp32_bf16")):
-        mg = hx.Multigrid(ops, precision=prec, use_graph=use_graph, level_mode="auto")
+    for key in variants:
+        use_graph, prec, fuse = MG_VARIANTS[key]
+        mg = hx.Multigrid(ops, precision=prec, use_graph=use_graph, level_mode="auto", fuse_smoother=fuse)
         t0 = time.perf_counter()
         mg.update(ud)
         t_upd = time.perf_counter() - t0
         r32 = bd.float()
         z = mg.vcycle(r32)
         ms = timer.time(lambda: mg.vcycle(r32, z), reps)
-        key = ("graph" if use_graph else "eager") + ("" if prec == "fp32" else "_" + prec)
         out[f"vcycle_ms_{key}"] = ms
-        if use_graph and prec == "fp32":
+        if key == "graph":
             # the finest level's FP32 apply on its own: the V-cycle's dominant cost, against the
             # HBM roof with its algorithmic bytes (stored data + direction read + output write)
             x32 = torch.randn(n, device=dev, dtype=torch.float32)
@@ -628,7 +641,7 @@ def mg_study(hx, workloads, torch, dev, timer, cells=(16, 8, 200), degrees=(6, 3
             fine_bytes = ops[0].linearization_bytes("fp32") + 2 * 4 * n
             out["finest_apply_fp32"] = {"mode": mg.level_mode(0), "ms": t_fine, "bytes": fine_bytes,
                                         "hbm_frac": fine_bytes / (t_fine * 1e-3) / 1e9 / HBM_PEAK_GBS}
-        if use_graph:
+        if key in ("graph", "graph_fp32_bf16"):
             sfx = "" if prec == "fp32" else "_" + prec
             out["update_s" + sfx] = t_upd
             out["level_modes" + sfx] = [mg.level_mode(l) for l in range(len(ops))]

@@ -934,21 +934,48 @@ __device__ __forceinline__ int cells_at(int Ig, int ncell, int Nn, int* cc, int*
 // the 1, 2, 4 or 8 cells that share it, in a fixed order (the apply is deterministic), or, on
 // constrained rows, cons_src (du of the apply: identity rows) or zero (residual).
 // the node kernel's last step on component row idx with assembled value t (see NodeEpilogue)
+// The epilogue's operands at one component row (b, the inverse diagonal, the previous direction
+// and x), requested before the node's bricks so that their memory latency overlaps the brick loads.
 template <typename R>
-__device__ __forceinline__ void node_epilogue(const Epi<R>& ep, int64_t idx, R t, R* __restrict__ out) {
+struct EpiIn {
+  R b, dinv, d, x;
+};
+
+template <typename R>
+__device__ __forceinline__ EpiIn<R> epi_load(const Epi<R>& ep, int64_t idx) {
+  EpiIn<R> v{R(0), R(0), R(0), R(0)};
+  if (ep.kind == kEpiStore) return v;
+  v.b = ep.b[idx];
+  if (ep.kind == kEpiChebyshev || ep.kind == kEpiChebyshevFirst) {
+    v.dinv = ep.dinv[idx];
+    v.x = ep.x[idx];
+    if (ep.kind == kEpiChebyshev) v.d = ep.d[idx];
+  }
+  return v;
+}
+
+// the node kernel's last step on component row idx with assembled value t (see NodeEpilogue)
+template <typename R>
+__device__ __forceinline__ void node_epilogue(const Epi<R>& ep, int64_t idx, R t, R* __restrict__ out,
+                                              const EpiIn<R>& v) {
   if (ep.kind == kEpiChebyshev) {
-    const R di = ep.c1 * ep.d[idx] + ep.c2 * ep.dinv[idx] * (ep.b[idx] - t);
+    const R di = ep.c1 * v.d + ep.c2 * v.dinv * (v.b - t);
     ep.d[idx] = di;
-    ep.x[idx] += di;
+    ep.x[idx] = v.x + di;
   } else if (ep.kind == kEpiChebyshevFirst) {
-    const R di = ep.c2 * ep.dinv[idx] * (ep.b[idx] - t);
+    const R di = ep.c2 * v.dinv * (v.b - t);
     ep.d[idx] = di;
-    ep.x[idx] += di;
+    ep.x[idx] = v.x + di;
   } else if (ep.kind == kEpiResidual) {
-    out[idx] = ep.b[idx] - t;
+    out[idx] = v.b - t;
   } else {
     out[idx] = t;
   }
+}
+
+template <typename R>
+__device__ __forceinline__ void node_epilogue(const Epi<R>& ep, int64_t idx, R t, R* __restrict__ out) {
+  node_epilogue(ep, idx, t, out, epi_load(ep, idx));
 }
 
 template <int N, typename R>
@@ -979,6 +1006,7 @@ __global__ void __launch_bounds__(256) assemble_kernel(Lattice L, const R* __res
   const int x1 = nxc > 1 ? cx[1] * N + lx[1] : x0;
   // all loads are issued before the first sum: summing each value as it arrives would wait for
   // up to eight memory round trips one after the other
+  const EpiIn<R> pre[3] = {epi_load(ep, node), epi_load(ep, n + node), epi_load(ep, 2 * n + node)};
   R v[4][3][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -1009,9 +1037,9 @@ __global__ void __launch_bounds__(256) assemble_kernel(Lattice L, const R* __res
       s2 += v[k][2][1];
     }
   }
-  node_epilogue(ep, node, s0, out);
-  node_epilogue(ep, n + node, s1, out);
-  node_epilogue(ep, 2 * n + node, s2, out);
+  node_epilogue(ep, node, s0, out, pre[0]);
+  node_epilogue(ep, n + node, s1, out, pre[1]);
+  node_epilogue(ep, 2 * n + node, s2, out, pre[2]);
 }
 
 // General meshes: one thread per node sums the element-vector slots of its list (increasing slot

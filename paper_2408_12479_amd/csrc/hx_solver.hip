@@ -260,49 +260,86 @@ __device__ __forceinline__ bool owns_node(const Lattice& L, const CellPos& cp, i
          owns(k, L.p, cp.ez, L.nz, periodic & 4);
 }
 
-// xf += P xc: each fine node written once, by its owning cell
+// Sum-factorised transfers between degrees on one cell: the 3D interpolation matrix is the tensor
+// product of the 1D table Icf (fine GLL point x coarse basis function), applied as three 1D
+// contractions through LDS; every pencil's coefficients are compile-time constants.
+// in: NI values per pencil with stride SI, out: NO values with stride SO (TR: Icf^T, i.e. from the
+// fine to the coarse points).
+template <int NF, int NC, bool TR, typename T>
+__device__ __forceinline__ void transfer_pencil(const T* in, int si, T* out, int so) {
+  constexpr int NI = TR ? NF : NC, NO = TR ? NC : NF;
+  T v[NI];
+#pragma unroll
+  for (int m = 0; m < NI; ++m) v[m] = in[m * si];
+#pragma unroll
+  for (int o = 0; o < NO; ++o) {
+    T acc = T(0);
+#pragma unroll
+    for (int m = 0; m < NI; ++m)
+      acc += (TR ? Transfer1D<NF, NC, T>::Icf[m * NC + o] : Transfer1D<NF, NC, T>::Icf[o * NC + m]) * v[m];
+    out[o * so] = acc;
+  }
+}
+
+// xf += P xc: each fine node written once, by its owning cell. Contractions along x, y, z:
+// [NC^3] -> [NF NC^2] -> [NF^2 NC] -> [NF^3] per component.
 template <int NF, int NC, typename T>
 __global__ void __launch_bounds__(NF* NF* NF) k_prolong_add(const T* __restrict__ xc,
                                                             T* __restrict__ xf, Lattice Lf,
                                                             Lattice Lc, int periodic) {
   constexpr int QF = NF * NF * NF, QC = NC * NC * NC;
-  __shared__ T sc[3 * QC];
+  constexpr int S1 = NF * NC * NC, S2 = NF * NF * NC;
+  __shared__ T s0[3 * QC];
+  __shared__ T s1[3 * S1];
+  __shared__ T s2[3 * S2];
+  __shared__ T s3[3 * QF];
   const int e = blockIdx.x;
   const CellPos cp = cell_pos(Lf, e);
   const int t = threadIdx.x;
   if (t < QC) {
     bool cons;
     const int64_t node = node_of(Lc, cp, t % NC, (t / NC) % NC, t / (NC * NC), cons);
-    for (int c = 0; c < 3; ++c) sc[c * QC + t] = xc[c * Lc.n_nodes + node];
+    for (int c = 0; c < 3; ++c) s0[c * QC + t] = xc[c * Lc.n_nodes + node];
+  }
+  __syncthreads();
+  // along x: pencils (c, b, cc), coarse a -> fine i
+  for (int job = t; job < 3 * NC * NC; job += QF) {
+    const int c = job / (NC * NC), r = job - c * (NC * NC);
+    transfer_pencil<NF, NC, false>(s0 + c * QC + NC * r, 1, s1 + c * S1 + NF * r, 1);
+  }
+  __syncthreads();
+  // along y: pencils (c, i, cc), coarse b -> fine j
+  for (int job = t; job < 3 * NF * NC; job += QF) {
+    const int c = job / (NF * NC), r = job - c * (NF * NC);
+    const int i = r % NF, cc = r / NF;
+    transfer_pencil<NF, NC, false>(s1 + c * S1 + i + NF * NC * cc, NF, s2 + c * S2 + i + NF * NF * cc, NF);
+  }
+  __syncthreads();
+  // along z: pencils (c, i, j), coarse cc -> fine k
+  for (int job = t; job < 3 * NF * NF; job += QF) {
+    const int c = job / (NF * NF), r = job - c * (NF * NF);
+    transfer_pencil<NF, NC, false>(s2 + c * S2 + r, NF * NF, s3 + c * QF + r, NF * NF);
   }
   __syncthreads();
   const int i = t % NF, j = (t / NF) % NF, k = t / (NF * NF);
   if (!owns_node(Lf, cp, i, j, k, periodic)) return;
-  T v[3] = {T(0), T(0), T(0)};
-  for (int cc = 0; cc < NC; ++cc)
-    for (int b = 0; b < NC; ++b) {
-      const T wjk = Transfer1D<NF, NC, T>::Icf[j * NC + b] * Transfer1D<NF, NC, T>::Icf[k * NC + cc];
-      for (int a = 0; a < NC; ++a) {
-        const T w = wjk * Transfer1D<NF, NC, T>::Icf[i * NC + a];
-        const int l = a + NC * (b + NC * cc);
-        v[0] += w * sc[l];
-        v[1] += w * sc[QC + l];
-        v[2] += w * sc[2 * QC + l];
-      }
-    }
   bool cons;
   const int64_t node = node_of(Lf, cp, i, j, k, cons);
-  for (int c = 0; c < 3; ++c) xf[c * Lf.n_nodes + node] += v[c];
-  (void)QF;
+  for (int c = 0; c < 3; ++c) xf[c * Lf.n_nodes + node] += s3[c * QF + t];
 }
 
-// rc += P^T rf (rc zeroed by the caller)
+// rc += P^T rf (rc zeroed by the caller): the owned fine values of the cell contracted along z,
+// y, x: [NF^3] -> [NF^2 NC] -> [NF NC^2] -> [NC^3], then added atomically at the coarse nodes.
 template <int NF, int NC, typename T>
 __global__ void __launch_bounds__(NF* NF* NF) k_restrict_add(const T* __restrict__ rf,
                                                              T* __restrict__ rc, Lattice Lf,
                                                              Lattice Lc, int periodic) {
   constexpr int QF = NF * NF * NF, QC = NC * NC * NC;
+  constexpr int S1 = NF * NC * NC, S2 = NF * NF * NC;
   __shared__ T sf[3 * QF];
+  __shared__ T s2[3 * S2];
+  __shared__ T s1[3 * S1];
+  __shared__ T s0[3 * QC];
   const int e = blockIdx.x;
   const CellPos cp = cell_pos(Lf, e);
   const int t = threadIdx.x;
@@ -314,24 +351,31 @@ __global__ void __launch_bounds__(NF* NF* NF) k_restrict_add(const T* __restrict
     for (int c = 0; c < 3; ++c) sf[c * QF + t] = own ? rf[c * Lf.n_nodes + node] : T(0);
   }
   __syncthreads();
+  // along z: pencils (c, i, j), fine k -> coarse cc
+  for (int job = t; job < 3 * NF * NF; job += QF) {
+    const int c = job / (NF * NF), r = job - c * (NF * NF);
+    transfer_pencil<NF, NC, true>(sf + c * QF + r, NF * NF, s2 + c * S2 + r, NF * NF);
+  }
+  __syncthreads();
+  // along y: pencils (c, i, cc), fine j -> coarse b
+  for (int job = t; job < 3 * NF * NC; job += QF) {
+    const int c = job / (NF * NC), r = job - c * (NF * NC);
+    const int i = r % NF, cc = r / NF;
+    transfer_pencil<NF, NC, true>(s2 + c * S2 + i + NF * NF * cc, NF, s1 + c * S1 + i + NF * NC * cc, NF);
+  }
+  __syncthreads();
+  // along x: pencils (c, b, cc), fine i -> coarse a
+  for (int job = t; job < 3 * NC * NC; job += QF) {
+    const int c = job / (NC * NC), r = job - c * (NC * NC);
+    transfer_pencil<NF, NC, true>(s1 + c * S1 + NF * r, 1, s0 + c * QC + NC * r, 1);
+  }
+  __syncthreads();
   if (t >= QC) return;
   const int a = t % NC, b = (t / NC) % NC, cc = t / (NC * NC);
-  T v[3] = {T(0), T(0), T(0)};
-  for (int k = 0; k < NF; ++k)
-    for (int j = 0; j < NF; ++j) {
-      const T wjk = Transfer1D<NF, NC, T>::Icf[j * NC + b] * Transfer1D<NF, NC, T>::Icf[k * NC + cc];
-      for (int i = 0; i < NF; ++i) {
-        const T w = wjk * Transfer1D<NF, NC, T>::Icf[i * NC + a];
-        const int l = i + NF * (j + NF * k);
-        v[0] += w * sf[l];
-        v[1] += w * sf[QF + l];
-        v[2] += w * sf[2 * QF + l];
-      }
-    }
   bool cons;
   const int64_t node = node_of(Lc, cp, a, b, cc, cons);
   if (cons) return;
-  for (int c = 0; c < 3; ++c) unsafeAtomicAdd(rc + c * Lc.n_nodes + node, v[c]);
+  for (int c = 0; c < 3; ++c) unsafeAtomicAdd(rc + c * Lc.n_nodes + node, s0[c * QC + t]);
 }
 
 // uc = uf at the coarse nodes (each coarse node written once, by its owning cell)
