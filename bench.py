@@ -16,6 +16,7 @@ timed on a bounded sample of cells on the host (cpu_baseline). The oracle leg al
 error of every sweep entry against the oracle on sampled output rows (rel_err_vs_oracle_sampled).
 """
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -34,8 +35,14 @@ FP32_PEAK_TFLOPS = 157.3
 # Algorithmic work per q-point (FP64 flops, cNH) of each storage mode's q-point routine, and
 # stored words per q-point; sum factorisation adds 12 n^4 fused multiply-adds per field and cell
 # (6 sweeps forward, 6 backward), 6 n^4 for the linearisation point in recompute mode.
-QPOINT_FLOPS = {"tangent": 162, "finv_j": 400, "none": 597, "spatial": 205}
-QPOINT_WORDS = {"tangent": 45, "finv_j": 10, "none": 0, "spatial": 16}
+# The stored-scalar stage does the recompute work without the logarithm; the stored-tensor stage
+# forms F^-1 G, (F^-1 G) C^-1, D_u S and G S + F D_u S from its words (counted from the code).
+QPOINT_FLOPS = {"tangent": 162, "finv_j": 400, "none": 597, "spatial": 205, "scalars": 580, "tensors": 374,
+                "spatial_recompute": 800}
+QPOINT_WORDS = {"tangent": 45, "finv_j": 10, "none": 0, "spatial": 16, "scalars": 1, "tensors": 31,
+                "spatial_recompute": 0}
+# modes that interpolate the linearisation point u_k at every apply
+RECOMPUTE_MODES = ("none", "scalars", "spatial_recompute")
 
 
 def parse():
@@ -44,7 +51,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--p", type=int, default=4)
-    ap.add_argument("--mode", default="auto", choices=["auto", "none", "finv_j", "tangent", "spatial"])
+    ap.add_argument("--mode", default="auto", choices=["auto", "none", "finv_j", "tangent", "spatial", "scalars",
+                                                       "tensors"])
     ap.add_argument("--degrees", default="2,3,4,6")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
@@ -89,9 +97,9 @@ def algorithmic(p, mode, n_cells, n_dofs):
     n = p + 1
     Q = n ** 3
     words = QPOINT_WORDS[mode]
-    vec_words = 2 + (1 if mode == "none" else 0)
+    vec_words = 2 + (1 if mode in RECOMPUTE_MODES else 0)
     bytes_ = 8.0 * (vec_words * n_dofs + words * Q * n_cells)
-    fwd_fields = 3 + (3 if mode == "none" else 0)
+    fwd_fields = 3 + (3 if mode in RECOMPUTE_MODES else 0)
     flops = n_cells * (sumfac_flops(n, fwd_fields, 3) + QPOINT_FLOPS[mode] * Q)
     return bytes_, flops
 
@@ -210,6 +218,16 @@ def start_oracle_pool(workers):
     return ctx.Pool(workers, initializer=_oracle_worker_start, initargs=(barrier,))
 
 
+def stop_resource_tracker():
+    """The spawn context's locks and barrier start multiprocessing's resource-tracker process; once
+    the pool has ended and been released it is stopped, so that no process outlives the bench."""
+    try:
+        from multiprocessing import resource_tracker
+        resource_tracker._resource_tracker._stop()
+    except Exception:  # pragma: no cover
+        pass
+
+
 def cpu_baseline(pool, workers, p, cells, budget_s=15.0, gpu_dst=None):
     """The FP64 oracle's element-by-element tangent apply on a bounded, contiguous run of cells,
     spread over a pool of single-threaded worker processes. With the headline apply's output
@@ -322,7 +340,7 @@ def main():
     degrees = [int(x) for x in args.degrees.split(",")]
     if args.p not in degrees:
         degrees.append(args.p)
-    modes = ["none", "finv_j", "tangent", "spatial"]
+    modes = ["none", "scalars", "tensors", "finv_j", "tangent", "spatial"]
     sweep = {}
     samples = {}
     extra = {}
@@ -456,6 +474,9 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pool, workers, head["p"], args.cells, gpu_dst=head["dst"])
+        pool = None   # the pool has ended; releasing it lets the tracker stop without leftovers
+        gc.collect()
+        stop_resource_tracker()
         par = sweep_parity(samples, args.cells)
         out["cpu_baseline"]["sweep_parity"] = par
         for key, errs in par.items():

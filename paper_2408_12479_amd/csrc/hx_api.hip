@@ -766,17 +766,17 @@ hx_status hx::update_linearization(hx_ctx_s* ctx, const double* u, hx_storage mo
   if (!ctx || !u) return fail(ctx, HX_E_ARG, "hx_update_linearization: NULL argument");
   if (variant < 0 || variant >= kVariants || (variant != 0 && ctx->topo != kTopoLattice))
     return fail(ctx, HX_E_ARG, "hx_update_linearization: cells-per-workgroup variant not available for this mesh");
-  if (mode != HX_STORE_NONE && mode != HX_STORE_FINV_J && mode != HX_STORE_TANGENT && mode != HX_STORE_SPATIAL &&
-      mode != HX_STORE_SPATIAL_RECOMPUTE)
-    return fail(ctx, HX_E_ARG, "hx_update_linearization: unknown storage mode");
+  if (mode < HX_STORE_NONE || mode >= kModes) return fail(ctx, HX_E_ARG, "hx_update_linearization: unknown storage mode");
   // the modes that re-interpolate the linearisation point at every apply keep a copy of it
-  const bool keeps_uk = mode == HX_STORE_NONE || mode == HX_STORE_SPATIAL_RECOMPUTE;
+  const bool keeps_uk = mode == HX_STORE_NONE || mode == HX_STORE_SPATIAL_RECOMPUTE || mode == HX_STORE_SCALARS;
   const int st = store_of(prec);
   if (st < 0) return fail(ctx, HX_E_ARG, "hx_update_linearization: unknown precision");
   // bfloat16 data (FP32 range) for every mode that stores data; binary16 (range limited, scaled per
   // cell by a power of two) for the stored tangent only; the modes that store nothing run as FP32
   if (st == kStoreF16 && (mode == HX_STORE_FINV_J || mode == HX_STORE_SPATIAL))
     return fail(ctx, HX_E_UNSUPPORTED, "hx_update_linearization: binary16 data only for the stored tangent");
+  if ((st == kStoreF16 || st == kStoreBF16) && (mode == HX_STORE_SCALARS || mode == HX_STORE_TENSORS))
+    return fail(ctx, HX_E_UNSUPPORTED, "hx_update_linearization: the scalar and tensor stages store FP64 or FP32 data");
   hipStream_t s = static_cast<hipStream_t>(stream);
   Slot& sl = ctx->slot[prec == HX_FP64 ? 0 : 1];
   const Lattice& L = ctx->L;
@@ -822,7 +822,7 @@ hx_status hx::update_linearization(hx_ctx_s* ctx, const double* u, hx_storage mo
   // FP32 recompute and F^-1+J modes of the fibre law: the tension switches are decided here in
   // FP64 and kept, so that the FP32 apply cannot flip them by rounding
   const bool keep_act = ctx->base.mat.law == HX_LAW_FIBER && prec != HX_FP64 &&
-                        (keeps_uk || mode == HX_STORE_FINV_J);
+                        (mode == HX_STORE_NONE || mode == HX_STORE_SPATIAL_RECOMPUTE || mode == HX_STORE_FINV_J);
   if (keep_act) {
     const size_t ab = static_cast<size_t>(padded_cells) * Q;
     if (sl.act_bytes < ab) {
@@ -980,8 +980,10 @@ struct TuneBench {
   }
 };
 
-const hx_storage kTuneModes[5] = {HX_STORE_NONE, HX_STORE_FINV_J, HX_STORE_TANGENT, HX_STORE_SPATIAL,
-                                  HX_STORE_SPATIAL_RECOMPUTE};
+const hx_storage kTuneModes[kModes] = {HX_STORE_NONE,    HX_STORE_FINV_J,
+                                       HX_STORE_TANGENT, HX_STORE_SPATIAL,
+                                       HX_STORE_SPATIAL_RECOMPUTE, HX_STORE_SCALARS,
+                                       HX_STORE_TENSORS};
 
 }  // namespace
 
@@ -1030,7 +1032,7 @@ hx_status hx_autotune(hx_ctx ctx, const double* u, hx_precision prec, int32_t re
   int count = 0;
   hx_tune_entry overall{};
   overall.ms = -1.0;
-  for (int k = 0; k < 5; ++k) {
+  for (int k = 0; k < kModes; ++k) {
     const hx_storage mode = kTuneModes[k];
     const bool stored = mode != HX_STORE_NONE && mode != HX_STORE_SPATIAL_RECOMPUTE;
     hx_tune_entry mode_best{};

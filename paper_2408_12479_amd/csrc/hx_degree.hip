@@ -171,6 +171,14 @@ hipError_t by_law(const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok) 
         if (op.store == kStoreF32) return launch<double, 2, HX_STORE_FINV_J, LAW, kStoreF32>(h, s);
         if (op.store == kStoreBF16) return launch<double, 2, HX_STORE_FINV_J, LAW, kStoreBF16>(h, s);
       }
+      if (op.mode == HX_STORE_SCALARS) {
+        if (op.store == kStoreF64) return launch<double, 2, HX_STORE_SCALARS, LAW, kStoreF64>(h, s);
+        if (op.store == kStoreF32) return launch<double, 2, HX_STORE_SCALARS, LAW, kStoreF32>(h, s);
+      }
+      if (op.mode == HX_STORE_TENSORS) {
+        if (op.store == kStoreF64) return launch<double, 2, HX_STORE_TENSORS, LAW, kStoreF64>(h, s);
+        if (op.store == kStoreF32) return launch<double, 2, HX_STORE_TENSORS, LAW, kStoreF32>(h, s);
+      }
       if (op.mode == HX_STORE_SPATIAL) {
         if (op.store == kStoreF64) return launch<double, 2, HX_STORE_SPATIAL, LAW, kStoreF64>(h, s);
         if (op.store == kStoreF32) return launch<double, 2, HX_STORE_SPATIAL, LAW, kStoreF32>(h, s);
@@ -196,6 +204,14 @@ hipError_t by_law(const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok) 
       if (op.mode == HX_STORE_SPATIAL_RECOMPUTE) {
         return op.fp32 ? launch<float, 0, HX_STORE_SPATIAL_RECOMPUTE, LAW, kStoreF32>(h, s)
                        : launch<double, 0, HX_STORE_SPATIAL_RECOMPUTE, LAW, kStoreF64>(h, s);
+      }
+      if (op.mode == HX_STORE_SCALARS) {
+        if (!op.fp32 && op.store == kStoreF64) return launch<double, 0, HX_STORE_SCALARS, LAW, kStoreF64>(h, s);
+        if (op.fp32 && op.store == kStoreF32) return launch<float, 0, HX_STORE_SCALARS, LAW, kStoreF32>(h, s);
+      }
+      if (op.mode == HX_STORE_TENSORS) {
+        if (!op.fp32 && op.store == kStoreF64) return launch<double, 0, HX_STORE_TENSORS, LAW, kStoreF64>(h, s);
+        if (op.fp32 && op.store == kStoreF32) return launch<float, 0, HX_STORE_TENSORS, LAW, kStoreF32>(h, s);
       }
       if (op.mode == HX_STORE_FINV_J) {
         if (!op.fp32 && op.store == kStoreF64)

@@ -1271,6 +1271,189 @@ __device__ __forceinline__ void spatial_action(const R* d, const MaterialK<R>& m
       t[3 * c + dd] = sg[3 * c] * Kt[3 * dd] + sg[3 * c + 1] * Kt[3 * dd + 1] + sg[3 * c + 2] * Kt[3 * dd + 2];
 }
 
+// ------------------------------------------------------------------------------------------
+// The stored-scalar and stored-tensor stages of the reference-configuration operator (Section 5:
+// the weak forms with the stored quantities marked; Tab. overview_precompute).
+// SCALARS: the law's scalars are stored and F is formed from u_k at every apply, as with nothing
+// stored; F^-1 = adj(F) / J. Words:
+//   cNH   ln J
+//   iNH   J - 1, J^-2/3, c1, c2
+//   fibre the iNH words, then c3 and E_i of each family (c3 carries the tension switch)
+// TENSORS: F, S, F^-1 and C^-1 are stored with the scalars of D_u S, and the apply evaluates
+// P' = G S + F D_u S[G] (G = Grad du) term by term:
+//   cNH   D_u S = 2 (mu - 2 lambda ln J) sym(F^-1 G C^-1) + 2 lambda tr(F^-1 G) C^-1
+//   iNH   D_u S = -2 c1 sym(F^-1 G C^-1) + (c2 tr(F^-1 G) - 2mu/3 J^-2/3 F:G) C^-1
+//                 - 2mu/3 J^-2/3 tr(F^-1 G) I
+//   fibre adds sum_i 2 c3 (2 k2 E_i^2 + 1) ((F H_i):G) H_i
+// with the c1 sign of the appendix derivation (as in `action`). Words: F 9, S 6 (symmetric),
+// F^-1 9, C^-1 6 (symmetric), then cNH ln J; iNH J^-2/3, c1, c2; fibre adds 2 c3 (2 k2 E_i^2 + 1)
+// per family.
+// ------------------------------------------------------------------------------------------
+template <int LAW>
+constexpr int kScalarWords = LAW == kCNH ? 1 : (LAW == kINH ? 4 : 8);
+template <int LAW>
+constexpr int kTensorWords = LAW == kCNH ? 31 : (LAW == kINH ? 33 : 35);
+
+template <int LAW, typename R>
+__device__ __forceinline__ void scalar_words(const QState<R>& s, R* d) {
+  if constexpr (LAW == kCNH) {
+    d[0] = s.lnJ;
+  } else {
+    d[0] = s.Jm;
+    d[1] = s.Jp;
+    d[2] = s.c1;
+    d[3] = s.c2;
+    if constexpr (kIsFiber<LAW>) {
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        d[4 + 2 * f] = s.c3[f];
+        d[5 + 2 * f] = s.Ei[f];
+      }
+    }
+  }
+}
+
+// State of an apply from H = Grad u_k and the stored scalars. cNH forms J - 1 from the invariants
+// of H in FP64, as the update does.
+template <int LAW, typename R>
+__device__ __forceinline__ void state_from_scalars(const R* H, const R* d, const MaterialK<R>& m, QState<R>& s) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) s.F[i] = H[i];
+  s.F[0] += R(1);
+  s.F[4] += R(1);
+  s.F[8] += R(1);
+  if constexpr (LAW == kCNH) {
+    double Hd[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Hd[i] = static_cast<double>(H[i]);
+    const double trH = Hd[0] + Hd[4] + Hd[8];
+    const double I2 = Hd[0] * Hd[4] + Hd[0] * Hd[8] + Hd[4] * Hd[8] - Hd[1] * Hd[3] - Hd[2] * Hd[6] - Hd[5] * Hd[7];
+    s.Jm = static_cast<R>(det3(Hd) + I2 + trH);
+    s.lnJ = d[0];
+  } else {
+    s.Jm = d[0];
+    s.Jp = d[1];
+    s.c1 = d[2];
+    s.c2 = d[3];
+    if constexpr (kIsFiber<LAW>) {
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        s.c3[f] = d[4 + 2 * f];
+        s.Ei[f] = d[5 + 2 * f];
+        s.dfac[f] = R(2) * m.k2 * s.Ei[f] * s.Ei[f] + R(1);
+      }
+    }
+  }
+  R A[9];
+  adj3(s.F, A);
+  const R invJ = R(1) / (R(1) + s.Jm);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) s.Fi[i] = A[i] * invJ;
+}
+
+template <int LAW, typename R>
+__device__ __forceinline__ void tensor_words(const QState<R>& s, const R* E, const MaterialK<R>& m,
+                                             const Fib<R>& fb, R* d) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) d[i] = s.F[i];
+  // S = F^-1 P, symmetrised (P from the stable stress of the residual)
+  R P[9], S[9];
+  stress_P<LAW>(s, E, m, fb, P);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) S[3 * i + j] = s.Fi[3 * i] * P[j] + s.Fi[3 * i + 1] * P[3 + j] + s.Fi[3 * i + 2] * P[6 + j];
+  R Ss[9], Ci[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      Ss[3 * i + j] = R(0.5) * (S[3 * i + j] + S[3 * j + i]);
+      Ci[3 * i + j] = s.Fi[3 * i] * s.Fi[3 * j] + s.Fi[3 * i + 1] * s.Fi[3 * j + 1] + s.Fi[3 * i + 2] * s.Fi[3 * j + 2];
+    }
+  full_to_sym(Ss, d + 9);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) d[15 + i] = s.Fi[i];
+  full_to_sym(Ci, d + 24);
+  if constexpr (LAW == kCNH) {
+    d[30] = s.lnJ;
+  } else {
+    d[30] = s.Jp;
+    d[31] = s.c1;
+    d[32] = s.c2;
+    if constexpr (kIsFiber<LAW>) {
+#pragma unroll
+      for (int f = 0; f < 2; ++f) d[33 + f] = R(2) * s.c3[f] * s.dfac[f];
+    }
+  }
+}
+
+template <int LAW, typename R>
+__device__ __forceinline__ void tensor_action(const R* d, const MaterialK<R>& m, const Fib<R>& fb, const R* G,
+                                              R* Pd) {
+  const R* F = d;
+  const R* Fi = d + 15;
+  R S[9], Ci[9];
+  sym_to_full(d + 9, S);
+  sym_to_full(d + 24, Ci);
+  // Y = F^-1 G, M = Y C^-1
+  R Y[9], M[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Y[3 * i + j] = Fi[3 * i] * G[j] + Fi[3 * i + 1] * G[3 + j] + Fi[3 * i + 2] * G[6 + j];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) M[3 * i + j] = Y[3 * i] * Ci[j] + Y[3 * i + 1] * Ci[3 + j] + Y[3 * i + 2] * Ci[6 + j];
+  const R tr = Y[0] + Y[4] + Y[8];
+  R DS[9];
+  if constexpr (LAW == kCNH) {
+    const R a = m.mu - R(2) * m.lam * d[30];   // 2 a sym(M) = a (M + M^T)
+    const R b = R(2) * m.lam * tr;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) DS[3 * i + j] = a * (M[3 * i + j] + M[3 * j + i]) + b * Ci[3 * i + j];
+  } else {
+    const R Jp = d[30], c1 = d[31], c2 = d[32];
+    R FG = R(0);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) FG += F[i] * G[i];
+    const R two3 = R(2) / R(3) * m.mu * Jp;
+    const R cc = c2 * tr - two3 * FG;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) DS[3 * i + j] = -c1 * (M[3 * i + j] + M[3 * j + i]) + cc * Ci[3 * i + j];
+    DS[0] -= two3 * tr;
+    DS[4] -= two3 * tr;
+    DS[8] -= two3 * tr;
+    if constexpr (kIsFiber<LAW>) {
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        const R* Hf = f == 0 ? fb.H4 : fb.H6;
+        R fhg = R(0);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j)
+            fhg += (F[3 * i] * Hf[j] + F[3 * i + 1] * Hf[3 + j] + F[3 * i + 2] * Hf[6 + j]) * G[3 * i + j];
+        const R w = d[33 + f] * fhg;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) DS[i] += w * Hf[i];
+      }
+    }
+  }
+  // P' = G S + F D_u S
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      Pd[3 * i + j] = G[3 * i] * S[j] + G[3 * i + 1] * S[3 + j] + G[3 * i + 2] * S[6 + j] + F[3 * i] * DS[j] +
+                      F[3 * i + 1] * DS[3 + j] + F[3 * i + 2] * DS[6 + j];
+}
+
 template <int N, int EB, typename R>
 __device__ __forceinline__ void load_vertices(const KernelArgs<N, R>& a, R* sv, int e0,
                                               const CellPos& c0) {
@@ -1328,16 +1511,20 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
   const CellPos c0 = cell_pos(a.L, e0);
   // stored data: block-interleaved planes [block][word][EB * Q]; the plane base is uniform
   // across the workgroup and the lane offset is the thread index
-  constexpr int W = MODE == HX_STORE_TANGENT
-                        ? 45
-                        : (MODE == HX_STORE_FINV_J ? 10 : (MODE == HX_STORE_SPATIAL ? kSpatialWords<LAW> : 0));
+  constexpr int W = MODE == HX_STORE_TANGENT          ? 45
+                    : MODE == HX_STORE_FINV_J         ? 10
+                    : MODE == HX_STORE_SPATIAL        ? kSpatialWords<LAW>
+                    : MODE == HX_STORE_SCALARS        ? kScalarWords<LAW>
+                    : MODE == HX_STORE_TENSORS        ? kTensorWords<LAW>
+                                                      : 0;
   constexpr int EBQ = EB * Q;
   const int64_t qblk = static_cast<int64_t>(blk) * W * EBQ;
   const int qi = threadIdx.x;
 
   // stored q-point data of this thread (apply), requested before the sum factorisation so that
-  // its HBM latency overlaps the gather and the forward sweeps
-  constexpr int WA = KIND == 0 ? W : 0;
+  // its HBM latency overlaps the gather and the forward sweeps (the tensor stage's 31-35 words
+  // would stay live through the sweeps and spill: they are loaded where they are used)
+  constexpr int WA = KIND == 0 && MODE != HX_STORE_TENSORS ? W : 0;
   ST qv[WA > 0 ? WA : 1];
   if constexpr (WA > 0) {
     if (valid) {
@@ -1391,7 +1578,7 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
 
   R g0[9], g1[9], t[9];
   // the apply modes that interpolate the linearisation point u_k at every apply
-  constexpr bool kRecompute = MODE == HX_STORE_NONE || MODE == HX_STORE_SPATIAL_RECOMPUTE;
+  constexpr bool kRecompute = MODE == HX_STORE_NONE || MODE == HX_STORE_SPATIAL_RECOMPUTE || MODE == HX_STORE_SCALARS;
   if constexpr (KIND == 0 && kRecompute) {
     // linearisation point first (not masked), then the direction (masked)
     forward_vector<N, EB, false, TOPO>(a, sb, a.in1, e0, c0, le, q, g1);
@@ -1465,6 +1652,22 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
       for (int w = 0; w < WS; ++w) d[w] = R(0);
     }
     spatial_action<LAW>(d, m, g0, t);
+  } else if constexpr (KIND == 0 && MODE == HX_STORE_TENSORS) {
+    R K[9];
+    const R wdet = geometry(K);
+    R d[W];
+    const ST* qd = static_cast<const ST*>(a.qdata) + qblk;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      if constexpr (NT)
+        d[w] = valid ? static_cast<R>(as_val(load_stream(qd + w * EBQ + qi))) : R(0);
+      else
+        d[w] = valid ? static_cast<R>(as_val(qd[w * EBQ + qi])) : R(0);
+    }
+    R G[9], Pd[9];
+    to_physical(g0, K, G);
+    tensor_action<LAW>(d, m, fb, G, Pd);
+    to_reference(Pd, K, wdet, t);
   } else if constexpr (KIND == 0) {
     R K[9];
     const R wdet = geometry(K);
@@ -1476,6 +1679,12 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
       R H[9], E[9];
       to_physical(g1, K, H);
       state_from_H<LAW>(H, m, fb, st, E);
+    } else if constexpr (MODE == HX_STORE_SCALARS) {
+      R H[9], d[W];
+      to_physical(g1, K, H);
+#pragma unroll
+      for (int w = 0; w < W; ++w) d[w] = valid ? static_cast<R>(as_val(qv[w])) : R(0);
+      state_from_scalars<LAW>(H, d, m, st);
     } else {
       R Fi[9], Jm;
       if (valid) {
@@ -1583,6 +1792,20 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
       if (valid) {
 #pragma unroll
         for (int i = 0; i < 45; ++i) store_val(qw + i * EBQ + qi, Dsym[i] * scale);
+      }
+    } else if constexpr (MODE == HX_STORE_SCALARS || MODE == HX_STORE_TENSORS) {
+      R dw[W];
+      if constexpr (MODE == HX_STORE_SCALARS)
+        scalar_words<LAW>(st, dw);
+      else
+        tensor_words<LAW>(st, E, m, fb, dw);
+      R chk = R(0);
+#pragma unroll
+      for (int w = 0; w < W; ++w) chk += dw[w];
+      if (valid && !isfinite(chk)) bad |= kFlagNonFinite;
+      if (valid) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) store_val(qw + w * EBQ + qi, dw[w]);
       }
     } else if constexpr (MODE == HX_STORE_SPATIAL) {
       R J0[9], dw[W];
