@@ -137,7 +137,10 @@ hipError_t launch_v(const HostArgs& h, hipStream_t s) {
       assemble_map_kernel<R><<<grid, dim3(256), 0, s>>>(h.L.n_nodes, h.nptr, h.nslot, h.cmask, ES, a.ework,
                                                          KIND == 0 ? a.in0 : nullptr, a.out, ep);
     } else {
-      assemble_kernel<N, R><<<grid, dim3(256), 0, s>>>(h.L, a.ework, KIND == 0 ? a.in0 : nullptr, a.out, ep);
+      if (ep.kind != kEpiStore)
+        assemble_kernel<N, R, true><<<grid, dim3(256), 0, s>>>(h.L, a.ework, KIND == 0 ? a.in0 : nullptr, a.out, ep);
+      else
+        assemble_kernel<N, R, false><<<grid, dim3(256), 0, s>>>(h.L, a.ework, KIND == 0 ? a.in0 : nullptr, a.out, ep);
     }
   }
   return hipGetLastError();

@@ -978,7 +978,9 @@ __device__ __forceinline__ void node_epilogue(const Epi<R>& ep, int64_t idx, R t
   node_epilogue(ep, idx, t, out, epi_load(ep, idx));
 }
 
-template <int N, typename R>
+// EPI: the apply carries a smoother or residual epilogue (a separate instantiation, so that the
+// plain store keeps the lean kernel).
+template <int N, typename R, bool EPI>
 __global__ void __launch_bounds__(256) assemble_kernel(Lattice L, const R* __restrict__ E,
                                                        const R* cons_src, R* out, Epi<R> ep) {
   constexpr int P = N - 1;
@@ -1006,7 +1008,12 @@ __global__ void __launch_bounds__(256) assemble_kernel(Lattice L, const R* __res
   const int x1 = nxc > 1 ? cx[1] * N + lx[1] : x0;
   // all loads are issued before the first sum: summing each value as it arrives would wait for
   // up to eight memory round trips one after the other
-  const EpiIn<R> pre[3] = {epi_load(ep, node), epi_load(ep, n + node), epi_load(ep, 2 * n + node)};
+  EpiIn<R> pre[3] = {};
+  if constexpr (EPI) {
+    pre[0] = epi_load(ep, node);
+    pre[1] = epi_load(ep, n + node);
+    pre[2] = epi_load(ep, 2 * n + node);
+  }
   R v[4][3][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -1037,9 +1044,15 @@ __global__ void __launch_bounds__(256) assemble_kernel(Lattice L, const R* __res
       s2 += v[k][2][1];
     }
   }
-  node_epilogue(ep, node, s0, out, pre[0]);
-  node_epilogue(ep, n + node, s1, out, pre[1]);
-  node_epilogue(ep, 2 * n + node, s2, out, pre[2]);
+  if constexpr (EPI) {
+    node_epilogue(ep, node, s0, out, pre[0]);
+    node_epilogue(ep, n + node, s1, out, pre[1]);
+    node_epilogue(ep, 2 * n + node, s2, out, pre[2]);
+  } else {
+    out[node] = s0;
+    out[n + node] = s1;
+    out[2 * n + node] = s2;
+  }
 }
 
 // General meshes: one thread per node sums the element-vector slots of its list (increasing slot
