@@ -38,11 +38,11 @@ FP32_PEAK_TFLOPS = 157.3
 # The stored-scalar stage does the recompute work without the logarithm; the stored-tensor stage
 # forms F^-1 G, (F^-1 G) C^-1, D_u S and G S + F D_u S from its words (counted from the code).
 QPOINT_FLOPS = {"tangent": 162, "finv_j": 400, "none": 597, "spatial": 205, "scalars": 580, "tensors": 374,
-                "spatial_recompute": 800}
+                "spatial_recompute": 800, "spatial_scalars": 780}
 QPOINT_WORDS = {"tangent": 45, "finv_j": 10, "none": 0, "spatial": 16, "scalars": 1, "tensors": 31,
-                "spatial_recompute": 0}
+                "spatial_recompute": 0, "spatial_scalars": 1}
 # modes that interpolate the linearisation point u_k at every apply
-RECOMPUTE_MODES = ("none", "scalars", "spatial_recompute")
+RECOMPUTE_MODES = ("none", "scalars", "spatial_recompute", "spatial_scalars")
 
 
 def parse():
@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--p", type=int, default=4)
     ap.add_argument("--mode", default="auto", choices=["auto", "none", "finv_j", "tangent", "spatial", "scalars",
-                                                       "tensors"])
+                                                       "tensors", "spatial_recompute", "spatial_scalars"])
     ap.add_argument("--degrees", default="2,3,4,6")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
@@ -340,7 +340,9 @@ def main():
     degrees = [int(x) for x in args.degrees.split(",")]
     if args.p not in degrees:
         degrees.append(args.p)
-    modes = ["none", "scalars", "tensors", "finv_j", "tangent", "spatial"]
+    # the paper's three stages over the reference and the spatial configuration, then F^-1 + J and
+    # the stored tangent
+    modes = ["none", "scalars", "tensors", "spatial_recompute", "spatial_scalars", "spatial", "finv_j", "tangent"]
     sweep = {}
     samples = {}
     extra = {}

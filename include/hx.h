@@ -119,6 +119,10 @@ typedef enum {
                            D_u S (cNH ln J; iNH J^-2/3, c1, c2; fibre adds 2 c3 (2 k2 E_i^2 + 1) per
                            family: 31 / 33 / 35 words); the apply forms P' = G S + F D_u S[G]
                            term by term; FP64 or FP32 data */
+  HX_STORE_SPATIAL_SCALARS = 7, /* the paper's stored-scalar stage over the spatial configuration:
+                                   the SCALARS words are stored, and every apply re-interpolates
+                                   u_k and forms the SPATIAL mode's data from it with those scalars
+                                   (the library keeps a copy of u_k); FP64 or FP32 data */
   HX_STORE_AUTO = 255 /* only where a field says so: the mode is chosen by hx_autotune_storage */
 } hx_storage;
 
@@ -309,7 +313,7 @@ int32_t hx_cells_per_workgroup(int32_t p, int32_t variant);
 
 /* Autotuner of the apply's configuration (Section 7.2: the fastest evaluation depends on the
  * hardware, degree and law and has to be measured): for each storage mode (NONE, FINV_J,
- * TANGENT, SPATIAL, SPATIAL_RECOMPUTE, SCALARS, TENSORS), each cells-per-workgroup variant (two on a lattice of trilinear cells, the
+ * TANGENT, SPATIAL, SPATIAL_RECOMPUTE, SCALARS, TENSORS, SPATIAL_SCALARS), each cells-per-workgroup variant (two on a lattice of trilinear cells, the
  * default elsewhere; the stored data is laid out per variant) and, for the modes with stored
  * data, both load policies of that data (plain or non-temporal), updates the slot of prec
  * (HX_FP64 or HX_FP32) at u, applies once to warm up and times `reps` applies (1..1000) of a fixed
@@ -317,7 +321,7 @@ int32_t hx_cells_per_workgroup(int32_t p, int32_t variant);
  * fastest configuration of every mode as the
  * context's choice, which later hx_update_linearization calls of that mode and precision class use,
  * and leaves the slot linearised in the overall fastest one (*best). table (HOST, max_entries) or
- * NULL receives every timed configuration, *n_entries (or NULL) their number (at most 24).
+ * NULL receives every timed configuration, *n_entries (or NULL) their number (at most 28).
  * Allocates two temporary device vectors and waits for the stream. */
 hx_status hx_autotune(hx_ctx ctx, const double* u, hx_precision prec, int32_t reps,
                       hx_tune_entry* table, int32_t max_entries, int32_t* n_entries,

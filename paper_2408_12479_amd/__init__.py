@@ -22,9 +22,10 @@ STATUS = {0: "HX_OK", 1: "HX_E_ARG", 2: "HX_E_HIP", 3: "HX_E_NOMEM", 4: "HX_E_ST
           6: "HX_E_NONFINITE", 7: "HX_E_NOT_CONVERGED", 8: "HX_E_UNSUPPORTED"}
 LAWS = {"cnh": 0, "inh": 1, "fiber": 2}
 MODES = {"none": 0, "finv_j": 1, "tangent": 2, "spatial": 3, "spatial_recompute": 4, "scalars": 5, "tensors": 6,
-         "auto": 255}
+         "spatial_scalars": 7, "auto": 255}
 MODE_NAMES = {v: k for k, v in MODES.items()}
-STORAGE_MODES = ("none", "finv_j", "tangent", "spatial", "spatial_recompute", "scalars", "tensors")
+STORAGE_MODES = ("none", "finv_j", "tangent", "spatial", "spatial_recompute", "scalars", "tensors",
+                 "spatial_scalars")
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_bf16": 2, "fp32_fp16": 3}
 
 
@@ -331,11 +332,11 @@ class _Context:
         variant, cells_per_workgroup, nontemporal and ms per apply. The choice per mode is kept by
         the context for its later updates."""
         import torch
-        table = (_TuneEntry * 24)()
+        table = (_TuneEntry * 28)()
         n = ctypes.c_int32()
         best = _TuneEntry()
         _check(lib.hx_autotune(self.ctx, self._vec(u, torch.float64, "u"), PRECISIONS[precision], int(reps),
-                               table, 24, ctypes.byref(n), ctypes.byref(best), _stream_handle(stream)), self.ctx)
+                               table, 28, ctypes.byref(n), ctypes.byref(best), _stream_handle(stream)), self.ctx)
         return best.as_dict(), [table[i].as_dict() for i in range(n.value)]
 
     def set_tuning(self, mode, precision="fp64", variant=0, nontemporal=-1):

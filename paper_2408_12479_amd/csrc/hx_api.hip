@@ -768,14 +768,16 @@ hx_status hx::update_linearization(hx_ctx_s* ctx, const double* u, hx_storage mo
     return fail(ctx, HX_E_ARG, "hx_update_linearization: cells-per-workgroup variant not available for this mesh");
   if (mode < HX_STORE_NONE || mode >= kModes) return fail(ctx, HX_E_ARG, "hx_update_linearization: unknown storage mode");
   // the modes that re-interpolate the linearisation point at every apply keep a copy of it
-  const bool keeps_uk = mode == HX_STORE_NONE || mode == HX_STORE_SPATIAL_RECOMPUTE || mode == HX_STORE_SCALARS;
+  const bool keeps_uk = mode == HX_STORE_NONE || mode == HX_STORE_SPATIAL_RECOMPUTE || mode == HX_STORE_SCALARS ||
+                        mode == HX_STORE_SPATIAL_SCALARS;
   const int st = store_of(prec);
   if (st < 0) return fail(ctx, HX_E_ARG, "hx_update_linearization: unknown precision");
   // bfloat16 data (FP32 range) for every mode that stores data; binary16 (range limited, scaled per
   // cell by a power of two) for the stored tangent only; the modes that store nothing run as FP32
   if (st == kStoreF16 && (mode == HX_STORE_FINV_J || mode == HX_STORE_SPATIAL))
     return fail(ctx, HX_E_UNSUPPORTED, "hx_update_linearization: binary16 data only for the stored tangent");
-  if ((st == kStoreF16 || st == kStoreBF16) && (mode == HX_STORE_SCALARS || mode == HX_STORE_TENSORS))
+  if ((st == kStoreF16 || st == kStoreBF16) &&
+      (mode == HX_STORE_SCALARS || mode == HX_STORE_TENSORS || mode == HX_STORE_SPATIAL_SCALARS))
     return fail(ctx, HX_E_UNSUPPORTED, "hx_update_linearization: the scalar and tensor stages store FP64 or FP32 data");
   hipStream_t s = static_cast<hipStream_t>(stream);
   Slot& sl = ctx->slot[prec == HX_FP64 ? 0 : 1];
@@ -983,7 +985,7 @@ struct TuneBench {
 const hx_storage kTuneModes[kModes] = {HX_STORE_NONE,    HX_STORE_FINV_J,
                                        HX_STORE_TANGENT, HX_STORE_SPATIAL,
                                        HX_STORE_SPATIAL_RECOMPUTE, HX_STORE_SCALARS,
-                                       HX_STORE_TENSORS};
+                                       HX_STORE_TENSORS, HX_STORE_SPATIAL_SCALARS};
 
 }  // namespace
 

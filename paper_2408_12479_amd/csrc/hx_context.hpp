@@ -25,8 +25,8 @@ struct Slot {
   int nt = -1;             // stored data loaded non-temporally: -1 by size, 0 no, 1 yes
 };
 
-// Storage modes NONE .. TENSORS (the hx_storage values 0 .. kModes - 1).
-constexpr int kModes = 7;
+// Storage modes NONE .. SPATIAL_SCALARS (the hx_storage values 0 .. kModes - 1).
+constexpr int kModes = 8;
 
 // A configuration the autotuner chose (or the caller set) for one storage mode of one slot.
 struct Tuning {

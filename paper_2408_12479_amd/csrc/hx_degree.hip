@@ -174,7 +174,8 @@ hipError_t by_law(const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok) 
         if (op.store == kStoreF32) return launch<double, 2, HX_STORE_FINV_J, LAW, kStoreF32>(h, s);
         if (op.store == kStoreBF16) return launch<double, 2, HX_STORE_FINV_J, LAW, kStoreBF16>(h, s);
       }
-      if (op.mode == HX_STORE_SCALARS) {
+      if (op.mode == HX_STORE_SCALARS || op.mode == HX_STORE_SPATIAL_SCALARS) {
+        // the same stored scalars for both configurations
         if (op.store == kStoreF64) return launch<double, 2, HX_STORE_SCALARS, LAW, kStoreF64>(h, s);
         if (op.store == kStoreF32) return launch<double, 2, HX_STORE_SCALARS, LAW, kStoreF32>(h, s);
       }
@@ -211,6 +212,10 @@ hipError_t by_law(const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok) 
       if (op.mode == HX_STORE_SCALARS) {
         if (!op.fp32 && op.store == kStoreF64) return launch<double, 0, HX_STORE_SCALARS, LAW, kStoreF64>(h, s);
         if (op.fp32 && op.store == kStoreF32) return launch<float, 0, HX_STORE_SCALARS, LAW, kStoreF32>(h, s);
+      }
+      if (op.mode == HX_STORE_SPATIAL_SCALARS) {
+        if (!op.fp32 && op.store == kStoreF64) return launch<double, 0, HX_STORE_SPATIAL_SCALARS, LAW, kStoreF64>(h, s);
+        if (op.fp32 && op.store == kStoreF32) return launch<float, 0, HX_STORE_SPATIAL_SCALARS, LAW, kStoreF32>(h, s);
       }
       if (op.mode == HX_STORE_TENSORS) {
         if (!op.fp32 && op.store == kStoreF64) return launch<double, 0, HX_STORE_TENSORS, LAW, kStoreF64>(h, s);

@@ -198,7 +198,8 @@ inline int mode_words(hx_storage m, hx_law law) {
     case HX_STORE_TANGENT: return 45;
     case HX_STORE_FINV_J: return 10;
     case HX_STORE_SPATIAL: return spatial_words(law);
-    case HX_STORE_SCALARS: return law == 0 ? 1 : (law == 1 ? 4 : 8);
+    case HX_STORE_SCALARS:
+    case HX_STORE_SPATIAL_SCALARS: return law == 0 ? 1 : (law == 1 ? 4 : 8);
     case HX_STORE_TENSORS: return law == 0 ? 31 : (law == 1 ? 33 : 35);
     default: return 0;
   }

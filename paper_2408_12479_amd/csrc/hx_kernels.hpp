@@ -1528,6 +1528,7 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
                     : MODE == HX_STORE_FINV_J         ? 10
                     : MODE == HX_STORE_SPATIAL        ? kSpatialWords<LAW>
                     : MODE == HX_STORE_SCALARS        ? kScalarWords<LAW>
+                    : MODE == HX_STORE_SPATIAL_SCALARS ? kScalarWords<LAW>
                     : MODE == HX_STORE_TENSORS        ? kTensorWords<LAW>
                                                       : 0;
   constexpr int EBQ = EB * Q;
@@ -1591,7 +1592,8 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
 
   R g0[9], g1[9], t[9];
   // the apply modes that interpolate the linearisation point u_k at every apply
-  constexpr bool kRecompute = MODE == HX_STORE_NONE || MODE == HX_STORE_SPATIAL_RECOMPUTE || MODE == HX_STORE_SCALARS;
+  constexpr bool kRecompute = MODE == HX_STORE_NONE || MODE == HX_STORE_SPATIAL_RECOMPUTE ||
+                              MODE == HX_STORE_SCALARS || MODE == HX_STORE_SPATIAL_SCALARS;
   if constexpr (KIND == 0 && kRecompute) {
     // linearisation point first (not masked), then the direction (masked)
     forward_vector<N, EB, false, TOPO>(a, sb, a.in1, e0, c0, le, q, g1);
@@ -1645,16 +1647,25 @@ __global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
 #pragma unroll
     for (int w = 0; w < W; ++w) d[w] = valid ? static_cast<R>(as_val(qv[w])) : R(0);
     spatial_action<LAW>(d, m, g0, t);
-  } else if constexpr (KIND == 0 && MODE == HX_STORE_SPATIAL_RECOMPUTE) {
-    // the spatial data formed from u_k at this apply, then the spatial action
-    R K[9], H[9], E[9];
+  } else if constexpr (KIND == 0 && (MODE == HX_STORE_SPATIAL_RECOMPUTE || MODE == HX_STORE_SPATIAL_SCALARS)) {
+    // the spatial data formed from u_k at this apply (with the law's scalars recomputed, or as
+    // stored), then the spatial action
+    R K[9], H[9];
     const R wdet = geometry(K);
     to_physical(g1, K, H);
     QState<R> st;
-    if constexpr (kIsFiber<LAW>) {
-      if (a.act && valid) st.forced = a.act[static_cast<int64_t>(blk) * EBQ + qi];
+    if constexpr (MODE == HX_STORE_SPATIAL_SCALARS) {
+      R ds[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) ds[w] = valid ? static_cast<R>(as_val(qv[w])) : R(0);
+      state_from_scalars<LAW>(H, ds, m, st);
+    } else {
+      if constexpr (kIsFiber<LAW>) {
+        if (a.act && valid) st.forced = a.act[static_cast<int64_t>(blk) * EBQ + qi];
+      }
+      R E[9];
+      state_from_H<LAW>(H, m, fb, st, E);
     }
-    state_from_H<LAW>(H, m, fb, st, E);
     R J0[9];
     jacobian_at(K, J0);
     constexpr int WS = kSpatialWords<LAW>;

@@ -974,7 +974,8 @@ hx_status hx_mg_create(const hx_ctx* levels, int32_t n_levels, const hx_mg_optio
     const bool mode_ok = o.level_mode == HX_STORE_NONE || o.level_mode == HX_STORE_FINV_J ||
                          o.level_mode == HX_STORE_TANGENT || o.level_mode == HX_STORE_SPATIAL ||
                          o.level_mode == HX_STORE_SPATIAL_RECOMPUTE || o.level_mode == HX_STORE_SCALARS ||
-                         o.level_mode == HX_STORE_TENSORS || o.level_mode == HX_STORE_AUTO;
+                         o.level_mode == HX_STORE_TENSORS || o.level_mode == HX_STORE_SPATIAL_SCALARS ||
+                         o.level_mode == HX_STORE_AUTO;
     if (o.smoother_degree < 1 || o.coarse_degree < 1 || o.eig_iters < 1 || !(o.smoothing_range > 1.0) ||
         !(o.eig_safety >= 1.0) ||
         (o.precision != HX_FP32 && o.precision != HX_FP64 && o.precision != HX_FP32_BF16DATA &&
@@ -1322,7 +1323,8 @@ hx_status hx_newton_solve(hx_mg mg, double* u, const double* f_ext, const hx_new
   const bool mode_ok = opt->outer_mode == HX_STORE_NONE || opt->outer_mode == HX_STORE_FINV_J ||
                        opt->outer_mode == HX_STORE_TANGENT || opt->outer_mode == HX_STORE_SPATIAL ||
                        opt->outer_mode == HX_STORE_SPATIAL_RECOMPUTE || opt->outer_mode == HX_STORE_SCALARS ||
-                       opt->outer_mode == HX_STORE_TENSORS || opt->outer_mode == HX_STORE_AUTO;
+                       opt->outer_mode == HX_STORE_TENSORS || opt->outer_mode == HX_STORE_SPATIAL_SCALARS ||
+                       opt->outer_mode == HX_STORE_AUTO;
   if (!mode_ok) return mg_fail(mg, HX_E_ARG, "hx_newton_solve: unknown outer_mode");
   int outer = opt->outer_mode == HX_STORE_AUTO ? -1 : opt->outer_mode;
   for (int step = 1; step <= opt->load_steps && status == HX_OK; ++step) {

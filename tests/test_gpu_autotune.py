@@ -40,7 +40,7 @@ def test_alternative_variant_matches_oracle(device, p):
     assert hx.cells_per_workgroup(p, 1) > 0 and hx.cells_per_workgroup(p, 1) != hx.cells_per_workgroup(p, 0)
     for prec in ("fp64", "fp32"):
         dt = "float64" if prec == "fp64" else "float32"
-        for mode in ("none", "finv_j", "tangent", "spatial", "spatial_recompute", "scalars", "tensors"):
+        for mode in hx.STORAGE_MODES:
             for nt in (0, 1):
                 op.set_tuning(mode, prec, variant=1, nontemporal=nt)
                 op.update_linearization(ud, mode=mode, precision=prec)
@@ -54,9 +54,9 @@ def test_autotune_picks_the_fastest_and_keeps_it(device):
     op, pb = make_pair((8, 8, 8), 3, "cnh", lam=100.0)
     u, du = _fields(pb)
     best, entries = op.autotune(to_dev(u), "fp64", reps=5)
-    assert len(entries) == 24
+    assert len(entries) == 28
     assert {e["mode"] for e in entries} == {"none", "finv_j", "tangent", "spatial", "spatial_recompute", "scalars",
-                                            "tensors"}
+                                            "tensors", "spatial_scalars"}
     assert {e["variant"] for e in entries} == {0, 1}
     assert best["ms"] == min(e["ms"] for e in entries)
     # the slot is left in the best configuration: the apply reproduces the oracle
@@ -80,7 +80,7 @@ def test_autotune_on_a_general_mesh(device):
     X = op.node_coords()
     u = 0.01 * np.stack([X[:, 2] * X[:, 0], X[:, 2] * X[:, 1], X[:, 2] ** 2])
     best, entries = op.autotune(to_dev(u), "fp32", reps=3)
-    assert len(entries) == 12 and {e["variant"] for e in entries} == {0}
+    assert len(entries) == 14 and {e["variant"] for e in entries} == {0}
     with pytest.raises(hx.HxError):
         op.set_tuning("tangent", "fp64", variant=1)
     op.close()
@@ -93,7 +93,7 @@ def test_stored_table_round_trip(device, tmp_path):
     ud = to_dev(u)
     best, used = hx.autotune_with_table(op, ud, "inh", "fp64", reps=3, path=path)
     table = json.load(open(path))
-    assert len(table) == 7 and all(k.startswith("p2/inh/fp64/") for k in table)
+    assert len(table) == 8 and all(k.startswith("p2/inh/fp64/") for k in table)
     op.close()
     op, pb = make_pair((6, 6, 6), 2, "inh")
     best2, used2 = hx.autotune_with_table(op, ud, "inh", "fp64", reps=3, path=path)

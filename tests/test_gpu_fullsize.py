@@ -82,7 +82,7 @@ def test_fiber_box_fp32_sampled_rows(device):
     ref = _rows(pb.apply_tangent(u, du.astype(np.float32).astype(np.float64), cells=cells), nodes, m.n_nodes)
     op = hx.Operator(64, 32, 32, V, 3, law="fiber", mu=2.0, kappa=1e3, k1=1.0, k2=10.0, H4=H4, H6=H6, M4=M4, M6=M6)
     ud, du32 = to_dev(u), to_dev(du, "float32")
-    for mode in ["none", "finv_j", "tangent", "spatial", "spatial_recompute", "scalars", "tensors"]:
+    for mode in hx.STORAGE_MODES:
         op.update_linearization(ud, mode=mode, precision="fp32")
         y = op.apply_tangent(du32, precision="fp32").double().cpu().numpy()
         err = _rel(_rows(y, nodes, m.n_nodes), ref)

@@ -62,7 +62,7 @@ def _fields(pb, scale=0.05, seed=1):
     return u, du
 
 
-def _check(op, pb, modes=("none", "finv_j", "tangent", "spatial", "spatial_recompute", "scalars", "tensors"),
+def _check(op, pb, modes=hx.STORAGE_MODES,
            precisions=("fp64", "fp32")):
     n = pb.mesh.n_nodes
     assert op.num_nodes == n

@@ -7,6 +7,7 @@ FP32 data. BF16 and FP16 stored data have no accuracy target; their error is bou
 import numpy as np
 import pytest
 
+import paper_2408_12479_amd as hx
 import workloads
 from tests.gpu_helpers import make_pair, rel, to_dev, to_host
 
@@ -53,7 +54,7 @@ def test_config1_small_cube(device):
     r = to_host(op.residual(ud), op.num_nodes)
     assert rel(r, r_ref) < TOL64
     assert rel(to_host(op.residual(ud, form="spatial"), op.num_nodes), r_ref) < TOL64
-    for mode in ["none", "finv_j", "tangent", "spatial", "spatial_recompute", "scalars", "tensors"]:
+    for mode in hx.STORAGE_MODES:
         op.update_linearization(ud, mode=mode, precision="fp64")
         y = to_host(op.apply_tangent(dud, precision="fp64"), op.num_nodes)
         assert rel(y, Kdu_ref) < TOL64, mode
@@ -73,7 +74,7 @@ def test_fp64_all_modes(device, p, law):
     # the residual over the spatial configuration equals the material one (Section 2)
     assert rel(to_host(op.residual(ud, form="spatial"), op.num_nodes), r_ref) < TOL64
     Kdu_ref = pb.apply_tangent(u, du)
-    for mode in ["none", "finv_j", "tangent", "spatial", "spatial_recompute", "scalars", "tensors"]:
+    for mode in hx.STORAGE_MODES:
         op.update_linearization(ud, mode=mode, precision="fp64")
         y = to_host(op.apply_tangent(dud, precision="fp64"), op.num_nodes)
         assert rel(y, Kdu_ref) < TOL64, mode
@@ -90,7 +91,8 @@ def test_fp32_and_16bit_data(device, p, law):
     bounds = {"fp32": TOL32, "fp32_bf16": 2e-2, "fp32_fp16": 3e-3}
     for mode, precs in [("none", ["fp32"]), ("finv_j", ["fp32", "fp32_bf16"]), ("spatial", ["fp32", "fp32_bf16"]),
                         ("spatial_recompute", ["fp32"]), ("tangent", ["fp32", "fp32_bf16", "fp32_fp16"]),
-                        ("scalars", ["fp32"]), ("tensors", ["fp32"])]:
+                        ("scalars", ["fp32"]), ("tensors", ["fp32"]),
+                        ("spatial_scalars", ["fp32"])]:
         for prec in precs:
             op.update_linearization(ud, mode=mode, precision=prec)
             y = to_host(op.apply_tangent(du32, precision=prec), op.num_nodes)
@@ -141,7 +143,7 @@ def test_cell_frames_tube(device, p):
     assert rel(to_host(op.residual(ud, form="spatial"), op.num_nodes), pb.residual(u)) < TOL64
     ref = pb.apply_tangent(u, du)
     ref32 = pb.apply_tangent(u, du.astype(np.float32).astype(np.float64))
-    for mode in ["none", "finv_j", "tangent", "spatial", "spatial_recompute", "scalars", "tensors"]:
+    for mode in hx.STORAGE_MODES:
         op.update_linearization(ud, mode=mode, precision="fp64")
         assert rel(to_host(op.apply_tangent(dud), op.num_nodes), ref) < TOL64, mode
         op.update_linearization(ud, mode=mode, precision="fp32")
@@ -157,7 +159,7 @@ def test_cell_frames_random_box(device):
     ud, dud = to_dev(u), to_dev(du)
     assert rel(to_host(op.residual(ud), op.num_nodes), pb.residual(u)) < TOL64
     ref = pb.apply_tangent(u, du)
-    for mode in ["none", "finv_j", "tangent", "spatial", "scalars", "tensors"]:
+    for mode in ["none", "finv_j", "tangent", "spatial", "scalars", "tensors", "spatial_scalars"]:
         op.update_linearization(ud, mode=mode, precision="fp64")
         assert rel(to_host(op.apply_tangent(dud), op.num_nodes), ref) < TOL64, mode
     op.close()
@@ -224,7 +226,7 @@ def test_error_paths(device):
             op.update_linearization(to_dev(np.zeros_like(u)), mode=mode, precision="fp32_fp16")
         assert ei.value.name == "HX_E_UNSUPPORTED"
     # the scalar and tensor stages store FP64 or FP32 words only
-    for mode in ("scalars", "tensors"):
+    for mode in ("scalars", "tensors", "spatial_scalars"):
         for prec in ("fp32_bf16", "fp32_fp16"):
             with pytest.raises(hx.HxError) as ei:
                 op.update_linearization(to_dev(np.zeros_like(u)), mode=mode, precision=prec)
