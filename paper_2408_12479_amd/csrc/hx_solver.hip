@@ -101,22 +101,45 @@ __global__ void k_dots(const T* a0, const T* b0, const T* a1, const T* b1, const
 }
 
 // ---------------------------------------------------------------- PCG with device-side scalars
-// Scalars of the flexible PCG in device memory, so that an iteration needs no host round trip:
 // Scalars of the device-resident PCG: inner products of the running iteration, the stop flag
 // (1: loss of positive definiteness, the iterate is kept; 2: converged), the count of completed
 // iterations and the squared stopping threshold.
 enum { CG_RZ = 0, CG_PQ, CG_RR, CG_RZN, CG_RZO, CG_STOP, CG_ITERS, CG_TOL2, CG_COUNT };
 
-// x += alpha p, r -= alpha q with alpha = rz / pq; nothing moves once the iteration has stopped or
-// pq <= 0 (then the iterate is kept, as the host-driven loop does)
-__global__ void k_cg_alpha(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
-                           const double* __restrict__ q, const double* __restrict__ sc, int64_t n) {
+// x += alpha p, r -= alpha q with alpha = rz / pq, and in the same pass the inner products of the
+// new residual with itself and with the previous preconditioned residual z (still in z: the
+// preconditioner has not run yet), so that the flexible beta needs no copy of z. Nothing moves
+// once the iteration has stopped or pq <= 0 (then the iterate is kept, as the host-driven loop
+// does); the condition is uniform over the grid.
+__global__ void __launch_bounds__(256) k_cg_alpha(double* __restrict__ x, double* __restrict__ r,
+                                                  const double* __restrict__ p, const double* __restrict__ q,
+                                                  const double* __restrict__ z, double* __restrict__ sc,
+                                                  int64_t n) {
   const double pq = sc[CG_PQ];
   if (sc[CG_STOP] != 0.0 || !(pq > 0.0)) return;
   const double alpha = sc[CG_RZ] / pq;
+  double rr = 0.0, rz = 0.0;
   HX_GRID_LOOP(i, n) {
     x[i] += alpha * p[i];
-    r[i] -= alpha * q[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    rr += ri * ri;
+    rz += ri * z[i];
+  }
+  __shared__ double red[2][256];
+  red[0][threadIdx.x] = rr;
+  red[1][threadIdx.x] = rz;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (static_cast<int>(threadIdx.x) < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    unsafeAtomicAdd(sc + CG_RR, red[0][0]);
+    unsafeAtomicAdd(sc + CG_RZO, red[1][0]);
   }
 }
 
@@ -628,7 +651,7 @@ struct hx_mg_s {
   int vcycles = 0;
   std::string err;
   // Newton / Krylov work vectors (FP64, finest level)
-  DevBuf r, x, p, q, z, zold, f;
+  DevBuf r, x, p, q, z, f;
   DevBuf cg;                          // device scalars of the PCG (CG_*), with the ||r||^2 history
   hipGraphExec_t cg_exec = nullptr;   // one PCG iteration, captured per linearisation
   // dense coarse solve: the coarsest operator is assembled by probing, factored by Cholesky and
@@ -1244,17 +1267,14 @@ static hx_status cg_iteration_enqueue(hx_mg mg, hx_ctx fine) {
   double* p = mg->p.as<double>();
   double* q = mg->q.as<double>();
   double* z = mg->z.as<double>();
-  double* zo = mg->zold.as<double>();
   double* sc = mg->cg.as<double>();
   const int dg = std::min(grid_for(n), 1024);
   hx_status st = hx_apply_tangent(fine, p, q, HX_FP64, mg->stream);
   if (st != HX_OK) return st;
   k_dots<double><<<dg, 256, 0, mg->stream>>>(p, q, nullptr, nullptr, nullptr, nullptr, 1, sc + CG_PQ, n);
-  k_cg_alpha<<<grid_for(n), 256, 0, mg->stream>>>(x, r, p, q, sc, n);
-  k_dots<double><<<dg, 256, 0, mg->stream>>>(r, r, nullptr, nullptr, nullptr, nullptr, 1, sc + CG_RR, n);
-  k_convert<double, double><<<grid_for(n), 256, 0, mg->stream>>>(z, zo, n);
+  k_cg_alpha<<<dg, 256, 0, mg->stream>>>(x, r, p, q, z, sc, n);
   if ((st = precondition_enqueue(mg, r, z)) != HX_OK) return st;
-  k_dots<double><<<dg, 256, 0, mg->stream>>>(r, z, r, zo, nullptr, nullptr, 2, sc + CG_RZN, n);
+  k_dots<double><<<dg, 256, 0, mg->stream>>>(r, z, nullptr, nullptr, nullptr, nullptr, 1, sc + CG_RZN, n);
   k_cg_beta<<<grid_for(n), 256, 0, mg->stream>>>(p, z, sc, n);
   k_cg_roll<<<1, 64, 0, mg->stream>>>(sc);
   return hipGetLastError() == hipSuccess ? HX_OK : HX_E_HIP;
@@ -1291,7 +1311,7 @@ hx_status hx_newton_solve(hx_mg mg, double* u, const double* f_ext, const hx_new
   const int64_t n = 3 * fine->L.n_nodes;
   const size_t nb = n * sizeof(double);
   hipError_t e = hipSuccess;
-  DevBuf* W[] = {&mg->r, &mg->x, &mg->p, &mg->q, &mg->z, &mg->zold, &mg->f};
+  DevBuf* W[] = {&mg->r, &mg->x, &mg->p, &mg->q, &mg->z, &mg->f};
   for (DevBuf* b : W)
     if ((e = b->alloc(nb)) != hipSuccess) return mg_fail(mg, HX_E_NOMEM, "hx_newton_solve: work vectors");
   if ((e = mg->cg.alloc(CG_COUNT * sizeof(double))) != hipSuccess)
@@ -1304,7 +1324,6 @@ hx_status hx_newton_solve(hx_mg mg, double* u, const double* f_ext, const hx_new
   double* p = mg->p.as<double>();
   double* q = mg->q.as<double>();
   double* z = mg->z.as<double>();
-  double* zo = mg->zold.as<double>();
   double* f = mg->f.as<double>();
   hx_newton_report R{};
   const int vc0 = mg->vcycles;
