@@ -361,6 +361,10 @@ def main():
         nodes = sample_nodes(op.num_nodes, p)
         nodes_d = torch.tensor(nodes, device=dev)
         rows = {}
+        # the configuration autotuner first: every storage mode x cells-per-workgroup variant x load
+        # policy of the stored data; its choice per mode is kept by the context, so that every mode
+        # below is timed in its own best configuration
+        best_cfg, configs = op.autotune(ud, "fp64", reps=max(10, args.steps // 2))
         t_res = timer.protocol(lambda: op.residual(ud, r), warmup=max(3, args.warmup))
         res = {"dofs": op.num_dofs, "cells": op.num_cells, "residual_ms": t_res,
                "timing": "mean of the best 3 of 5 trials, each >= 50 calls and >= 0.2 s, after warm-up"}
@@ -383,9 +387,6 @@ def main():
         samples[p] = (nodes, rows)
         print(f"[bench] p={p}: " + ", ".join(f"{m_} {res[m_]['gdofs']:.2f} GDoF/s" for m_ in modes),
               file=sys.stderr, flush=True)
-        # the configuration autotuner: every storage mode x cells-per-workgroup variant x load
-        # policy of the stored data; its choice per mode is kept by the context
-        best_cfg, configs = op.autotune(ud, "fp64", reps=max(10, args.steps // 2))
         res["autotune"] = {"best": best_cfg, "configurations": configs}
         print(f"[bench] p={p}: autotuner picks {best_cfg['mode']} with {best_cfg['cells_per_workgroup']} cells "
               f"per workgroup, non-temporal {best_cfg['nontemporal']} ({best_cfg['ms']:.4f} ms)",

@@ -1501,14 +1501,28 @@ __device__ __forceinline__ int xcd_block(int b, int g) {
   return x * per + (x < rem ? x : rem) + b / kXcd;
 }
 
+// Waves per SIMD the kernel is compiled for: the update may use the whole register file; the FP64
+// applies that re-evaluate the law from u_k at every apply with nothing or only scalars stored
+// (NONE, SPATIAL_RECOMPUTE, SPATIAL_SCALARS) hold more than 128 registers' worth of state and run
+// at 2 waves rather than spill (measured, with the autotuner's cells per workgroup: Q3 / Q4 / Q6
+// +2-3 % NONE, +16 / +4 / +17 % SPATIAL_RECOMPUTE, +5 / +8 / +14 % SPATIAL_SCALARS; the same bound
+// made SCALARS, F^-1 + J and TENSORS no faster or slower); the others keep 4.
+template <int KIND, int MODE, typename R>
+constexpr int kMinWaves = KIND == 2 ? 1
+                          : (KIND == 0 && sizeof(R) == 8 &&
+                             (MODE == HX_STORE_SPATIAL_RECOMPUTE || MODE == HX_STORE_SPATIAL_SCALARS ||
+                              MODE == HX_STORE_NONE))
+                                ? 2
+                                : 4;
+
 // Kernel: ops = residual, apply (four storage modes) and update (four storage modes).
 //   KIND 0 apply, 1 residual, 2 update; MODE = hx_storage; S = StoreType; LAW
 // The apply and residual kernels are held to at most 128 VGPRs (4 waves per SIMD; forcing 8
-// waves spills and is slower); the update runs once per Newton step and may use the whole
-// register file.
+// waves spills and is slower) except the FP64 applies of kMinWaves; the update runs once per
+// Newton step and may use the whole register file.
 template <int N, int EB, typename R, int KIND, int MODE, int LAW, int S, bool NT = false,
           int TOPO = kTopoLattice>
-__global__ void __launch_bounds__(EB * N * N * N, KIND == 2 ? 1 : 4)
+__global__ void __launch_bounds__(EB * N * N * N, (kMinWaves<KIND, MODE, R>))
     element_kernel(KernelArgs<N, R> a) {
   constexpr int Q = N * N * N;
   using ST = typename StoreOf<S>::T;

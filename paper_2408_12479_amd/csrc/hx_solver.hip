@@ -319,6 +319,15 @@ __global__ void __launch_bounds__(NF* NF* NF) k_prolong_add(const T* __restrict_
   const int e = blockIdx.x;
   const CellPos cp = cell_pos(Lf, e);
   const int t = threadIdx.x;
+  // this thread's fine node: its current values are requested first, so that the read half of the
+  // update overlaps the gather and the contractions
+  const int i = t % NF, j = (t / NF) % NF, k = t / (NF * NF);
+  const bool own = owns_node(Lf, cp, i, j, k, periodic);
+  bool fcons;
+  const int64_t fnode = node_of(Lf, cp, i, j, k, fcons);
+  T xo[3] = {T(0), T(0), T(0)};
+  if (own)
+    for (int c = 0; c < 3; ++c) xo[c] = xf[c * Lf.n_nodes + fnode];
   if (t < QC) {
     bool cons;
     const int64_t node = node_of(Lc, cp, t % NC, (t / NC) % NC, t / (NC * NC), cons);
@@ -344,11 +353,8 @@ __global__ void __launch_bounds__(NF* NF* NF) k_prolong_add(const T* __restrict_
     transfer_pencil<NF, NC, false>(s2 + c * S2 + r, NF * NF, s3 + c * QF + r, NF * NF);
   }
   __syncthreads();
-  const int i = t % NF, j = (t / NF) % NF, k = t / (NF * NF);
-  if (!owns_node(Lf, cp, i, j, k, periodic)) return;
-  bool cons;
-  const int64_t node = node_of(Lf, cp, i, j, k, cons);
-  for (int c = 0; c < 3; ++c) xf[c * Lf.n_nodes + node] += s3[c * QF + t];
+  if (!own) return;
+  for (int c = 0; c < 3; ++c) xf[c * Lf.n_nodes + fnode] = xo[c] + s3[c * QF + t];
 }
 
 // rc += P^T rf (rc zeroed by the caller): the owned fine values of the cell contracted along z,
