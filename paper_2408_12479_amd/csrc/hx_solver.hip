@@ -1000,11 +1000,7 @@ hx_status hx_mg_create(const hx_ctx* levels, int32_t n_levels, const hx_mg_optio
   hx_mg_default_options(&o);
   if (opt) {
     o = *opt;
-    const bool mode_ok = o.level_mode == HX_STORE_NONE || o.level_mode == HX_STORE_FINV_J ||
-                         o.level_mode == HX_STORE_TANGENT || o.level_mode == HX_STORE_SPATIAL ||
-                         o.level_mode == HX_STORE_SPATIAL_RECOMPUTE || o.level_mode == HX_STORE_SCALARS ||
-                         o.level_mode == HX_STORE_TENSORS || o.level_mode == HX_STORE_SPATIAL_SCALARS ||
-                         o.level_mode == HX_STORE_AUTO;
+    const bool mode_ok = (o.level_mode >= HX_STORE_NONE && o.level_mode < kModes) || o.level_mode == HX_STORE_AUTO;
     if (o.smoother_degree < 1 || o.coarse_degree < 1 || o.eig_iters < 1 || !(o.smoothing_range > 1.0) ||
         !(o.eig_safety >= 1.0) ||
         (o.precision != HX_FP32 && o.precision != HX_FP64 && o.precision != HX_FP32_BF16DATA &&
@@ -1328,7 +1324,6 @@ hx_status hx_newton_solve(hx_mg mg, double* u, const double* f_ext, const hx_new
   double* r = mg->r.as<double>();
   double* x = mg->x.as<double>();
   double* p = mg->p.as<double>();
-  double* q = mg->q.as<double>();
   double* z = mg->z.as<double>();
   double* f = mg->f.as<double>();
   hx_newton_report R{};
@@ -1345,10 +1340,7 @@ hx_status hx_newton_solve(hx_mg mg, double* u, const double* f_ext, const hx_new
     return hipGetLastError() == hipSuccess ? HX_OK : HX_E_HIP;
   };
   hx_status status = HX_OK;
-  const bool mode_ok = opt->outer_mode == HX_STORE_NONE || opt->outer_mode == HX_STORE_FINV_J ||
-                       opt->outer_mode == HX_STORE_TANGENT || opt->outer_mode == HX_STORE_SPATIAL ||
-                       opt->outer_mode == HX_STORE_SPATIAL_RECOMPUTE || opt->outer_mode == HX_STORE_SCALARS ||
-                       opt->outer_mode == HX_STORE_TENSORS || opt->outer_mode == HX_STORE_SPATIAL_SCALARS ||
+  const bool mode_ok = (opt->outer_mode >= HX_STORE_NONE && opt->outer_mode < kModes) ||
                        opt->outer_mode == HX_STORE_AUTO;
   if (!mode_ok) return mg_fail(mg, HX_E_ARG, "hx_newton_solve: unknown outer_mode");
   int outer = opt->outer_mode == HX_STORE_AUTO ? -1 : opt->outer_mode;
