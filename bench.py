@@ -150,6 +150,20 @@ def hbm_probe(hx, torch, dev, timer, n=192 << 20, reps=20):
             "GBps": 24 * n / (ms * 1e-3) / 1e9, "result_ok": ok}
 
 
+def fp64_pipe_rates(hx, torch, dev, timer, iters=2000, reps=10):
+    """FP64 rates the library's issue-rate probe sustains on the vector units, on the 16x16x4
+    matrix instructions, and with every wave issuing to both (equal flops of each)."""
+    out = torch.empty(hx.PIPE_PROBE_THREADS, dtype=torch.float64, device=dev)
+    res = {"kernel": "dependency chains of FP64 vector FMAs / 16x16x4 FP64 matrix instructions, "
+                     "2048 workgroups x 256 threads", "iters": iters}
+    for kind, name in enumerate(("valu", "mfma", "both")):
+        flops = hx.fp64_pipe_probe(kind, iters, out)
+        ms = timer.time(lambda: hx.fp64_pipe_probe(kind, iters, out), reps)
+        res[name + "_tflops"] = flops / (ms * 1e-3) / 1e12
+    res["peak_tflops"] = FP64_PEAK_TFLOPS
+    return res
+
+
 def cube_operator(hx, workloads, p, cells):
     V = workloads.box_vertices(cells, cells, cells, perturb=0.2, seed=2)
     op = hx.Operator(cells, cells, cells, V, p, law="cnh", mu=1.0, lam=100.0, dirichlet_faces=(0,))
@@ -338,6 +352,9 @@ def main():
     timer = Timer(torch, stream)
     triad = hbm_probe(hx, torch, dev, timer)
     print(f"[bench] STREAM triad: {triad['GBps']:.0f} GB/s", file=sys.stderr, flush=True)
+    pipes = fp64_pipe_rates(hx, torch, dev, timer)
+    print(f"[bench] FP64 probe: vector {pipes['valu_tflops']:.1f}, matrix {pipes['mfma_tflops']:.1f}, "
+          f"both {pipes['both_tflops']:.1f} TFLOP/s", file=sys.stderr, flush=True)
     degrees = [int(x) for x in args.degrees.split(",")]
     if args.p not in degrees:
         degrees.append(args.p)
@@ -490,6 +507,7 @@ def main():
                     sweep[key][mode]["rel_err_vs_oracle_sampled"] = err
     out["sweep"] = sweep
     extra["hbm_triad"] = triad
+    extra["fp64_pipes"] = pipes
     out["extra"] = extra
     print(json.dumps(out), flush=True)
 

@@ -489,7 +489,7 @@ hx_status hx_qpoint_eval(const hx_material* mat, int32_t form, hx_precision prec
                          void* stream);
 
 /* ------------------------------------------------------------------------------------------
- * Device bandwidth probe (not part of the method).
+ * Device bandwidth and issue-rate probes (not part of the method).
  * ------------------------------------------------------------------------------------------ */
 /* STREAM "triad" (McCalpin's memory benchmark): a[i] = b[i] + s * c[i] for 0 <= i < n, FP64
  * device arrays owned by the caller, each 16-byte aligned and not overlapping; moves 24 n bytes.
@@ -498,6 +498,21 @@ hx_status hx_qpoint_eval(const hx_material* mat, int32_t form, hx_precision prec
  * or misaligned array, or n beyond 2^39. */
 hx_status hx_stream_triad(int64_t n, double* a, const double* b, const double* c, double s,
                           void* stream);
+
+/* FP64 issue-rate probe: 2048 workgroups of 256 threads, each thread running iters iterations of
+ * independent dependency chains. kind 0: vector fused multiply-adds, 8192 flops per wave and
+ * iteration (8 chains x 8 steps x 64 lanes x 2); kind 1: 16x16x4 FP64 matrix instructions, the
+ * same 8192 flops per wave and iteration (4 chains x 2048); kind 2: both in every wave (16384).
+ * Flops per call: 2048 x 4 waves x iters x (8192, 8192 or 16384). Timed, it states the FP64 rate
+ * each unit sustains alone and whether the two add up when a wave issues to both, the basis for
+ * keeping the 1D contractions of the sum factorisation on the vector units. out: device FP64
+ * [2048 * 256] owned by the caller, 8-byte aligned, receives each thread's sum of its chains.
+ * Lane l of a wave supplies 1e-3 l to A and 1e-3 to B of every matrix instruction, so each one adds
+ * 16 x 1e-3 x sum_l 1e-3 l = 0.032256 to the sum of the wave's accumulator entries whatever the
+ * lane layout: over the 64 threads of a wave the matrix chains sum to iters x 0.129024.
+ * Asynchronous on the stream; HX_E_ARG for kind outside [0, 2], iters outside [1, 10^6], or a
+ * NULL or misaligned out. */
+hx_status hx_fp64_pipe_probe(int32_t kind, int64_t iters, double* out, void* stream);
 
 const char* hx_last_error(hx_ctx ctx);
 const char* hx_status_string(hx_status s);

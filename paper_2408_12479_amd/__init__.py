@@ -142,6 +142,7 @@ def _load():
         "hx_qpoint_eval": (ctypes.c_int, [ctypes.POINTER(_Material), ctypes.c_int32, ctypes.c_int, ctypes.c_int32,
                                           i64, vp, vp, vp, vp, vp]),
         "hx_stream_triad": (ctypes.c_int, [i64, vp, vp, vp, ctypes.c_double, vp]),
+        "hx_fp64_pipe_probe": (ctypes.c_int, [ctypes.c_int32, i64, vp, vp]),
         "hx_last_error": (ctypes.c_char_p, [vp]),
         "hx_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     }
@@ -213,6 +214,21 @@ def stream_triad(a, b, c, s, stream=None):
     _check(lib.hx_stream_triad(a.numel(), ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
                                ctypes.c_void_p(c.data_ptr()), float(s), _stream_handle(stream)))
     return a
+
+
+PIPE_PROBE_THREADS = 2048 * 256
+
+
+def fp64_pipe_probe(kind, iters, out, stream=None):
+    """FP64 issue-rate probe (hx_fp64_pipe_probe): kind 0 vector FMAs, 1 16x16x4 matrix
+    instructions, 2 both; out a contiguous CUDA float64 tensor of PIPE_PROBE_THREADS values.
+    Returns the flops of the call."""
+    import torch
+    if not isinstance(out, torch.Tensor) or not out.is_cuda or out.dtype != torch.float64 \
+            or not out.is_contiguous() or out.numel() != PIPE_PROBE_THREADS:
+        raise TypeError("out must be a contiguous CUDA float64 tensor of PIPE_PROBE_THREADS values")
+    _check(lib.hx_fp64_pipe_probe(int(kind), int(iters), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return 2048 * 4 * int(iters) * (16384 if kind == 2 else 8192)
 
 
 def _stream_handle(stream):

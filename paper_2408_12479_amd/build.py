@@ -50,7 +50,9 @@ def build(jobs=None, verbose=False):
             units.append(([hipcc] + FLAGS + [f"-DHX_DEGREE={p}", f"-DHX_TOPO={t}", "-c",
                                             os.path.join(CSRC, "hx_degree.hip"),
                            "-o", os.path.join(BUILD, f"hx_p{p}_t{t}.o")], f"p{p}/t{t}"))
-    units.append(([hipcc] + FLAGS + ["-c", os.path.join(CSRC, "hx_api.hip"),
+    # the only matrix instructions of the library are the FP64 issue-rate probe's (hx_api.hip): its
+    # accumulators stay in VGPRs instead of being copied to and from AGPRs in every loop iteration
+    units.append(([hipcc] + FLAGS + ["-mllvm", "-amdgpu-mfma-vgpr-form", "-c", os.path.join(CSRC, "hx_api.hip"),
                    "-o", os.path.join(BUILD, "hx_api.o")], "api"))
     units.append(([hipcc] + FLAGS + ["-c", os.path.join(CSRC, "hx_solver.hip"),
                    "-o", os.path.join(BUILD, "hx_solver.o")], "solver"))

@@ -324,6 +324,48 @@ __global__ void stream_triad(double* __restrict__ a, const double* __restrict__ 
   }
 }
 
+// FP64 issue-rate probe: per thread, independent dependency chains of vector fused multiply-adds
+// (kind 0), of 16x16x4 FP64 matrix instructions (kind 1), or both in every wave with equal flops of
+// each (kind 2). Per wave and iteration: 64 vector FMA instructions (8 chains x 8 steps, 64 lanes
+// x 2 flops each = 8192 flops) and 4 matrix instructions (16 x 16 x 4 x 2 = 2048 flops each).
+constexpr int kProbeBlocks = 2048, kProbeThreads = 256;
+typedef double probe_d4 __attribute__((ext_vector_type(4)));
+
+template <int KIND>
+__global__ void __launch_bounds__(kProbeThreads) fp64_pipe_probe(int64_t iters, double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const double y = 0.999999, z = 1e-6;
+  double x[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) x[c] = 1e-3 * c;
+  probe_d4 acc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = probe_d4{0.0, 0.0, 0.0, 0.0};
+  const double a = 1e-3 * lane, b = 1e-3;
+  for (int64_t it = 0; it < iters; ++it) {
+    if constexpr (KIND != 1) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) x[c] = fma(x[c], y, z);
+    }
+    if constexpr (KIND != 0) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+    }
+  }
+  double s = 0.0;
+  if constexpr (KIND != 1) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) s += x[c];
+  }
+  if constexpr (KIND != 0) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s += (acc[c][0] + acc[c][1]) + (acc[c][2] + acc[c][3]);
+  }
+  out[static_cast<int64_t>(blockIdx.x) * kProbeThreads + threadIdx.x] = s;
+}
+
 int grid_for(int64_t n) {
   const int64_t b = (n + 255) / 256;
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(b, 8192)));
@@ -1074,6 +1116,19 @@ int64_t hx_linearization_bytes(hx_ctx ctx, hx_precision prec) {
   if (!ctx || store_of(prec) < 0) return -1;
   const Slot& sl = ctx->slot[prec == HX_FP64 ? 0 : 1];
   return sl.valid ? static_cast<int64_t>(sl.qbytes) : 0;
+}
+
+hx_status hx_fp64_pipe_probe(int32_t kind, int64_t iters, double* out, void* stream) {
+  if (kind < 0 || kind > 2 || iters < 1 || iters > 1000000 || !out || (reinterpret_cast<uintptr_t>(out) & 7))
+    return HX_E_ARG;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  if (kind == 0)
+    hipLaunchKernelGGL(fp64_pipe_probe<0>, dim3(kProbeBlocks), dim3(kProbeThreads), 0, s, iters, out);
+  else if (kind == 1)
+    hipLaunchKernelGGL(fp64_pipe_probe<1>, dim3(kProbeBlocks), dim3(kProbeThreads), 0, s, iters, out);
+  else
+    hipLaunchKernelGGL(fp64_pipe_probe<2>, dim3(kProbeBlocks), dim3(kProbeThreads), 0, s, iters, out);
+  return hipGetLastError() == hipSuccess ? HX_OK : HX_E_HIP;
 }
 
 hx_status hx_stream_triad(int64_t n, double* a, const double* b, const double* c, double s, void* stream) {

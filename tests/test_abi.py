@@ -73,3 +73,33 @@ def test_one_hip_runtime_per_process():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_setup_refuses_empty_and_degenerate_meshes():
+    """hx_setup_lattice and hx_setup check their arguments on the host before any device call: an
+    empty lattice, a mesh without cells or with fewer than 8 vertices, a degree outside [1, 6] and
+    NULL arguments all come back as errors with no context."""
+    import paper_2408_12479_amd as hx
+    for dims in ((0, 2, 2), (2, 0, 2), (2, 2, 0)):
+        V = np.zeros((dims[2] + 1) * (dims[1] + 1) * (dims[0] + 1) * 3)
+        with pytest.raises(hx.HxError) as err:
+            hx.Operator(*dims, V, 2, law="cnh", mu=1.0, lam=1.0)
+        assert err.value.name == "HX_E_ARG"
+        assert "empty lattice" in str(err.value)
+    V8 = np.array([[a, b, c] for c in (0.0, 1.0) for b in (0.0, 1.0) for a in (0.0, 1.0)])
+    with pytest.raises(hx.HxError) as err:
+        hx.HexOperator(V8, np.zeros((0, 8), dtype=np.int64), 2, law="cnh", mu=1.0, lam=1.0)
+    assert err.value.name == "HX_E_ARG"
+    assert "at least one cell" in str(err.value)
+    with pytest.raises(hx.HxError) as err:
+        hx.HexOperator(V8[:7], np.arange(8)[None] % 7, 2, law="cnh", mu=1.0, lam=1.0)
+    assert err.value.name == "HX_E_ARG"
+    for p in (0, 7):
+        with pytest.raises(hx.HxError) as err:
+            hx.HexOperator(V8, np.arange(8)[None], p, law="cnh", mu=1.0, lam=1.0)
+        assert err.value.name == "HX_E_UNSUPPORTED"
+    ctx = ctypes.c_void_p()
+    assert hx.STATUS[hx.lib.hx_setup_lattice(None, 2, None, None, ctypes.byref(ctx))] == "HX_E_ARG"
+    assert hx.STATUS[hx.lib.hx_setup(None, 2, None, None, ctypes.byref(ctx))] == "HX_E_ARG"
+    assert ctx.value is None
+    assert hx.STATUS[hx.lib.hx_setup(None, 2, None, None, None)] == "HX_E_ARG"
