@@ -64,8 +64,9 @@ def parse():
     ap.add_argument("--newton-cells", default="32,16,400")
     ap.add_argument("--no-newton-bf16", action="store_true",
                     help="skip the solve with bfloat16-stored multigrid levels")
-    ap.add_argument("--mg-variants", default="graph,eager,graph_fp32_bf16,graph_unfused",
-                    help="V-cycle variants of the tube study (graph, eager, graph_fp32_bf16, graph_unfused)")
+    ap.add_argument("--mg-variants", default="graph,eager,graph_fp32_bf16,graph_unfused,graph_point",
+                    help="V-cycle variants of the tube study (graph, eager, graph_fp32_bf16, graph_unfused, "
+                         "graph_point: point Jacobi smoothing)")
     return ap.parse_args()
 
 
@@ -641,11 +642,13 @@ def tube_twist(op, amp=0.05):
     return np.stack([c * dx - sn * y - dx, sn * dx + c * y - y, np.zeros_like(s)])
 
 
-MG_VARIANTS = {  # name: (graph capture, precision, Chebyshev steps fused into the node kernels)
-    "graph": (True, "fp32", True),
-    "eager": (False, "fp32", True),
-    "graph_fp32_bf16": (True, "fp32_bf16", True),
-    "graph_unfused": (True, "fp32", False),
+MG_VARIANTS = {  # name: (graph capture, precision, Chebyshev steps fused into the node kernels,
+    #                 nodal block Jacobi (else point Jacobi))
+    "graph": (True, "fp32", True, True),
+    "eager": (False, "fp32", True, True),
+    "graph_fp32_bf16": (True, "fp32_bf16", True, True),
+    "graph_unfused": (True, "fp32", False, True),
+    "graph_point": (True, "fp32", True, False),
 }
 
 
@@ -667,8 +670,9 @@ def mg_study(hx, workloads, torch, dev, timer, cells=(16, 8, 200), degrees=(6, 3
     out = {"cells": list(cells), "levels": [[op.p, op.num_cells, op.num_dofs] for op in ops],
            "geometry": f"isoparametric: every level's cells map by the tube's map at degree {degrees[0]}"}
     for key in variants:
-        use_graph, prec, fuse = MG_VARIANTS[key]
-        mg = hx.Multigrid(ops, precision=prec, use_graph=use_graph, level_mode="auto", fuse_smoother=fuse)
+        use_graph, prec, fuse, blocks = MG_VARIANTS[key]
+        mg = hx.Multigrid(ops, precision=prec, use_graph=use_graph, level_mode="auto", fuse_smoother=fuse,
+                          smoother_blocks=blocks)
         t0 = time.perf_counter()
         mg.update(ud)
         t_upd = time.perf_counter() - t0
@@ -685,8 +689,8 @@ def mg_study(hx, workloads, torch, dev, timer, cells=(16, 8, 200), degrees=(6, 3
             fine_bytes = ops[0].linearization_bytes("fp32") + 2 * 4 * n
             out["finest_apply_fp32"] = {"mode": mg.level_mode(0), "ms": t_fine, "bytes": fine_bytes,
                                         "hbm_frac": fine_bytes / (t_fine * 1e-3) / 1e9 / HBM_PEAK_GBS}
-        if key in ("graph", "graph_fp32_bf16"):
-            sfx = "" if prec == "fp32" else "_" + prec
+        if key in ("graph", "graph_fp32_bf16", "graph_point"):
+            sfx = "" if key == "graph" else key[len("graph"):]
             out["update_s" + sfx] = t_upd
             out["level_modes" + sfx] = [mg.level_mode(l) for l in range(len(ops))]
             out["lambda_max" + sfx] = [mg.lambda_max(l) for l in range(len(ops))]

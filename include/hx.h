@@ -383,6 +383,11 @@ typedef struct {
   int32_t fuse_smoother;   /* 1 (default): every Chebyshev step after the first, and the residual
                               before the restriction, run in the node kernel of the level apply
                               (no separate pass over the level vectors); 0: separate kernels */
+  int32_t smoother_blocks; /* 0: point Jacobi (the inverse of the operator's diagonal); 1 (default):
+                              nodal block Jacobi, the inverse of each node's 3x3 block of the
+                              operator (the coupling of the three displacement components at the
+                              node), formed from the stored tangent like the diagonal; Chebyshev
+                              and the Lanczos bounds use the same D^-1 */
 } hx_mg_options;
 
 /* Fills *opt with the defaults listed above. */
@@ -425,8 +430,10 @@ double hx_mg_lambda_max(hx_mg mg, int32_t level);
 hx_status hx_mg_transfer(hx_mg mg, int32_t level, int32_t kind, const void* in, void* out,
                          void* stream);
 
-/* Copies the inverse diagonal of level `level` (identity on constrained rows) into out
- * (device [3][n_nodes], hierarchy precision). */
+/* Copies the smoother's D^-1 of level `level` into out (hierarchy precision). Point Jacobi:
+ * device [3][n_nodes], the inverse diagonal (1 on constrained rows). Nodal blocks: device
+ * [6][n_nodes], the entries (00, 11, 22, 01, 02, 12) of the inverse of each node's symmetric 3x3
+ * block (the identity at constrained nodes). */
 hx_status hx_mg_inverse_diagonal(hx_mg mg, int32_t level, void* out, void* stream);
 
 typedef struct {

@@ -76,7 +76,8 @@ class _MgOptions(ctypes.Structure):
     _fields_ = [("smoother_degree", ctypes.c_int32), ("coarse_degree", ctypes.c_int32),
                 ("smoothing_range", ctypes.c_double), ("eig_iters", ctypes.c_int32),
                 ("eig_safety", ctypes.c_double), ("precision", ctypes.c_int), ("use_graph", ctypes.c_int32),
-                ("level_mode", ctypes.c_int), ("coarse_solver", ctypes.c_int32), ("fuse_smoother", ctypes.c_int32)]
+                ("level_mode", ctypes.c_int), ("coarse_solver", ctypes.c_int32), ("fuse_smoother", ctypes.c_int32),
+                ("smoother_blocks", ctypes.c_int32)]
 
 
 class _NewtonOpts(ctypes.Structure):
@@ -451,18 +452,21 @@ class Multigrid:
 
     def __init__(self, levels, smoother_degree=4, coarse_degree=30, smoothing_range=20.0, eig_iters=20,
                  eig_safety=1.2, precision="fp32", use_graph=True, level_mode="tangent", coarse_solver="auto",
-                 fuse_smoother=True):
+                 fuse_smoother=True, smoother_blocks=True):
         """levels: Operators, finest first (see hx_mg_create for the allowed level pairs).
-        coarse_solver: "auto" (dense up to 8192 DoFs), "chebyshev" or "dense"."""
+        coarse_solver: "auto" (dense up to 8192 DoFs), "chebyshev" or "dense".
+        smoother_blocks: Jacobi with the inverses of the nodal 3x3 blocks (True) or of the diagonal."""
         self.levels = list(levels)
         arr = (ctypes.c_void_p * len(self.levels))(*[op.ctx.value for op in self.levels])
         o = _MgOptions(int(smoother_degree), int(coarse_degree), float(smoothing_range), int(eig_iters),
                        float(eig_safety), PRECISIONS[precision], int(bool(use_graph)), MODES[level_mode],
-                       {"auto": 0, "chebyshev": 1, "dense": 2}[coarse_solver], int(bool(fuse_smoother)))
+                       {"auto": 0, "chebyshev": 1, "dense": 2}[coarse_solver], int(bool(fuse_smoother)),
+                       int(bool(smoother_blocks)))
         mg = ctypes.c_void_p()
         _check(lib.hx_mg_create(arr, len(self.levels), ctypes.byref(o), ctypes.byref(mg)))
         self.mg = mg
         self.precision = precision
+        self.smoother_blocks = bool(smoother_blocks)
 
     def close(self):
         if getattr(self, "mg", None):
@@ -510,11 +514,13 @@ class Multigrid:
         return out
 
     def inverse_diagonal(self, level, stream=None):
+        """The smoother's D^-1 on a level: [3 * n_nodes] (point Jacobi) or, with nodal blocks,
+        [6 * n_nodes], the planes (00, 11, 22, 01, 02, 12) of the inverse blocks."""
         import torch
         dt = torch.float64 if self.precision == "fp64" else torch.float32
         op = self.levels[level]
-        out = torch.empty(op.num_dofs, dtype=dt, device="cuda")
-        _check_mg(lib.hx_mg_inverse_diagonal(self.mg, int(level), op._vec(out, dt, "out"),
+        out = torch.empty(op.num_dofs * (2 if self.smoother_blocks else 1), dtype=dt, device="cuda")
+        _check_mg(lib.hx_mg_inverse_diagonal(self.mg, int(level), ctypes.c_void_p(out.data_ptr()),
                                              _stream_handle(stream)), self.mg)
         return out
 

@@ -130,7 +130,8 @@ hipError_t launch_v(const HostArgs& h, hipStream_t s) {
     Epi<R> ep{};
     if constexpr (KIND == 0) {
       ep = Epi<R>{h.epi.kind, static_cast<const R*>(h.epi.b), static_cast<R*>(h.epi.x), static_cast<R*>(h.epi.d),
-                  static_cast<const R*>(h.epi.dinv), static_cast<R>(h.epi.c1), static_cast<R>(h.epi.c2)};
+                  static_cast<const R*>(h.epi.dinv), static_cast<R>(h.epi.c1), static_cast<R>(h.epi.c2),
+                  h.epi.blocks};
     }
     if constexpr (TOPO == kTopoMap) {
       const int64_t ES = static_cast<int64_t>(nblk) * EB * N * N * N;
@@ -199,6 +200,7 @@ hipError_t by_law(const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok) 
       }
       break;
     case OpKind::Diagonal:
+    case OpKind::DiagonalBlocks:
       break;
     case OpKind::Apply:
       if (op.mode == HX_STORE_NONE) {
@@ -247,13 +249,21 @@ hipError_t by_law(const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok) 
   return hipSuccess;
 }
 
+// the diagonal blocks of the three components; with blocks, also the three off-diagonal
+// component pairs into planes 3..5 of the output
 template <typename R, int S>
-hipError_t launch_diag(const HostArgs& h, hipStream_t s) {
+hipError_t launch_diag(const HostArgs& h, bool blocks, hipStream_t s) {
   constexpr int EB = Blocking<N>::EB;
-  const KernelArgs<N, R> a = make_args<R>(h);
+  KernelArgs<N, R> a = make_args<R>(h);
   const int nblk = (h.L.n_cells + EB - 1) / EB;
   if (nblk == 0) return hipSuccess;
-  diag_kernel<N, EB, R, S><<<dim3(nblk), dim3(EB * N * N * N), 0, s>>>(a);
+  diag_kernel<N, EB, R, S, false><<<dim3(nblk), dim3(EB * N * N * N), 0, s>>>(a);
+  if (blocks) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    a.out += 3 * h.L.n_nodes;
+    diag_kernel<N, EB, R, S, true><<<dim3(nblk), dim3(EB * N * N * N), 0, s>>>(a);
+  }
   return hipGetLastError();
 }
 
@@ -263,13 +273,14 @@ hipError_t launch_diag(const HostArgs& h, hipStream_t s) {
 #if HX_TOPO == 0
 hipError_t diagonal(const HostOp& op, const HostArgs& h, hipStream_t s, bool* ok) {
   *ok = true;
+  const bool blocks = op.kind == OpKind::DiagonalBlocks;
   if (op.mode == HX_STORE_TANGENT) {
-    if (!op.fp32 && op.store == kStoreF64) return launch_diag<double, kStoreF64>(h, s);
+    if (!op.fp32 && op.store == kStoreF64) return launch_diag<double, kStoreF64>(h, blocks, s);
     if (op.fp32) {
       switch (op.store) {
-        case kStoreF32: return launch_diag<float, kStoreF32>(h, s);
-        case kStoreBF16: return launch_diag<float, kStoreBF16>(h, s);
-        case kStoreF16: return launch_diag<float, kStoreF16>(h, s);
+        case kStoreF32: return launch_diag<float, kStoreF32>(h, blocks, s);
+        case kStoreBF16: return launch_diag<float, kStoreBF16>(h, blocks, s);
+        case kStoreF16: return launch_diag<float, kStoreF16>(h, blocks, s);
         default: break;
       }
     }
@@ -325,19 +336,19 @@ hipError_t HX_DISPATCH_NAME(HX_TOPO)(const HostOp& op, const HostArgs& h, hipStr
 #if HX_TOPO == 1
   // a lattice with stored geometry: the operations that never read the geometry are those of the
   // lattice of trilinear cells
-  if (op.kind == OpKind::Diagonal ||
+  if (op.kind == OpKind::Diagonal || op.kind == OpKind::DiagonalBlocks ||
       (op.kind == OpKind::Apply && (op.mode == HX_STORE_TANGENT || op.mode == HX_STORE_SPATIAL)))
     return HX_DISPATCH_NAME(0)(op, h, s, ok);
 #endif
 #if HX_TOPO == 2
   // the diagonal kernel addresses lattices only (general meshes have no multigrid)
-  if (op.kind == OpKind::Diagonal) {
+  if (op.kind == OpKind::Diagonal || op.kind == OpKind::DiagonalBlocks) {
     *ok = false;
     return hipSuccess;
   }
 #endif
 #if HX_TOPO == 0
-  if (op.kind == OpKind::Diagonal) return diagonal(op, h, s, ok);
+  if (op.kind == OpKind::Diagonal || op.kind == OpKind::DiagonalBlocks) return diagonal(op, h, s, ok);
 #endif
 #if HX_TOPO != 1
   if (op.kind == OpKind::Apply && op.mode == HX_STORE_TANGENT) return apply_tangent_mode(op, h, s, ok);

@@ -110,7 +110,9 @@ constexpr int kFlagInverted = 1;
 constexpr int kFlagNonFinite = 2;
 
 enum StoreType : int { kStoreF64 = 0, kStoreF32 = 1, kStoreBF16 = 2, kStoreF16 = 3 };
-enum class OpKind : int { Apply = 0, Residual = 1, Update = 2, Diagonal = 3 };
+// Diagonal: the operator's diagonal [3][n_nodes]; DiagonalBlocks: its nodal 3x3 blocks
+// [6][n_nodes] (00, 11, 22, 01, 02, 12)
+enum class OpKind : int { Apply = 0, Residual = 1, Update = 2, Diagonal = 3, DiagonalBlocks = 4 };
 
 // Host-side description of one launch.
 struct HostOp {
@@ -133,6 +135,8 @@ constexpr int kVariants = 2;
 //   kEpiChebyshevFirst  d = c2 dinv (b - t), x += d      (the first step from a nonzero iterate)
 enum EpiKind : int { kEpiStore = 0, kEpiChebyshev = 1, kEpiResidual = 2, kEpiChebyshevFirst = 3 };
 
+// dinv: the smoother's D^-1, point Jacobi [3][n_nodes] (blocks = 0) or the inverses of the nodal
+// 3x3 blocks [6][n_nodes], entries (00, 11, 22, 01, 02, 12) (blocks = 1)
 struct NodeEpilogue {
   int kind;
   const void* b;
@@ -140,6 +144,7 @@ struct NodeEpilogue {
   void* d;
   const void* dinv;
   double c1, c2;
+  int blocks;
 };
 
 // the same with the apply's arithmetic type, as the node kernel receives it
@@ -151,6 +156,7 @@ struct Epi {
   R* d;
   const R* dinv;
   R c1, c2;
+  int blocks;
 };
 
 struct HostArgs {

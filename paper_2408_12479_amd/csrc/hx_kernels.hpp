@@ -1009,10 +1009,16 @@ __global__ void __launch_bounds__(256) assemble_kernel(Lattice L, const R* __res
   // all loads are issued before the first sum: summing each value as it arrives would wait for
   // up to eight memory round trips one after the other
   EpiIn<R> pre[3] = {};
+  R off[3] = {R(0), R(0), R(0)};  // nodal block smoother: the inverse block's entries 01, 02, 12
   if constexpr (EPI) {
     pre[0] = epi_load(ep, node);
     pre[1] = epi_load(ep, n + node);
     pre[2] = epi_load(ep, 2 * n + node);
+    if (ep.blocks && ep.kind != kEpiResidual) {
+      off[0] = ep.dinv[3 * n + node];
+      off[1] = ep.dinv[4 * n + node];
+      off[2] = ep.dinv[5 * n + node];
+    }
   }
   R v[4][3][2];
 #pragma unroll
@@ -1045,9 +1051,24 @@ __global__ void __launch_bounds__(256) assemble_kernel(Lattice L, const R* __res
     }
   }
   if constexpr (EPI) {
-    node_epilogue(ep, node, s0, out, pre[0]);
-    node_epilogue(ep, n + node, s1, out, pre[1]);
-    node_epilogue(ep, 2 * n + node, s2, out, pre[2]);
+    if (ep.blocks && ep.kind != kEpiResidual) {
+      // nodal block Jacobi: the three residual components of the node times the inverse block
+      // (diagonal entries in pre[c].dinv), then the Chebyshev update of each component
+      const R r0 = pre[0].b - s0, r1 = pre[1].b - s1, r2 = pre[2].b - s2;
+      const R w[3] = {pre[0].dinv * r0 + off[0] * r1 + off[1] * r2,
+                      off[0] * r0 + pre[1].dinv * r1 + off[2] * r2,
+                      off[1] * r0 + off[2] * r1 + pre[2].dinv * r2};
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const R di = (ep.kind == kEpiChebyshev ? ep.c1 * pre[c].d : R(0)) + ep.c2 * w[c];
+        ep.d[c * n + node] = di;
+        ep.x[c * n + node] = pre[c].x + di;
+      }
+    } else {
+      node_epilogue(ep, node, s0, out, pre[0]);
+      node_epilogue(ep, n + node, s1, out, pre[1]);
+      node_epilogue(ep, 2 * n + node, s2, out, pre[2]);
+    }
   } else {
     out[node] = s0;
     out[n + node] = s1;
@@ -1874,12 +1895,14 @@ __global__ void __launch_bounds__(EB * N * N * N, (kMinWaves<KIND, MODE, R>))
 }
 
 // ------------------------------------------------------------------------------------------
-// Diagonal of the linearised operator from the stored reference tangent (multigrid smoothers).
-// For node a = (i,j,k) and component c:
-//   diag = sum_q sum_{al,be} D_(c al)(c be)(q) dphi_a/dxi_al(q) dphi_a/dxi_be(q),
+// Diagonal and nodal 3x3 blocks of the linearised operator from the stored reference tangent
+// (multigrid smoothers). For node a = (i,j,k) and components c, d:
+//   K_(c a)(d a) = sum_q sum_{al,be} D_(c al)(d be)(q) dphi_a/dxi_al(q) dphi_a/dxi_be(q),
 // and dphi_a/dxi_al dphi_a/dxi_be factorises per direction into products of the 1D tables
 // B (values) and G (derivatives of the nodal basis at the Gauss points), so each of the six
-// unique (al, be) pairs is three transposed 1D sweeps.
+// unique (al, be) pairs (the product is symmetric in al, be) is three transposed 1D sweeps, with
+// the coefficient D_(c al)(d be) + D_(c be)(d al) for al < be. The three fields of a pass are the
+// components c = d (OFF false: the diagonal) or the pairs (0,1), (0,2), (1,2) (OFF true).
 // ------------------------------------------------------------------------------------------
 template <int N, int AL, int BE, int DIR, typename R>
 __device__ __forceinline__ R diag_coef(int q, int i) {
@@ -1901,14 +1924,28 @@ __device__ __forceinline__ void diag_apply1d(const R* in, R* out) {
 
 __host__ __device__ constexpr int packed_index(int a, int b) { return a * 9 - a * (a + 1) / 2 + b; }
 
-template <int N, int EB, int AL, int BE, typename R>
+// components (c, d) of field f of a diagonal (OFF false) or off-diagonal (OFF true) pass
+template <bool OFF>
+__host__ __device__ constexpr int pair_c(int f) { return OFF ? (f == 2 ? 1 : 0) : f; }
+template <bool OFF>
+__host__ __device__ constexpr int pair_d(int f) { return OFF ? (f == 0 ? 1 : 2) : f; }
+
+template <int N, int EB, int AL, int BE, bool OFF, typename R>
 __device__ __forceinline__ void diag_pair(R* sb, const R* Dv, int le_me, int q_me) {
   constexpr int Q = N * N * N;
   constexpr int CB = 6 * Lds<N>::FS;
-  constexpr R fac = AL == BE ? R(1) : R(2);
   R* cb = sb + le_me * CB;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) cb[c * Lds<N>::FS + lds_q<N>(q_me)] = fac * Dv[packed_index(3 * c + AL, 3 * c + BE)];
+  for (int f = 0; f < 3; ++f) {
+    const int c = pair_c<OFF>(f), d = pair_d<OFF>(f);
+    // D is symmetric, stored as its upper triangle; 3c + AL <= 3d + BE always holds here
+    R coef = Dv[packed_index(3 * c + AL, 3 * d + BE)];
+    if constexpr (AL != BE) {
+      const int r = 3 * c + BE, k = 3 * d + AL;
+      coef += r <= k ? Dv[packed_index(r, k)] : Dv[packed_index(k, r)];
+    }
+    cb[f * Lds<N>::FS + lds_q<N>(q_me)] = coef;
+  }
   __syncthreads();
   pencil_jobs<N, EB, 3>([&](int le, int c, int i, int j) __attribute__((always_inline)) {
     R in[N], out[N];
@@ -1943,7 +1980,7 @@ __device__ __forceinline__ void diag_pair(R* sb, const R* Dv, int le_me, int q_m
   __syncthreads();
 }
 
-template <int N, int EB, typename R, int S>
+template <int N, int EB, typename R, int S, bool OFF>
 __global__ void __launch_bounds__(EB * N * N * N) diag_kernel(KernelArgs<N, R> a) {
   constexpr int Q = N * N * N;
   constexpr int EBQ = EB * Q;
@@ -1966,12 +2003,12 @@ __global__ void __launch_bounds__(EB * N * N * N) diag_kernel(KernelArgs<N, R> a
   R* cb = sb + le * 6 * Lds<N>::FS;
 #pragma unroll
   for (int c = 0; c < 3; ++c) cb[(3 + c) * Lds<N>::FS + lds_q<N>(q)] = R(0);
-  diag_pair<N, EB, 0, 0>(sb, Dv, le, q);
-  diag_pair<N, EB, 1, 1>(sb, Dv, le, q);
-  diag_pair<N, EB, 2, 2>(sb, Dv, le, q);
-  diag_pair<N, EB, 0, 1>(sb, Dv, le, q);
-  diag_pair<N, EB, 0, 2>(sb, Dv, le, q);
-  diag_pair<N, EB, 1, 2>(sb, Dv, le, q);
+  diag_pair<N, EB, 0, 0, OFF>(sb, Dv, le, q);
+  diag_pair<N, EB, 1, 1, OFF>(sb, Dv, le, q);
+  diag_pair<N, EB, 2, 2, OFF>(sb, Dv, le, q);
+  diag_pair<N, EB, 0, 1, OFF>(sb, Dv, le, q);
+  diag_pair<N, EB, 0, 2, OFF>(sb, Dv, le, q);
+  diag_pair<N, EB, 1, 2, OFF>(sb, Dv, le, q);
   if (!valid) return;
   const Lattice& L = a.L;
   const int i = q % N, j = (q / N) % N, k = q / (N * N);

@@ -78,6 +78,52 @@ __global__ void k_cheb_step(T* x, T* d, const T* b, const T* t, const T* dinv, T
   }
 }
 
+// The nodal block smoother's D^-1 r at node i: dinv holds the inverse blocks as planes
+// (00, 11, 22, 01, 02, 12) of nn nodes; r_c = b[c nn + i] - t[c nn + i] (t may be null).
+template <typename T>
+__device__ __forceinline__ void block_solve(const T* dinv, const T* b, const T* t, int64_t i, int64_t nn, T w[3]) {
+  T r[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) r[c] = b[c * nn + i] - (t ? t[c * nn + i] : T(0));
+  const T a00 = dinv[i], a11 = dinv[nn + i], a22 = dinv[2 * nn + i];
+  const T a01 = dinv[3 * nn + i], a02 = dinv[4 * nn + i], a12 = dinv[5 * nn + i];
+  w[0] = a00 * r[0] + a01 * r[1] + a02 * r[2];
+  w[1] = a01 * r[0] + a11 * r[1] + a12 * r[2];
+  w[2] = a02 * r[0] + a12 * r[1] + a22 * r[2];
+}
+
+// k_cheb_first with the nodal block smoother (one thread per node, nn nodes)
+template <typename T>
+__global__ void k_cheb_first_blk(T* x, T* d, const T* b, const T* t, const T* dinv, T c, int first,
+                                 int64_t nn) {
+  HX_GRID_LOOP(i, nn) {
+    T w[3];
+    block_solve(dinv, b, t, i, nn, w);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const T di = c * w[k];
+      const T xo = first ? T(0) : x[k * nn + i];
+      d[k * nn + i] = di;
+      x[k * nn + i] = first ? di : xo + di;
+    }
+  }
+}
+
+// k_cheb_step with the nodal block smoother
+template <typename T>
+__global__ void k_cheb_step_blk(T* x, T* d, const T* b, const T* t, const T* dinv, T c1, T c2, int64_t nn) {
+  HX_GRID_LOOP(i, nn) {
+    T w[3];
+    block_solve(dinv, b, t, i, nn, w);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const T di = c1 * d[k * nn + i] + c2 * w[k];
+      d[k * nn + i] = di;
+      x[k * nn + i] += di;
+    }
+  }
+}
+
 // out[k] += sum a_k b_k for up to three pairs, FP64 accumulation
 template <typename T>
 __global__ void k_dots(const T* a0, const T* b0, const T* a1, const T* b1, const T* a2,
@@ -185,6 +231,31 @@ __global__ void k_diag_finish(T* d, Lattice L) {
   HX_GRID_LOOP(i, 3 * L.n_nodes) {
     const T v = node_constrained(L, i % L.n_nodes) ? T(1) : d[i];
     d[i] = T(1) / v;
+  }
+}
+
+// nodal blocks (planes 00, 11, 22, 01, 02, 12) -> their inverses, in FP64 by the adjugate; the
+// identity at constrained nodes
+template <typename T>
+__global__ void k_block_finish(T* d, Lattice L) {
+  const int64_t nn = L.n_nodes;
+  HX_GRID_LOOP(i, nn) {
+    if (node_constrained(L, i)) {
+      d[i] = d[nn + i] = d[2 * nn + i] = T(1);
+      d[3 * nn + i] = d[4 * nn + i] = d[5 * nn + i] = T(0);
+      continue;
+    }
+    const double a00 = d[i], a11 = d[nn + i], a22 = d[2 * nn + i];
+    const double a01 = d[3 * nn + i], a02 = d[4 * nn + i], a12 = d[5 * nn + i];
+    const double c00 = a11 * a22 - a12 * a12, c01 = a02 * a12 - a01 * a22, c02 = a01 * a12 - a02 * a11;
+    const double c11 = a00 * a22 - a02 * a02, c12 = a01 * a02 - a00 * a12, c22 = a00 * a11 - a01 * a01;
+    const double inv = 1.0 / (a00 * c00 + a01 * c01 + a02 * c02);
+    d[i] = static_cast<T>(c00 * inv);
+    d[nn + i] = static_cast<T>(c11 * inv);
+    d[2 * nn + i] = static_cast<T>(c22 * inv);
+    d[3 * nn + i] = static_cast<T>(c01 * inv);
+    d[4 * nn + i] = static_cast<T>(c02 * inv);
+    d[5 * nn + i] = static_cast<T>(c12 * inv);
   }
 }
 
@@ -710,7 +781,7 @@ hipError_t level_apply(hx_mg mg, int l, const T* x, T* y) {
 template <typename T>
 hipError_t level_apply_epi(hx_mg mg, int l, T* x, T* y, int kind, const T* b, T* d, const T* dinv, double c1,
                            double c2) {
-  const NodeEpilogue epi{kind, b, x, d, dinv, c1, c2};
+  const NodeEpilogue epi{kind, b, x, d, dinv, c1, c2, mg->opt.smoother_blocks};
   const hx_status st = hx::apply_with_epilogue(mg->lv[l], x, y, level_prec(mg, l), mg->stream, epi);
   return st == HX_OK ? hipSuccess : hipErrorLaunchFailure;
 }
@@ -736,15 +807,24 @@ hipError_t chebyshev(hx_mg mg, int l, int deg, bool zero_init) {
   double rho_old = 1.0 / sigma;
   hipError_t e;
   const bool fuse = mg->opt.fuse_smoother != 0;
+  const bool blk = mg->opt.smoother_blocks != 0;
+  const int64_t nn = c->L.n_nodes;
+  // separate smoother steps: point or nodal block Jacobi
+  auto first_step = [&](const T* tt, int first) {
+    if (blk)
+      k_cheb_first_blk<T><<<grid_for(nn), 256, 0, mg->stream>>>(x, d, b, tt, dinv, static_cast<T>(1.0 / theta), first, nn);
+    else
+      k_cheb_first<T><<<grid_for(n), 256, 0, mg->stream>>>(x, d, b, tt, dinv, static_cast<T>(1.0 / theta), first, n);
+  };
   if (zero_init) {
-    k_cheb_first<T><<<grid_for(n), 256, 0, mg->stream>>>(x, d, b, nullptr, dinv, static_cast<T>(1.0 / theta), 1, n);
+    first_step(nullptr, 1);
   } else if (fuse) {
     // the step in the apply's node kernel (no separate pass over the vectors)
     if ((e = level_apply_epi<T>(mg, l, x, t, kEpiChebyshevFirst, b, d, dinv, 0.0, 1.0 / theta)) != hipSuccess)
       return e;
   } else {
     if ((e = level_apply<T>(mg, l, x, t)) != hipSuccess) return e;
-    k_cheb_first<T><<<grid_for(n), 256, 0, mg->stream>>>(x, d, b, t, dinv, static_cast<T>(1.0 / theta), 0, n);
+    first_step(t, 0);
   }
   for (int k = 1; k < deg; ++k) {
     const double rho = 1.0 / (2.0 * sigma - rho_old);
@@ -753,7 +833,11 @@ hipError_t chebyshev(hx_mg mg, int l, int deg, bool zero_init) {
       if ((e = level_apply_epi<T>(mg, l, x, t, kEpiChebyshev, b, d, dinv, c1, c2)) != hipSuccess) return e;
     } else {
       if ((e = level_apply<T>(mg, l, x, t)) != hipSuccess) return e;
-      k_cheb_step<T><<<grid_for(n), 256, 0, mg->stream>>>(x, d, b, t, dinv, static_cast<T>(c1), static_cast<T>(c2), n);
+      if (blk)
+        k_cheb_step_blk<T><<<grid_for(nn), 256, 0, mg->stream>>>(x, d, b, t, dinv, static_cast<T>(c1),
+                                                                 static_cast<T>(c2), nn);
+      else
+        k_cheb_step<T><<<grid_for(n), 256, 0, mg->stream>>>(x, d, b, t, dinv, static_cast<T>(c1), static_cast<T>(c2), n);
     }
     rho_old = rho;
   }
@@ -856,8 +940,16 @@ hipError_t estimate_spectrum(hx_mg mg, int l, double* lmax, double* lmin) {
   T* q = B[B_T].as<T>();
   T* p = B[B_D].as<T>();
   const T* dinv = B[B_DINV].as<T>();
+  const int64_t nn = c->L.n_nodes;
+  // z = D^-1 r (point or nodal block Jacobi)
+  auto precond = [&]() {
+    if (mg->opt.smoother_blocks)
+      k_cheb_first_blk<T><<<grid_for(nn), 256, 0, mg->stream>>>(z, z, r, nullptr, dinv, T(1), 1, nn);
+    else
+      k_cheb_first<T><<<grid_for(n), 256, 0, mg->stream>>>(z, z, r, nullptr, dinv, T(1), 1, n);
+  };
   k_hash_vector<T><<<grid_for(n), 256, 0, mg->stream>>>(r, c->L);
-  k_cheb_first<T><<<grid_for(n), 256, 0, mg->stream>>>(z, z, r, nullptr, dinv, T(1), 1, n);
+  precond();
   k_convert<T, T><<<grid_for(n), 256, 0, mg->stream>>>(z, p, n);
   double h[3];
   hipError_t e = dots<T>(mg, n, 1, r, z, nullptr, nullptr, nullptr, nullptr, h);
@@ -870,7 +962,7 @@ hipError_t estimate_spectrum(hx_mg mg, int l, double* lmax, double* lmin) {
     if (!(h[0] > 0.0)) break;
     const double a = rz / h[0];
     k_axpby<T><<<grid_for(n), 256, 0, mg->stream>>>(r, static_cast<T>(-a), q, T(1), n);
-    k_cheb_first<T><<<grid_for(n), 256, 0, mg->stream>>>(z, z, r, nullptr, dinv, T(1), 1, n);
+    precond();
     if ((e = dots<T>(mg, n, 1, r, z, nullptr, nullptr, nullptr, nullptr, h)) != hipSuccess) return e;
     const double bta = h[0] / rz;
     alpha.push_back(a);
@@ -948,19 +1040,23 @@ hipError_t level_diagonal(hx_mg mg, int l) {
   const hx_ctx c = mg->lv[l];
   const int64_t n = 3 * c->L.n_nodes;
   T* dinv = mg->buf[l][B_DINV].as<T>();
-  k_fill<T><<<grid_for(n), 256, 0, mg->stream>>>(dinv, T(0), n);
+  const bool blk = mg->opt.smoother_blocks != 0;
+  k_fill<T><<<grid_for(blk ? 2 * n : n), 256, 0, mg->stream>>>(dinv, T(0), blk ? 2 * n : n);
   const Slot& sl = c->slot[mg->fp32 ? 1 : 0];
   if (sl.variant != 0) return hipErrorInvalidValue;  // the diagonal reads the default layout
   HostArgs h = args_for(c);
   h.out = dinv;
   h.qdata = sl.qdata;
   h.cscale = sl.cscale;
-  HostOp op{OpKind::Diagonal, c->base.mat.law, HX_STORE_TANGENT, sl.store, mg->fp32};
+  HostOp op{blk ? OpKind::DiagonalBlocks : OpKind::Diagonal, c->base.mat.law, HX_STORE_TANGENT, sl.store, mg->fp32};
   bool ok = false;
   hipError_t e = dispatch(c->p, op, h, mg->stream, &ok);
   if (!ok) return hipErrorInvalidValue;
   if (e != hipSuccess) return e;
-  k_diag_finish<T><<<grid_for(n), 256, 0, mg->stream>>>(dinv, c->L);
+  if (blk)
+    k_block_finish<T><<<grid_for(c->L.n_nodes), 256, 0, mg->stream>>>(dinv, c->L);
+  else
+    k_diag_finish<T><<<grid_for(n), 256, 0, mg->stream>>>(dinv, c->L);
   return hipGetLastError();
 }
 
@@ -1006,7 +1102,8 @@ hx_status hx_mg_create(const hx_ctx* levels, int32_t n_levels, const hx_mg_optio
         (o.precision != HX_FP32 && o.precision != HX_FP64 && o.precision != HX_FP32_BF16DATA &&
          o.precision != HX_FP32_FP16DATA) ||
         !mode_ok ||
-        o.coarse_solver < 0 || o.coarse_solver > 2 || o.fuse_smoother < 0 || o.fuse_smoother > 1) {
+        o.coarse_solver < 0 || o.coarse_solver > 2 || o.fuse_smoother < 0 || o.fuse_smoother > 1 ||
+        o.smoother_blocks < 0 || o.smoother_blocks > 1) {
       delete mg;
       return HX_E_ARG;
     }
@@ -1029,7 +1126,10 @@ hx_status hx_mg_create(const hx_ctx* levels, int32_t n_levels, const hx_mg_optio
   for (int l = 0; l < n_levels && e == hipSuccess; ++l) {
     mg->buf.emplace_back(new DevBuf[B_COUNT]);
     for (int k = 0; k < B_COUNT && e == hipSuccess; ++k) {
-      const size_t b = k == B_U ? 3 * levels[l]->L.n_nodes * sizeof(double) : vec_bytes(mg, l);
+      // D^-1: 3 values per node (point Jacobi) or 6 (nodal blocks)
+      const size_t b = k == B_U      ? 3 * levels[l]->L.n_nodes * sizeof(double)
+                       : k == B_DINV ? vec_bytes(mg, l) * (o.smoother_blocks ? 2 : 1)
+                                     : vec_bytes(mg, l);
       e = mg->buf[l][k].alloc(b);
     }
   }
@@ -1065,6 +1165,7 @@ hx_status hx_mg_default_options(hx_mg_options* o) {
   o->level_mode = HX_STORE_TANGENT;
   o->coarse_solver = 0;
   o->fuse_smoother = 1;
+  o->smoother_blocks = 1;
   return HX_OK;
 }
 
@@ -1218,7 +1319,8 @@ hx_status hx_mg_inverse_diagonal(hx_mg mg, int32_t level, void* out, void* strea
   if (!mg->ready) return mg_fail(mg, HX_E_STATE, "hx_mg_inverse_diagonal: no hx_mg_update yet");
   hipStream_t s = static_cast<hipStream_t>(stream);
   (void)hipStreamSynchronize(mg->stream);
-  const hipError_t e = hipMemcpyAsync(out, mg->buf[level][B_DINV].p, vec_bytes(mg, level), hipMemcpyDeviceToDevice, s);
+  const size_t bytes = vec_bytes(mg, level) * (mg->opt.smoother_blocks ? 2 : 1);
+  const hipError_t e = hipMemcpyAsync(out, mg->buf[level][B_DINV].p, bytes, hipMemcpyDeviceToDevice, s);
   return e == hipSuccess ? HX_OK : mg_fail(mg, HX_E_HIP, "hx_mg_inverse_diagonal: copy");
 }
 

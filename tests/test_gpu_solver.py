@@ -2,7 +2,8 @@
 
 * transfers: prolongation, restriction (= transpose) and interpolation of the linearisation point
   against the oracle's dense transfer matrices (FP64 hierarchy, element by element);
-* inverse diagonal of each level against the diagonal of the oracle's assembled operator;
+* the smoother's D^-1 of each level against the oracle's assembled operator: the inverse diagonal
+  (point Jacobi) or the inverses of the nodal 3x3 blocks;
 * V-cycle: symmetric (FP64), convergent as a stationary iteration, graph replay = eager launch;
 * dead-load surface vector against the oracle;
 * Newton solve: the solution satisfies the oracle's residual equation to the solve tolerance, in
@@ -74,27 +75,45 @@ def test_transfers_match_oracle(device):
     mg.close()
 
 
+def _inverse_node_blocks(K, n):
+    """Planes (00, 11, 22, 01, 02, 12) of the inverses of the 3x3 blocks that couple the three
+    components of each node in the assembled operator (identity blocks at constrained nodes)."""
+    B = np.zeros((n, 3, 3))
+    for c in range(3):
+        for d in range(3):
+            B[:, c, d] = np.diag(K[c * n:(c + 1) * n, d * n:(d + 1) * n])
+    Bi = np.linalg.inv(B)
+    return np.stack([Bi[:, 0, 0], Bi[:, 1, 1], Bi[:, 2, 2], Bi[:, 0, 1], Bi[:, 0, 2], Bi[:, 1, 2]])
+
+
 @pytest.mark.parametrize("law", ["cnh", "fiber"])
-def test_inverse_diagonal_matches_oracle(device, law):
+@pytest.mark.parametrize("blocks", [False, True])
+def test_inverse_diagonal_matches_oracle(device, law, blocks):
     ops, pbs = _levels((2, 2, 1), [3, 1], law=law, faces=(0,))
     u = _smooth_u(pbs[0])
-    mg = hx.Multigrid(ops, precision="fp64")
+    mg = hx.Multigrid(ops, precision="fp64", smoother_blocks=blocks)
     mg.update(to_dev(u))
-    dinv = to_host(mg.inverse_diagonal(0), ops[0].num_nodes)
-    K = pbs[0].tangent_matrix(u)
-    assert rel(dinv.ravel(), 1.0 / np.diag(K)) < 1e-12
     # the coarse level is linearised at the fine displacement interpolated onto its nodes
     J = fem.interpolation_matrix(pbs[0].mesh, pbs[1].mesh)
-    uc = (J @ u.T).T
-    dinv1 = to_host(mg.inverse_diagonal(1), ops[1].num_nodes)
-    assert rel(dinv1.ravel(), 1.0 / np.diag(pbs[1].tangent_matrix(uc))) < 1e-12
+    for level, ul in ((0, u), (1, (J @ u.T).T)):
+        n = ops[level].num_nodes
+        K = pbs[level].tangent_matrix(ul)
+        got = mg.inverse_diagonal(level).cpu().numpy()
+        if blocks:
+            ref = _inverse_node_blocks(K, n)
+            assert rel(got.reshape(6, n), ref) < 1e-12
+            # the blocks couple the components: the off-diagonal entries are not negligible
+            assert np.abs(ref[3:]).max() > 1e-3 * np.abs(ref[:3]).max()
+        else:
+            assert rel(got, 1.0 / np.diag(K)) < 1e-12
     mg.close()
 
 
-def test_vcycle_symmetric_and_convergent(device):
+@pytest.mark.parametrize("blocks", [False, True])
+def test_vcycle_symmetric_and_convergent(device, blocks):
     ops, pbs = _levels((3, 3, 2), [3, 2, 1], faces=(0,))
     u = _smooth_u(pbs[0])
-    mg = hx.Multigrid(ops, precision="fp64", coarse_degree=20)
+    mg = hx.Multigrid(ops, precision="fp64", coarse_degree=20, smoother_blocks=blocks)
     mg.update(to_dev(u))
     n = ops[0].num_nodes
     rng = np.random.default_rng(5)
@@ -338,10 +357,12 @@ def test_hp_hierarchy_vcycle_on_ring(device):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_fused_smoother_equals_unfused(device, precision):
+@pytest.mark.parametrize("blocks", [False, True])
+def test_fused_smoother_equals_unfused(device, precision, blocks):
     """The Chebyshev steps and the pre-restriction residual fused into the level applies' node
     kernels give the V-cycle of the separate kernels (FP64 within 1e-12, FP32 within 1e-5), on a
-    hierarchy with degree and lattice levels and a dense coarse solve."""
+    hierarchy with degree and lattice levels and a dense coarse solve, with point or nodal block
+    Jacobi."""
     ops, pbs = _levels((4, 2, 4), [3, 2, 1], law="inh", faces=(0,), mu=2.0, kappa=50.0)
     ops += _levels((2, 2, 2), [1], law="inh", faces=(0,), mu=2.0, kappa=50.0)[0]
     u = _smooth_u(pbs[0])
@@ -351,7 +372,7 @@ def test_fused_smoother_equals_unfused(device, precision):
     dt = "float64" if precision == "fp64" else "float32"
     outs = []
     for fuse in (True, False):
-        mg = hx.Multigrid(ops, precision=precision, fuse_smoother=fuse)
+        mg = hx.Multigrid(ops, precision=precision, fuse_smoother=fuse, smoother_blocks=blocks)
         mg.update(to_dev(u))
         z = to_host(mg.vcycle(to_dev(r, dt)), ops[0].num_nodes)
         outs.append(z)
