@@ -355,7 +355,7 @@ typedef struct {
   int32_t smoother_degree; /* Chebyshev degree of the Jacobi smoother on all but the coarsest
                               level (default 4) */
   int32_t coarse_degree;   /* Chebyshev degree of the approximate coarse solve (default 30) */
-  double smoothing_range;  /* smoother interval [lambda_max / range, lambda_max] (default 20); the
+  double smoothing_range;  /* smoother interval [lambda_max / range, lambda_max] (default 100); the
                               coarse Chebyshev solve extends it down to the smallest Ritz value */
   int32_t eig_iters;       /* Lanczos (Jacobi-preconditioned CG) steps that estimate the extreme
                               eigenvalues of D^-1 A (default 20) */

@@ -450,7 +450,7 @@ def _check_mg(status, mg):
 class Multigrid:
     """p-multigrid V-cycle over operators on the same lattice with decreasing degrees."""
 
-    def __init__(self, levels, smoother_degree=4, coarse_degree=30, smoothing_range=20.0, eig_iters=20,
+    def __init__(self, levels, smoother_degree=4, coarse_degree=30, smoothing_range=100.0, eig_iters=20,
                  eig_safety=1.2, precision="fp32", use_graph=True, level_mode="tangent", coarse_solver="auto",
                  fuse_smoother=True, smoother_blocks=True):
         """levels: Operators, finest first (see hx_mg_create for the allowed level pairs).

@@ -1157,7 +1157,7 @@ hx_status hx_mg_default_options(hx_mg_options* o) {
   *o = hx_mg_options{};
   o->smoother_degree = 4;
   o->coarse_degree = 30;
-  o->smoothing_range = 20.0;
+  o->smoothing_range = 100.0;
   o->eig_iters = 20;
   o->eig_safety = 1.2;
   o->precision = HX_FP32;
