@@ -367,11 +367,11 @@ typedef struct {
                               stored tangents (the level mode is then TANGENT); HX_FP64:
                               everything in FP64 */
   int32_t use_graph;       /* 1: one V-cycle is captured into a HIP graph per update */
-  hx_storage level_mode;   /* storage mode of the level operators inside the V-cycle: NONE,
-                              FINV_J, TANGENT (default), SPATIAL, SPATIAL_RECOMPUTE or AUTO
-                              (hx_autotune_storage on each
-                              level at the first update; the choice is kept). The inverse
-                              diagonal always comes from a TANGENT update of the level. */
+  hx_storage level_mode;   /* storage mode of the level operators inside the V-cycle: any of
+                              the eight modes (default TANGENT) or AUTO (hx_autotune_storage on
+                              each level at the first update; the choice is kept). The
+                              smoother's D (diagonal or nodal blocks) always comes from a TANGENT
+                              update of the level. */
   int32_t coarse_solver;   /* coarsest level: 0 = dense if it has at most 8192 DoFs, else
                               Chebyshev (default); 1 = Chebyshev of coarse_degree; 2 = dense
                               (HX_E_UNSUPPORTED above 32768 DoFs; 20 n^2 bytes of device memory). Dense: the level operator is
@@ -407,8 +407,9 @@ hx_status hx_mg_destroy(hx_mg mg);
 const char* hx_mg_last_error(hx_mg mg);
 
 /* Linearisation of every level at the finest-level displacement u (device FP64 [3][n_nodes]):
- * u is interpolated onto the coarser nodes, each level stores its tangent, its inverse diagonal
- * and a lambda_max estimate; the V-cycle is then captured into a graph. Synchronous. */
+ * u is interpolated onto the coarser nodes, each level stores its tangent, the smoother's D^-1
+ * (inverse diagonal or inverse nodal blocks) and a lambda_max estimate; the V-cycle is then
+ * captured into a graph. Synchronous. */
 hx_status hx_mg_update(hx_mg mg, const double* u, void* stream);
 
 /* z = M^-1 r with one V-cycle (pre/post Chebyshev smoothing, restriction by the transpose of the
