@@ -110,10 +110,13 @@ def test_inverse_diagonal_matches_oracle(device, law, blocks):
 
 
 @pytest.mark.parametrize("blocks", [False, True])
-def test_vcycle_symmetric_and_convergent(device, blocks):
+@pytest.mark.parametrize("coarse", ["auto", "chebyshev"])
+def test_vcycle_symmetric_and_convergent(device, blocks, coarse):
+    # coarse "auto" factors the small coarsest level; "chebyshev" runs the Chebyshev coarse solve
+    # over the Lanczos interval widened to the smallest Ritz value
     ops, pbs = _levels((3, 3, 2), [3, 2, 1], faces=(0,))
     u = _smooth_u(pbs[0])
-    mg = hx.Multigrid(ops, precision="fp64", coarse_degree=20, smoother_blocks=blocks)
+    mg = hx.Multigrid(ops, precision="fp64", coarse_degree=20, smoother_blocks=blocks, coarse_solver=coarse)
     mg.update(to_dev(u))
     n = ops[0].num_nodes
     rng = np.random.default_rng(5)
