@@ -450,6 +450,11 @@ typedef struct {
                              hierarchy shares the
                              finest level's data with the outer operator and ignores it. */
   int32_t verbose;        /* 1: one progress line per Newton iteration on stderr */
+  int32_t predictor;      /* 1: each load step after the first starts from the previous converged
+                             displacement plus the previous step's increment (secant predictor),
+                             unless the new load's residual is not finite there; the step's
+                             ||r_0|| is still that of the previous displacement. 0: Newton starts
+                             from the previous displacement. */
 } hx_newton_opts;
 
 typedef struct {

@@ -84,7 +84,7 @@ class _NewtonOpts(ctypes.Structure):
     _fields_ = [("newton_rel_tol", ctypes.c_double), ("newton_abs_tol", ctypes.c_double),
                 ("max_newton", ctypes.c_int32), ("krylov_rel_tol", ctypes.c_double),
                 ("max_krylov", ctypes.c_int32), ("load_steps", ctypes.c_int32), ("outer_mode", ctypes.c_int),
-                ("verbose", ctypes.c_int32)]
+                ("verbose", ctypes.c_int32), ("predictor", ctypes.c_int32)]
 
 
 class _NewtonReport(ctypes.Structure):
@@ -525,10 +525,13 @@ class Multigrid:
         return out
 
     def newton_solve(self, u, f_ext=None, rel_tol=1e-8, abs_tol=0.0, max_newton=20, krylov_rel_tol=1e-3,
-                     max_krylov=500, load_steps=1, outer_mode="tangent", stream=None, check=True, verbose=False):
+                     max_krylov=500, load_steps=1, outer_mode="tangent", stream=None, check=True, verbose=False,
+                     predictor=True):
+        """predictor: load steps after the first start from the secant extrapolation of the previous
+        two converged displacements unless its residual is not finite (see hx_newton_opts)."""
         import torch
         o = _NewtonOpts(float(rel_tol), float(abs_tol), int(max_newton), float(krylov_rel_tol), int(max_krylov),
-                        int(load_steps), MODES[outer_mode], int(bool(verbose)))
+                        int(load_steps), MODES[outer_mode], int(bool(verbose)), int(bool(predictor)))
         rep = _NewtonReport()
         f = None if f_ext is None else self.levels[0]._vec(f_ext, torch.float64, "f_ext")
         st = lib.hx_newton_solve(self.mg, self.levels[0]._vec(u, torch.float64, "u"), f, ctypes.byref(o),

@@ -729,6 +729,7 @@ struct hx_mg_s {
   std::string err;
   // Newton / Krylov work vectors (FP64, finest level)
   DevBuf r, x, p, q, z, f;
+  DevBuf us, du;                      // load stepping: displacement at the step's start, last increment
   DevBuf cg;                          // device scalars of the PCG (CG_*), with the ||r||^2 history
   hipGraphExec_t cg_exec = nullptr;   // one PCG iteration, captured per linearisation
   // dense coarse solve: the coarsest operator is assembled by probing, factored by Cholesky and
@@ -1418,6 +1419,8 @@ hx_status hx_newton_solve(hx_mg mg, double* u, const double* f_ext, const hx_new
   DevBuf* W[] = {&mg->r, &mg->x, &mg->p, &mg->q, &mg->z, &mg->f};
   for (DevBuf* b : W)
     if ((e = b->alloc(nb)) != hipSuccess) return mg_fail(mg, HX_E_NOMEM, "hx_newton_solve: work vectors");
+  if (opt->predictor && ((e = mg->us.alloc(nb)) != hipSuccess || (e = mg->du.alloc(nb)) != hipSuccess))
+    return mg_fail(mg, HX_E_NOMEM, "hx_newton_solve: predictor vectors");
   if ((e = mg->cg.alloc(CG_COUNT * sizeof(double))) != hipSuccess)
     return mg_fail(mg, HX_E_NOMEM, "hx_newton_solve: scalars");
   hipStream_t caller = static_cast<hipStream_t>(stream);
@@ -1446,12 +1449,39 @@ hx_status hx_newton_solve(hx_mg mg, double* u, const double* f_ext, const hx_new
                        opt->outer_mode == HX_STORE_AUTO;
   if (!mode_ok) return mg_fail(mg, HX_E_ARG, "hx_newton_solve: unknown outer_mode");
   int outer = opt->outer_mode == HX_STORE_AUTO ? -1 : opt->outer_mode;
+  double* us = opt->predictor ? mg->us.as<double>() : nullptr;
+  double* du = opt->predictor ? mg->du.as<double>() : nullptr;
   for (int step = 1; step <= opt->load_steps && status == HX_OK; ++step) {
     const double scale = static_cast<double>(step) / opt->load_steps;
     if ((status = residual(scale)) != HX_OK) break;
     if ((e = dots<double>(mg, n, 1, r, r, nullptr, nullptr, nullptr, nullptr, h)) != hipSuccess) { status = HX_E_HIP; break; }
     double rn = std::sqrt(h[0]);
     const double r0 = rn;
+    if (us) {
+      k_convert<double, double><<<grid_for(n), 256, 0, mg->stream>>>(u, us, n);
+      if (step > 1) {
+        // secant predictor u_k + (u_k - u_(k-1)). Its residual is often larger than at u_k (the
+        // extrapolation's error sits in the stiff volumetric modes), yet Newton converges from it
+        // in fewer steps, because one linear solve removes that error; it is dropped only where
+        // the residual is not finite (a state that inverts cells)
+        k_axpby<double><<<grid_for(n), 256, 0, mg->stream>>>(u, 1.0, du, 1.0, n);
+        if ((status = residual(scale)) != HX_OK) break;
+        if ((e = dots<double>(mg, n, 1, r, r, nullptr, nullptr, nullptr, nullptr, h)) != hipSuccess) { status = HX_E_HIP; break; }
+        const double rp = std::sqrt(h[0]);
+        const bool keep = std::isfinite(rp);
+        if (keep) {
+          rn = rp;
+        } else {
+          k_convert<double, double><<<grid_for(n), 256, 0, mg->stream>>>(us, u, n);
+          if ((status = residual(scale)) != HX_OK) break;
+        }
+        if (opt->verbose) {
+          std::fprintf(stderr, "[hx_newton] load step %d/%d  predictor |r|/|r0| %.3e (%s)\n", step, opt->load_steps,
+                       rp / r0, keep ? "kept" : "dropped");
+          std::fflush(stderr);
+        }
+      }
+    }
     if (step == 1) R.initial_residual = r0;
     int it = 0;
     bool converged = rn <= std::max(opt->newton_abs_tol, opt->newton_rel_tol * r0);
@@ -1531,6 +1561,11 @@ hx_status hx_newton_solve(hx_mg mg, double* u, const double* f_ext, const hx_new
     }
     R.newton_iters += it;
     R.final_residual = rn;
+    if (us && status == HX_OK) {
+      // this step's increment, from the previous converged displacement
+      k_convert<double, double><<<grid_for(n), 256, 0, mg->stream>>>(u, du, n);
+      k_axpby<double><<<grid_for(n), 256, 0, mg->stream>>>(du, -1.0, us, 1.0, n);
+    }
     if (status == HX_OK) {
       R.load_steps_done = step;
       if (!converged) status = HX_E_NOT_CONVERGED;

@@ -190,6 +190,27 @@ def test_newton_solve_box(device, precision):
     mg.close()
 
 
+def test_newton_load_step_predictor(device):
+    """Load steps started from the secant predictor reach the same solution (each satisfies the
+    oracle's residual equation to the Newton tolerance) in no more Newton steps than without it."""
+    ops, pbs = _levels((3, 2, 2), [2, 1], faces=(0,), mu=1.0, lam=10.0)
+    f = -ops[0].surface_load(1, 0.15)
+    fo = f.copy()
+    fo[:, pbs[0].mesh.constrained] = 0.0
+    sols, reps = {}, {}
+    for pred in (True, False):
+        mg = hx.Multigrid(ops, precision="fp32")
+        u = torch.zeros(ops[0].num_dofs, dtype=torch.float64, device="cuda")
+        reps[pred] = mg.newton_solve(u, to_dev(f), rel_tol=1e-9, krylov_rel_tol=1e-4, load_steps=4,
+                                     outer_mode="tangent", predictor=pred)
+        assert reps[pred]["status"] == "HX_OK"
+        sols[pred] = to_host(u, ops[0].num_nodes)
+        assert np.linalg.norm(pbs[0].residual(sols[pred]) - fo) < 1e-8 * np.linalg.norm(fo)
+        mg.close()
+    assert reps[True]["newton_iters"] <= reps[False]["newton_iters"]
+    assert rel(sols[True], sols[False]) < 1e-7
+
+
 @pytest.mark.parametrize("law", ["inh", "fiber"])
 def test_newton_solve_pressurised_ring_mixed_matches_fp64(device, law):
     tube = dict(r_in=1.0, wall=0.2, length=1.0, bend=0.2)
