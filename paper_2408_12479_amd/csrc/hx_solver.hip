@@ -1486,6 +1486,7 @@ hx_status hx_newton_solve(hx_mg mg, double* u, const double* f_ext, const hx_new
     int it = 0;
     bool converged = rn <= std::max(opt->newton_abs_tol, opt->newton_rel_tol * r0);
     while (!converged && it < opt->max_newton) {
+      const auto t_lin = std::chrono::steady_clock::now();
       // linearisation of the outer FP64 operator and of every multigrid level
       if (mg->fp32) {
         if (outer < 0) {
@@ -1523,6 +1524,7 @@ hx_status hx_newton_solve(hx_mg mg, double* u, const double* f_ext, const hx_new
       k_fill<double><<<1, 64, 0, mg->stream>>>(sc + CG_TOL2, tol * tol, 1);
       // the graph holds the buffers of this linearisation: captured again at every Newton step
       if (mg->opt.use_graph && (status = capture_cg_iteration(mg, fine)) != HX_OK) break;
+      const double lin_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_lin).count();
       int k = 0;
       double stop = 0.0;
       while (stop == 0.0 && k < opt->max_krylov) {
@@ -1553,9 +1555,9 @@ hx_status hx_newton_solve(hx_mg mg, double* u, const double* f_ext, const hx_new
       if (!std::isfinite(rn)) { status = HX_E_NONFINITE; break; }
       converged = rn <= std::max(opt->newton_abs_tol, opt->newton_rel_tol * r0);
       if (opt->verbose) {
-        std::fprintf(stderr, "[hx_newton] load step %d/%d  Newton %d  CG %d  |r|/|r0| %.3e  %.2f s\n", step,
-                     opt->load_steps, it, k, rn / r0,
-                     std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+        std::fprintf(stderr, "[hx_newton] load step %d/%d  Newton %d  CG %d  |r|/|r0| %.3e  %.2f s (linearisation %.3f s)\n",
+                     step, opt->load_steps, it, k, rn / r0,
+                     std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(), lin_s);
         std::fflush(stderr);
       }
     }
