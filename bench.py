@@ -43,6 +43,9 @@ QPOINT_WORDS = {"tangent": 45, "finv_j": 10, "none": 0, "spatial": 16, "scalars"
                 "spatial_recompute": 0, "spatial_scalars": 1}
 # modes that interpolate the linearisation point u_k at every apply
 RECOMPUTE_MODES = ("none", "scalars", "spatial_recompute", "spatial_scalars")
+# stored words per q-point of each mode for the three laws (cNH, iNH, fibre)
+MODE_WORDS = {"tangent": (45, 45, 45), "finv_j": (10, 10, 10), "spatial": (16, 23, 37), "scalars": (1, 4, 8),
+              "spatial_scalars": (1, 4, 8), "tensors": (31, 33, 35), "none": (0, 0, 0), "spatial_recompute": (0, 0, 0)}
 
 
 def parse():
@@ -686,7 +689,9 @@ def mg_study(hx, workloads, torch, dev, timer, cells=(16, 8, 200), degrees=(6, 3
             x32 = torch.randn(n, device=dev, dtype=torch.float32)
             y32 = torch.empty_like(x32)
             t_fine = timer.time(lambda: ops[0].apply_tangent(x32, y32, precision="fp32"), reps)
-            fine_bytes = ops[0].linearization_bytes("fp32") + 2 * 4 * n
+            # the stored words the apply reads, then the direction read and the output write
+            words = MODE_WORDS[mg.level_mode(0)][2]
+            fine_bytes = 4 * words * ops[0].num_cells * (ops[0].p + 1) ** 3 + 2 * 4 * n
             out["finest_apply_fp32"] = {"mode": mg.level_mode(0), "ms": t_fine, "bytes": fine_bytes,
                                         "hbm_frac": fine_bytes / (t_fine * 1e-3) / 1e9 / HBM_PEAK_GBS}
         if key in ("graph", "graph_fp32_bf16", "graph_point"):

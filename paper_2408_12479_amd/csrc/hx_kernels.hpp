@@ -58,6 +58,61 @@ __device__ __forceinline__ float as_val(float v) { return v; }
 __device__ __forceinline__ float as_val(bf16_t v) { return __uint_as_float(static_cast<uint32_t>(v.v) << 16); }
 __device__ __forceinline__ float as_val(_Float16 v) { return static_cast<float>(v); }
 
+// Layout of the stored q-point words inside a block of EB cells (EBQ = EB (p+1)^3 slots): the
+// first W - W mod G words of a slot are packed in groups of G = 8 / sizeof(word) (FP64 one, FP32
+// two, 16-bit four), group-major, so word w sits at (w / G) G EBQ + qi G + w mod G; the remaining
+// W mod G words follow as planes of EBQ words. One 8-byte load per lane then brings G words, the
+// lanes of a wavefront read one contiguous run, no word is padded, and FP64 data keeps the plain
+// planes [word][EBQ]. Blocks follow each other at a stride of W EBQ words rounded up to a group,
+// so that every group stays 8-byte aligned.
+template <typename ST>
+constexpr int kPack = static_cast<int>(8 / sizeof(ST));
+template <typename ST>
+__host__ __device__ constexpr int64_t block_words(int W, int EBQ) {
+  return (static_cast<int64_t>(W) * EBQ + kPack<ST> - 1) / kPack<ST> * kPack<ST>;
+}
+template <typename ST, int W>
+__device__ __forceinline__ int qword(int w, int EBQ, int qi) {
+  constexpr int G = kPack<ST>;
+  constexpr int WF = W - W % G;
+  return w < WF ? (w / G) * (EBQ * G) + qi * G + w % G : w * EBQ + qi;
+}
+
+// one group of G words of one slot by a single 8-byte load (non-temporal with NT)
+template <bool NT>
+__device__ __forceinline__ void load_group(const double* p, double* out) {
+  out[0] = NT ? load_stream(p) : *p;
+}
+typedef unsigned int hx_u2 __attribute__((ext_vector_type(2)));
+template <bool NT>
+__device__ __forceinline__ hx_u2 load_u2(const void* p) {
+  const hx_u2* q = static_cast<const hx_u2*>(p);
+  if constexpr (NT) return __builtin_nontemporal_load(q);
+  else return *q;
+}
+template <bool NT>
+__device__ __forceinline__ void load_group(const float* p, float* out) {
+  const hx_u2 v = load_u2<NT>(p);
+  out[0] = __uint_as_float(v.x);
+  out[1] = __uint_as_float(v.y);
+}
+template <bool NT>
+__device__ __forceinline__ void load_group(const bf16_t* p, bf16_t* out) {
+  const hx_u2 v = load_u2<NT>(p);
+  out[0] = bf16_t{static_cast<uint16_t>(v.x & 0xffffu)};
+  out[1] = bf16_t{static_cast<uint16_t>(v.x >> 16)};
+  out[2] = bf16_t{static_cast<uint16_t>(v.y & 0xffffu)};
+  out[3] = bf16_t{static_cast<uint16_t>(v.y >> 16)};
+}
+template <bool NT>
+__device__ __forceinline__ void load_group(const _Float16* p, _Float16* out) {
+  const hx_u2 v = load_u2<NT>(p);
+  const uint16_t h[4] = {static_cast<uint16_t>(v.x & 0xffffu), static_cast<uint16_t>(v.x >> 16),
+                         static_cast<uint16_t>(v.y & 0xffffu), static_cast<uint16_t>(v.y >> 16)};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) __builtin_memcpy(&out[i], &h[i], sizeof(_Float16));
+}
+
 __device__ __forceinline__ void store_val(double* p, double v) { *p = v; }
 __device__ __forceinline__ void store_val(float* p, double v) { *p = static_cast<float>(v); }
 __device__ __forceinline__ void store_val(bf16_t* p, double v) {
@@ -1557,8 +1612,8 @@ __global__ void __launch_bounds__(EB * N * N * N, (kMinWaves<KIND, MODE, R>))
   const int e = e0 + le;
   const bool valid = e < a.L.n_cells;
   const CellPos c0 = cell_pos(a.L, e0);
-  // stored data: block-interleaved planes [block][word][EB * Q]; the plane base is uniform
-  // across the workgroup and the lane offset is the thread index
+  // stored data: blocks of W words per slot, packed in 8-byte groups (qword); the block base is
+  // uniform across the workgroup and the lane offset follows the thread index
   constexpr int W = MODE == HX_STORE_TANGENT          ? 45
                     : MODE == HX_STORE_FINV_J         ? 10
                     : MODE == HX_STORE_SPATIAL        ? kSpatialWords<LAW>
@@ -1567,7 +1622,7 @@ __global__ void __launch_bounds__(EB * N * N * N, (kMinWaves<KIND, MODE, R>))
                     : MODE == HX_STORE_TENSORS        ? kTensorWords<LAW>
                                                       : 0;
   constexpr int EBQ = EB * Q;
-  const int64_t qblk = static_cast<int64_t>(blk) * W * EBQ;
+  const int64_t qblk = static_cast<int64_t>(blk) * block_words<ST>(W, EBQ);
   const int qi = threadIdx.x;
 
   // stored q-point data of this thread (apply), requested before the sum factorisation so that
@@ -1578,12 +1633,15 @@ __global__ void __launch_bounds__(EB * N * N * N, (kMinWaves<KIND, MODE, R>))
   if constexpr (WA > 0) {
     if (valid) {
       const ST* qd = static_cast<const ST*>(a.qdata) + qblk;
-      if constexpr (NT) {
+      constexpr int G = kPack<ST>;
 #pragma unroll
-        for (int w = 0; w < WA; ++w) qv[w] = load_stream(qd + w * EBQ + qi);
-      } else {
+      for (int g = 0; g < WA / G; ++g) load_group<NT>(qd + qword<ST, W>(g * G, EBQ, qi), qv + g * G);
 #pragma unroll
-        for (int w = 0; w < WA; ++w) qv[w] = qd[w * EBQ + qi];
+      for (int w = WA / G * G; w < WA; ++w) {
+        if constexpr (NT)
+          qv[w] = load_stream(qd + qword<ST, W>(w, EBQ, qi));
+        else
+          qv[w] = qd[qword<ST, W>(w, EBQ, qi)];
       }
     }
   }
@@ -1719,9 +1777,9 @@ __global__ void __launch_bounds__(EB * N * N * N, (kMinWaves<KIND, MODE, R>))
 #pragma unroll
     for (int w = 0; w < W; ++w) {
       if constexpr (NT)
-        d[w] = valid ? static_cast<R>(as_val(load_stream(qd + w * EBQ + qi))) : R(0);
+        d[w] = valid ? static_cast<R>(as_val(load_stream(qd + qword<ST, W>(w, EBQ, qi)))) : R(0);
       else
-        d[w] = valid ? static_cast<R>(as_val(qd[w * EBQ + qi])) : R(0);
+        d[w] = valid ? static_cast<R>(as_val(qd[qword<ST, W>(w, EBQ, qi)])) : R(0);
     }
     R G[9], Pd[9];
     to_physical(g0, K, G);
@@ -1802,8 +1860,8 @@ __global__ void __launch_bounds__(EB * N * N * N, (kMinWaves<KIND, MODE, R>))
       if (valid && !isfinite(chk)) bad |= kFlagNonFinite;
       if (valid) {
 #pragma unroll
-        for (int w = 0; w < 9; ++w) store_val(qw + w * EBQ + qi, st.Fi[w]);
-        store_val(qw + 9 * EBQ + qi, st.Jm);
+        for (int w = 0; w < 9; ++w) store_val(qw + qword<ST, W>(w, EBQ, qi), st.Fi[w]);
+        store_val(qw + qword<ST, W>(9, EBQ, qi), st.Jm);
       }
     } else if constexpr (MODE == HX_STORE_TANGENT) {
       // columns of the reference tangent: unit reference gradient e_k (x) e_b maps to the
@@ -1850,7 +1908,7 @@ __global__ void __launch_bounds__(EB * N * N * N, (kMinWaves<KIND, MODE, R>))
       }
       if (valid) {
 #pragma unroll
-        for (int i = 0; i < 45; ++i) store_val(qw + i * EBQ + qi, Dsym[i] * scale);
+        for (int i = 0; i < 45; ++i) store_val(qw + qword<ST, W>(i, EBQ, qi), Dsym[i] * scale);
       }
     } else if constexpr (MODE == HX_STORE_SCALARS || MODE == HX_STORE_TENSORS) {
       R dw[W];
@@ -1864,7 +1922,7 @@ __global__ void __launch_bounds__(EB * N * N * N, (kMinWaves<KIND, MODE, R>))
       if (valid && !isfinite(chk)) bad |= kFlagNonFinite;
       if (valid) {
 #pragma unroll
-        for (int w = 0; w < W; ++w) store_val(qw + w * EBQ + qi, dw[w]);
+        for (int w = 0; w < W; ++w) store_val(qw + qword<ST, W>(w, EBQ, qi), dw[w]);
       }
     } else if constexpr (MODE == HX_STORE_SPATIAL) {
       R J0[9], dw[W];
@@ -1876,7 +1934,7 @@ __global__ void __launch_bounds__(EB * N * N * N, (kMinWaves<KIND, MODE, R>))
       if (valid && !isfinite(chk)) bad |= kFlagNonFinite;
       if (valid) {
 #pragma unroll
-        for (int w = 0; w < W; ++w) store_val(qw + w * EBQ + qi, dw[w]);
+        for (int w = 0; w < W; ++w) store_val(qw + qword<ST, W>(w, EBQ, qi), dw[w]);
       }
     } else {
       R chk = st.Jm;
@@ -1992,14 +2050,15 @@ __global__ void __launch_bounds__(EB * N * N * N) diag_kernel(KernelArgs<N, R> a
   const int e = e0 + le;
   const bool valid = e < a.L.n_cells;
   const CellPos c0 = cell_pos(a.L, e0);
-  const ST* qd = static_cast<const ST*>(a.qdata) + static_cast<int64_t>(blockIdx.x) * 45 * EBQ;
+  const ST* qd = static_cast<const ST*>(a.qdata) + static_cast<int64_t>(blockIdx.x) * block_words<ST>(45, EBQ);
   R Dv[45];
   R inv = R(1);
   if constexpr (S == kStoreF16) {
     if (valid) inv = R(1) / static_cast<R>(a.cscale[e]);
   }
 #pragma unroll
-  for (int w = 0; w < 45; ++w) Dv[w] = valid ? static_cast<R>(load_val(qd + w * EBQ + threadIdx.x)) * inv : R(0);
+  for (int w = 0; w < 45; ++w)
+    Dv[w] = valid ? static_cast<R>(load_val(qd + qword<ST, 45>(w, EBQ, threadIdx.x))) * inv : R(0);
   R* cb = sb + le * 6 * Lds<N>::FS;
 #pragma unroll
   for (int c = 0; c < 3; ++c) cb[(3 + c) * Lds<N>::FS + lds_q<N>(q)] = R(0);
