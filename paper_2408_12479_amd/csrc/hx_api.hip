@@ -828,8 +828,9 @@ hx_status hx::update_linearization(hx_ctx_s* ctx, const double* u, hx_storage mo
   // whole workgroup blocks of cells (the last one may be partly unused)
   const int64_t eb = cells_per_block(ctx->p, variant);
   const int64_t padded_cells = (L.n_cells + eb - 1) / eb * eb;
-  // blocks of eb cells, each rounded up to whole 8-byte groups (the kernels' block stride)
-  const int64_t group = static_cast<int64_t>(8 / store_bytes(st));
+  // blocks of eb cells, each rounded up to whole groups of stored words (the kernels' block
+  // stride: one FP64 word, four FP32 or 16-bit words)
+  const int64_t group = st == kStoreF64 ? 1 : 4;
   const int64_t block = (mode_words(mode, ctx->base.mat.law) * eb * Q + group - 1) / group * group;
   const size_t need = static_cast<size_t>(block) * (padded_cells / eb) * store_bytes(st);
   hipError_t e = hipStreamSynchronize(s);  // the slot's buffers may still be in use

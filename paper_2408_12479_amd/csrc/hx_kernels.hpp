@@ -59,14 +59,21 @@ __device__ __forceinline__ float as_val(bf16_t v) { return __uint_as_float(stati
 __device__ __forceinline__ float as_val(_Float16 v) { return static_cast<float>(v); }
 
 // Layout of the stored q-point words inside a block of EB cells (EBQ = EB (p+1)^3 slots): the
-// first W - W mod G words of a slot are packed in groups of G = 8 / sizeof(word) (FP64 one, FP32
-// two, 16-bit four), group-major, so word w sits at (w / G) G EBQ + qi G + w mod G; the remaining
-// W mod G words follow as planes of EBQ words. One 8-byte load per lane then brings G words, the
-// lanes of a wavefront read one contiguous run, no word is padded, and FP64 data keeps the plain
-// planes [word][EBQ]. Blocks follow each other at a stride of W EBQ words rounded up to a group,
-// so that every group stays 8-byte aligned.
+// first W - W mod G words of a slot are packed in groups of G words, group-major, so word w sits
+// at (w / G) G EBQ + qi G + w mod G; the remaining W mod G words follow as planes of EBQ words.
+// One load per lane then brings a whole group and the lanes of a wavefront read one contiguous
+// run, with no word padded. G per word type, as measured (same-GPU A/B of the applies): FP64 one
+// word (8-byte loads; 16-byte pairs were 2-8 % slower), FP32 four (16-byte loads: +5 % over pairs,
+// which gained up to 5 % over single words), 16-bit four (8-byte loads; 16-byte groups within
+// -2 to +3 %). Blocks follow each other at a stride of W EBQ words rounded up to a group, so that
+// every group stays aligned to its size.
+template <typename ST> struct Pack;
+template <> struct Pack<double> { static constexpr int G = 1; };
+template <> struct Pack<float> { static constexpr int G = 4; };
+template <> struct Pack<bf16_t> { static constexpr int G = 4; };
+template <> struct Pack<_Float16> { static constexpr int G = 4; };
 template <typename ST>
-constexpr int kPack = static_cast<int>(8 / sizeof(ST));
+constexpr int kPack = Pack<ST>::G;
 template <typename ST>
 __host__ __device__ constexpr int64_t block_words(int W, int EBQ) {
   return (static_cast<int64_t>(W) * EBQ + kPack<ST> - 1) / kPack<ST> * kPack<ST>;
@@ -78,27 +85,30 @@ __device__ __forceinline__ int qword(int w, int EBQ, int qi) {
   return w < WF ? (w / G) * (EBQ * G) + qi * G + w % G : w * EBQ + qi;
 }
 
-// one group of G words of one slot by a single 8-byte load (non-temporal with NT)
-template <bool NT>
-__device__ __forceinline__ void load_group(const double* p, double* out) {
-  out[0] = NT ? load_stream(p) : *p;
-}
+// one group of one slot by a single load (non-temporal with NT)
 typedef unsigned int hx_u2 __attribute__((ext_vector_type(2)));
-template <bool NT>
-__device__ __forceinline__ hx_u2 load_u2(const void* p) {
-  const hx_u2* q = static_cast<const hx_u2*>(p);
+typedef unsigned int hx_u4 __attribute__((ext_vector_type(4)));
+template <typename V, bool NT>
+__device__ __forceinline__ V load_vec(const void* p) {
+  const V* q = static_cast<const V*>(p);
   if constexpr (NT) return __builtin_nontemporal_load(q);
   else return *q;
 }
 template <bool NT>
+__device__ __forceinline__ void load_group(const double* p, double* out) {
+  out[0] = NT ? load_stream(p) : *p;
+}
+template <bool NT>
 __device__ __forceinline__ void load_group(const float* p, float* out) {
-  const hx_u2 v = load_u2<NT>(p);
+  const hx_u4 v = load_vec<hx_u4, NT>(p);
   out[0] = __uint_as_float(v.x);
   out[1] = __uint_as_float(v.y);
+  out[2] = __uint_as_float(v.z);
+  out[3] = __uint_as_float(v.w);
 }
 template <bool NT>
 __device__ __forceinline__ void load_group(const bf16_t* p, bf16_t* out) {
-  const hx_u2 v = load_u2<NT>(p);
+  const hx_u2 v = load_vec<hx_u2, NT>(p);
   out[0] = bf16_t{static_cast<uint16_t>(v.x & 0xffffu)};
   out[1] = bf16_t{static_cast<uint16_t>(v.x >> 16)};
   out[2] = bf16_t{static_cast<uint16_t>(v.y & 0xffffu)};
@@ -106,7 +116,7 @@ __device__ __forceinline__ void load_group(const bf16_t* p, bf16_t* out) {
 }
 template <bool NT>
 __device__ __forceinline__ void load_group(const _Float16* p, _Float16* out) {
-  const hx_u2 v = load_u2<NT>(p);
+  const hx_u2 v = load_vec<hx_u2, NT>(p);
   const uint16_t h[4] = {static_cast<uint16_t>(v.x & 0xffffu), static_cast<uint16_t>(v.x >> 16),
                          static_cast<uint16_t>(v.y & 0xffffu), static_cast<uint16_t>(v.y >> 16)};
 #pragma unroll
