@@ -520,6 +520,14 @@ def main():
                     sweep[key][mode]["rel_err_vs_oracle_sampled"] = err
     out["sweep"] = sweep
     extra["hbm_triad"] = triad
+    # the paper's own node-level numbers for this path, with their hardware: context, not a target
+    # (another machine, another workload: a deformed cube of 2.5-5 MDoF, 100 applies per update)
+    extra["paper_context"] = {
+        "hardware": "2x Intel Xeon Platinum 8360Y (2x36 cores, 2.0 GHz, AVX-512, DDR4-3200), 72 MPI ranks",
+        "peak_tangent_apply_gdofs": {"cnh_and_inh": 1.75, "fibre": 1.25},
+        "memory_bandwidth_p4_gbs": {"store tensors": "260-280", "store scalars": "220", "recompute": "140-160"},
+        "source": "Section 7.2 (node-level performance of the matrix-free operator)",
+    }
     extra["fp64_pipes"] = pipes
     out["extra"] = extra
     print(json.dumps(out), flush=True)
