@@ -341,8 +341,8 @@ def measured_traffic(p, mode):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(multi-GPU sharding is a design note only)", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              "(how the apply would shard across GPUs is described, not built)", file=sys.stderr)
         sys.exit(2)
     pool, workers = None, 0
     if not args.no_cpu_baseline:
